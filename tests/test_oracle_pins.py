@@ -1,0 +1,343 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+(the tanh rule), identities proved in the paper's appendix, brute-force
+enumeration on tiny codes, an independent textbook layered BP written here in
+pure Python, invariants and counts stated in the paper.
+"""
+import json
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_05286_amd.workload import get_code, make_frames, noiseless_llrs, encode
+
+from helpers import (brute_force_map_llr, brute_force_max_marginal, code_from_dense,
+                     hamming_H, ml_codeword, random_tree_H, syndrome)
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+LMAX = oracle.LMAX
+A = oracle.phi(LMAX)
+
+
+def rel(a, b):
+    return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+# ---------------------------------------------------------------- P1: phi, psi
+
+def test_phi_self_reciprocal():
+    # App. A: phi is its own inverse on (0, inf)
+    xs = np.geomspace(A, LMAX, 200)
+    back = np.array([oracle.phi(oracle.phi(x)) for x in xs])
+    assert np.max(np.abs(back - xs) / xs) < 1e-11
+
+
+def test_phi_matches_tanh_definition():
+    # eq. (equ_s2e5): phi(x) = -log tanh(x/2) = 2 atanh(exp(-x))
+    xs = np.geomspace(1e-6, 30.0, 300)
+    got = np.array([oracle.phi(x) for x in xs])
+    ref = -np.log(np.tanh(xs / 2.0))
+    ref2 = 2.0 * np.arctanh(np.exp(-xs))
+    # log((1 + t) / (1 - t)), t = e^-x: 1 - t from expm1 for small x, log1p(-t) for large x
+    t = np.exp(-xs)
+    ref3 = np.log1p(t) - np.where(xs < 1.0, np.log(-np.expm1(-xs)), np.log1p(-t))
+    assert np.max(np.abs(got - ref3) / ref3) < 1e-13
+    assert np.max(np.abs(got - ref2) / ref2) < 1e-10
+    mid = xs < 15
+    assert np.max(np.abs(got[mid] - ref[mid]) / ref[mid]) < 1e-9
+    assert oracle.phi(0.0) == np.inf and oracle.phi(np.inf) == 0.0
+
+
+def test_psi_plus_is_tanh_rule():
+    # eq. (equ_s4e6) folds two inputs of the check rule:
+    # psi+(x, y) = 2 atanh(tanh(x/2) tanh(y/2)) for finite x and a <= |y| <= LMAX
+    rng = np.random.default_rng(0)
+    for _ in range(500):
+        x = rng.normal() * 4
+        y = rng.choice([-1, 1]) * rng.uniform(0.01, 15.0)
+        ref = 2.0 * np.arctanh(np.tanh(x / 2) * np.tanh(y / 2))
+        assert abs(oracle.psi_plus(x, y) - ref) <= 1e-10 * max(1.0, abs(ref))
+
+
+def test_psi_plus_seed_infinity():
+    # Omega^(-1) = inf seeds the recursion (equ_s4e8): psi+(inf, y) = y
+    for y in [-13.0, -0.3, 0.01, 2.5, 19.0]:
+        assert abs(oracle.psi_plus(np.inf, y) - y) < 1e-12 * max(1, abs(y))
+    # magnitudes beyond LMAX are clamped (reading R3)
+    assert abs(oracle.psi_plus(np.inf, 35.0) - LMAX) < 1e-12
+
+
+def test_psi_minus_inverts_psi_plus():
+    # App. A (equ_ae7): excluding y from a belief that folded y returns the rest
+    rng = np.random.default_rng(1)
+    for _ in range(500):
+        x = rng.choice([-1, 1]) * rng.uniform(0.05, 12.0)
+        y = rng.choice([-1, 1]) * rng.uniform(0.05, 12.0)
+        w = oracle.psi_plus(x, y)
+        assert abs(oracle.psi_minus(w, y) - x) <= 1e-8 * max(1.0, abs(x))
+
+
+def test_psi_minus_tanh_rule():
+    # tanh(Omega/2) = tanh(x/2) tanh(y/2)  =>  x = 2 atanh(tanh(Omega/2) / tanh(y/2))
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        y = rng.choice([-1, 1]) * rng.uniform(0.1, 8.0)
+        ty = np.tanh(y / 2)
+        om = 2 * np.arctanh(ty * rng.uniform(-0.95, 0.95))
+        ref = 2 * np.arctanh(np.tanh(om / 2) / ty)
+        assert abs(oracle.psi_minus(om, y) - ref) <= 1e-8 * max(1.0, abs(ref))
+
+
+# ----------------------------------------------------- P2: fold == direct form
+
+def test_c2b_fold_equals_direct_check_belief():
+    # eq. (equ_s4e3): Omega_c = prod sgn(Q) * phi(sum phi|Q|) = 2 atanh(prod tanh(Q/2)).
+    # In sweep 1 every variable of row 0 is visited for the first time, so the
+    # V2C messages folded into Omega_0 are the channel LLRs.
+    rng = np.random.default_rng(3)
+    for d in [2, 3, 6, 9]:
+        H = np.zeros((2, d + 1), np.uint8)
+        H[0, :d] = 1
+        H[1, d - 1:] = 1
+        code = code_from_dense(H)
+        llr = (rng.normal(size=(20, d + 1)) * 3).astype(np.float32)
+        out = oracle.decode(code, llr, 1, "cbp", stop_rule=2, dump_sweep=1, ndump=20)
+        L = llr[:, :d].astype(np.float64)
+        ref = 2 * np.arctanh(np.prod(np.tanh(L / 2), axis=1))
+        assert np.max(rel(out["Om"][:, 0], ref)) < 1e-9
+
+
+# ------------------------------------------- P3: CBP == textbook layered BP
+
+def _lbp_pure_python(H, L, sweeps):
+    """Independent textbook layered BP (tanh form of the check rule)."""
+    M, N = H.shape
+    lam = L.astype(np.float64).copy()
+    R = np.zeros((M, N))
+    for _ in range(sweeps):
+        for i in range(M):
+            vs = np.nonzero(H[i])[0]
+            q = lam[vs] - R[i, vs]
+            aq = np.clip(np.abs(q), A, LMAX) * np.where(q >= 0, 1.0, -1.0)
+            t = np.tanh(aq / 2)
+            for k, v in enumerate(vs):
+                prod = np.prod(np.delete(t, k))
+                rn = 2 * np.arctanh(prod)
+                lam[v] = q[k] + rn
+                R[i, v] = rn
+    return lam
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_oracle_lbp_matches_pure_python_textbook(seed):
+    H = hamming_H(3)
+    H = np.vstack([H, (H[0] ^ H[1])])  # a redundant row adds cycles
+    code = code_from_dense(H)
+    rng = np.random.default_rng(seed)
+    llr = (rng.normal(size=(6, code.N)) * 1.5 + 1.0).astype(np.float32)
+    for k in [1, 2, 4]:
+        out = oracle.decode(code, llr, k, "lbp", stop_rule=2, dump_sweep=k, ndump=6)
+        for f in range(6):
+            ref = _lbp_pure_python(H, llr[f], k)
+            assert np.max(rel(out["Lam"][f], ref)) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc_t16", "qc_t64s"])
+def test_cbp_flushed_posterior_equals_lbp(name):
+    # Sec. IV-B derives CBP from layered BP (equ_s4e9, equ_s4e10, equ_s4e14,
+    # equ_s4e20): after every sweep the CBP state, with the deferred C2V of
+    # each variable's last check flushed, is the layered-BP posterior.
+    code = get_code(name)
+    llr, _ = make_frames(code, 1.5, 64, key=(11,))
+    for k in [1, 2, 3, 5]:
+        c = oracle.decode(code, llr, k, "cbp", stop_rule=2, dump_sweep=k, ndump=64)
+        l = oracle.decode(code, llr, k, "lbp", stop_rule=2, dump_sweep=k, ndump=64)
+        assert np.max(rel(c["Lam"], l["Lam"])) < 1e-9, (name, k)
+
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc_t64s"])
+def test_cbp_iterations_equal_lbp_with_flushed_decision(name):
+    code = get_code(name)
+    llr, _ = make_frames(code, 2.0, 400, key=(12,))
+    c = oracle.decode(code, llr, 30, "cbp", hd_mode=1)
+    l = oracle.decode(code, llr, 30, "lbp")
+    assert np.array_equal(c["iters"], l["iters"])
+    assert np.array_equal(c["bits"], l["bits"])
+
+
+def test_cbp_nms_flushed_equals_lbp_nms():
+    # the min-sum form of Sec. IV-D (reading: unscaled min/submin, value
+    # equality selects submin) is layered normalized min-sum with deferred C2V
+    code = get_code("reg36_n96")
+    llr, _ = make_frames(code, 1.5, 64, key=(13,))
+    for k in [1, 3]:
+        c = oracle.decode(code, llr, k, "cbp_nms", stop_rule=2, dump_sweep=k, ndump=64)
+        l = oracle.decode(code, llr, k, "lbp_nms", stop_rule=2, dump_sweep=k, ndump=64)
+        assert np.max(rel(c["Lam"], l["Lam"])) < 1e-9
+
+
+# -------------------------------------------------------- P4: state invariant
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc_t64s"])
+def test_latest_v2c_invariant(name):
+    # Q_v = L_v + sum of R(c, v) over every neighbour c except the latest updated one
+    code = get_code(name)
+    llr, _ = make_frames(code, 1.0, 16, key=(14,))
+    k = 3
+    out = oracle.decode(code, llr, k, "cbp", stop_rule=2, dump_sweep=k, ndump=16)
+    rows = np.repeat(np.arange(code.M), np.diff(code.row_ptr))
+    for f in range(16):
+        acc = llr[f].astype(np.float64).copy()
+        last_row = np.full(code.N, -1)
+        for e in range(code.E):
+            last_row[code.col_idx[e]] = max(last_row[code.col_idx[e]], rows[e])
+        for e in range(code.E):
+            v = code.col_idx[e]
+            if rows[e] != last_row[v]:
+                acc[v] += out["R"][f, e]
+        assert np.max(rel(out["Q"][f], acc)) < 1e-10
+
+
+# ------------------------------------------------------ P5: Table I op counts
+
+def test_update_counts_match_table1():
+    spec = json.loads((GOLDEN / "table1_cbp_updates.json").read_text())["CBP"]
+    assert spec["B2V"] == spec["V2C"] == spec["C2B"] == "E" and spec["C2V"] == 0
+    for name in ["reg36_n96", "qc_t64s"]:
+        code = get_code(name)
+        llr, _ = make_frames(code, 0.0, 1, key=(15,))
+        out = oracle.decode(code, llr, 4, "cbp", stop_rule=2, opcounts=True)
+        ops = out["ops"]
+        E, N = code.E, code.N
+        # sweep 1: a variable's first visit has no latest check, so no B2V
+        assert list(ops[0]) == [E - N, E, E]
+        for t in range(1, 4):
+            assert list(ops[t]) == [E, E, E]
+
+
+def test_state_sizes_match_table4():
+    spec = json.loads((GOLDEN / "table4_memory.json").read_text())["CBP"]
+    assert (spec["LLR"], spec["C2V"], spec["Check-belief"]) == ("N", "E", "M")
+    code = get_code("qc_t16")
+    llr, _ = make_frames(code, 1.0, 2, key=(16,))
+    out = oracle.decode(code, llr, 1, "cbp", stop_rule=2, dump_sweep=1, ndump=2)
+    assert out["Q"].shape[1] == code.N and out["R"].shape[1] == code.E and out["Om"].shape[1] == code.M
+
+
+# ------------------------------------------------- P6: trees, exact marginals
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tree_bp_is_exact(seed):
+    H = random_tree_H(12, seed)
+    code = code_from_dense(H)
+    rng = np.random.default_rng(100 + seed)
+    llr = (rng.normal(size=(8, code.N)) * 1.2 + 0.5).astype(np.float32)
+    sweeps = 2 * code.N
+    for algo in ["fbp", "lbp", "cbp"]:
+        out = oracle.decode(code, llr, sweeps, algo, stop_rule=2, dump_sweep=sweeps, ndump=8)
+        for f in range(8):
+            ref = brute_force_map_llr(H, llr[f].astype(np.float64))
+            assert np.max(rel(out["Lam"][f], ref)) < 1e-9, algo
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tree_minsum_is_max_marginal(seed):
+    # with alpha = 1 the min-sum rule on a tree computes max-marginals exactly
+    H = random_tree_H(11, 50 + seed)
+    code = code_from_dense(H)
+    rng = np.random.default_rng(200 + seed)
+    llr = (rng.normal(size=(8, code.N)) * 1.2 + 0.5).astype(np.float32)
+    sweeps = 2 * code.N
+    for algo in ["fbp_nms", "lbp_nms", "cbp_nms"]:
+        out = oracle.decode(code, llr, sweeps, algo, alpha=1.0, stop_rule=2,
+                            dump_sweep=sweeps, ndump=8)
+        for f in range(8):
+            ref = brute_force_max_marginal(H, llr[f].astype(np.float64))
+            assert np.max(rel(out["Lam"][f], ref)) < 1e-9, algo
+
+
+def test_single_check_nms_closed_form():
+    # one parity check: C2V = alpha * prod(other signs) * min(other |L|)
+    H = np.ones((1, 5), np.uint8)
+    code = code_from_dense(H)
+    llr = np.array([[1.5, -0.25, 3.0, -2.0, 0.75]], np.float32)
+    out = oracle.decode(code, llr, 1, "lbp_nms", alpha=0.75, stop_rule=2, dump_sweep=1, ndump=1)
+    L = llr[0].astype(np.float64)
+    for v in range(5):
+        o = np.delete(L, v)
+        ref = 0.75 * np.prod(np.sign(o)) * np.min(np.abs(o))
+        assert abs(out["R"][0, v] - ref) < 1e-15
+
+
+# --------------------------------------------------- P7: ML on Hamming codes
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_ml_bound_hamming(m):
+    H = hamming_H(m)
+    code = code_from_dense(H)
+    rng = np.random.default_rng(m)
+    from helpers import all_codewords
+    C = all_codewords(H)
+    B = 300
+    cw = C[rng.integers(0, len(C), B)]
+    s2 = 0.5
+    llr = ((2.0 / s2) * ((1 - 2.0 * cw) + np.sqrt(s2) * rng.normal(size=cw.shape))).astype(np.float32)
+    ml_err = 0
+    for f in range(B):
+        ml_err += not np.array_equal(ml_codeword(H, llr[f].astype(np.float64)), cw[f])
+    for algo in ["cbp", "lbp", "fbp"]:
+        out = oracle.decode(code, llr, 30, algo)
+        err = (out["bits"] != cw).any(axis=1).sum()
+        # no decoder beats ML by more than chance (same frames: ML is optimal)
+        assert err >= ml_err - 3, (algo, err, ml_err)
+        ok = (syndrome(code, out["bits"]) == 0).all(axis=1)
+        for f in np.nonzero(ok)[0]:
+            c_ml = ml_codeword(H, llr[f].astype(np.float64))
+            corr = lambda c: float(((1 - 2.0 * c) * llr[f]).sum())
+            assert corr(c_ml) >= corr(out["bits"][f]) - 1e-9
+
+
+# ------------------------------------- P8, P9, P10: success, noiseless, symmetry
+
+@pytest.mark.parametrize("algo", list(oracle.ALGOS))
+def test_stopped_frames_have_zero_syndrome(algo):
+    code = get_code("reg36_n96")
+    llr, _ = make_frames(code, 1.5, 300, key=(17,))
+    out = oracle.decode(code, llr, 20, algo)
+    stopped = out["iters"] < 20
+    assert stopped.sum() > 100
+    assert (syndrome(code, out["bits"][stopped]) == 0).all()
+
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc_t16"])
+def test_noiseless_input_stops_immediately(name):
+    code = get_code(name)
+    llr, cw = noiseless_llrs(code, 20, 4.0)
+    for algo in oracle.ALGOS:
+        out = oracle.decode(code, llr, 10, algo)
+        assert (out["iters"] == 0).all() and np.array_equal(out["bits"], cw)
+
+
+@pytest.mark.parametrize("algo", list(oracle.ALGOS))
+def test_codeword_symmetry(algo):
+    # BP on a binary-input symmetric channel: flipping the LLR signs on the
+    # support of a codeword c flips the decisions by c; iterations unchanged.
+    code = get_code("qc_t16")
+    llr, _ = make_frames(code, 1.0, 100, key=(18,))
+    rng = np.random.default_rng(7)
+    c = encode(code, rng.integers(0, 2, size=(100, code.K), dtype=np.uint8))
+    a = oracle.decode(code, llr, 15, algo)
+    b = oracle.decode(code, llr * (1 - 2 * c.astype(np.float32)), 15, algo)
+    assert np.array_equal(a["iters"], b["iters"])
+    assert np.array_equal(a["bits"] ^ c, b["bits"])
+
+
+def test_paper_stop_rule_agrees_at_high_snr():
+    code = get_code("reg36_n96")
+    llr, cw = make_frames(code, 4.0, 200, key=(19,))
+    a = oracle.decode(code, llr, 30, "cbp", stop_rule=1)
+    assert ((a["bits"] != cw).any(axis=1)).mean() < 0.02
+    assert (a["iters"] >= 1).all()
