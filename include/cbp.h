@@ -1,0 +1,167 @@
+/*
+ * cbp.h -- C ABI of the MI355X check-belief propagation (CBP) LDPC decoder.
+ *
+ * Method: W. Guan, L. Liang, "Check-Belief Propagation Decoding of LDPC
+ * Codes", IEEE Trans. Commun. (arXiv 2305.05286).
+ *
+ * All entry points use C linkage, plain pointers and sizes, and return an int
+ * status (CBP_OK or a negative CBP_E* code); none aborts or prints.  A
+ * human-readable message for the last failure of the calling thread is
+ * returned by cbp_last_error().
+ *
+ * Device buffers are owned by the caller; the decoders read and write them
+ * asynchronously on the caller's HIP stream (passed as void*, NULL = the
+ * default stream) and results are valid once that stream has synchronised.
+ * A code handle owns copies of the parity-check tables (host and, created on
+ * first use, per device); it is immutable and may be shared by any number of
+ * threads and streams.
+ */
+#ifndef CBP_H
+#define CBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CBP_OK 0
+#define CBP_EINVAL (-1)       /* null pointer, bad shape/size/option, malformed H */
+#define CBP_EUNSUPPORTED (-2) /* valid request this build does not implement      */
+#define CBP_EHIP (-3)         /* HIP runtime or launch error                      */
+#define CBP_ENOMEM (-4)       /* device or host allocation failed                 */
+
+/* ---- code handles ------------------------------------------------------ */
+typedef struct cbp_code cbp_code_t;
+
+/*
+ * Parity-check matrix H (M x N) in CSR form: row i is check-node c_i, column v
+ * is variable-node v (paper Sec. II).  row_ptr has M+1 entries (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[M] = E); col_idx has E entries, strictly ascending
+ * within each row (ascending order is the order in which the C2B recursion
+ * folds a row's V2C messages).  Every row needs degree >= 2 and every column
+ * degree >= 1, else CBP_EINVAL.  Host pointers; copied.
+ */
+int cbp_code_from_csr(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_idx,
+                      cbp_code_t **out);
+
+/*
+ * Quasi-cyclic H from a base matrix of mb x nb circulant shifts (row-major,
+ * host pointer, copied): -1 is a Z x Z zero block, s in [0, Z) is the identity
+ * cyclically shifted so that row k of the block connects to column (k+s) mod Z
+ * of the block-column.  Row r*Z+k of H is row k of block-row r; the lifted H
+ * is also available to every decoder as CSR.  Block-rows are the layers of the
+ * sweep: the Z rows of a block-row share no variable, so they are updated in
+ * parallel with a result identical to the paper's row-by-row order.
+ */
+int cbp_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, cbp_code_t **out);
+
+void cbp_code_free(cbp_code_t *code);
+
+/* Shape of a handle.  Any output pointer may be NULL.  *kernels is a bit set of
+ * the decoder layouts available for this code (CBP_KERNEL_* below). */
+int cbp_code_info(const cbp_code_t *code, int32_t *M, int32_t *N, int64_t *E, int32_t *Z,
+                  int32_t *kernels);
+
+/* ---- options ----------------------------------------------------------- */
+#define CBP_KERNEL_AUTO 0
+#define CBP_KERNEL_QC_REG 1    /* QC: frame state in VGPRs + LDS (compiled base patterns) */
+#define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
+#define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, frame-interleaved state     */
+
+typedef struct {
+    /* 0: stop when the syndrome H x^T = 0, tested on [L < 0] before the first
+     *    sweep and after every sweep (default).  2: run exactly max_iter sweeps.
+     *    (1, the paper's consecutive-positive-check-belief rule, is not
+     *    implemented on the GPU: CBP_EUNSUPPORTED.) */
+    int32_t stop_rule;
+    /* CBP hard decision.  0: x_v = [Lambda_v < 0] from the V2C phase of v's
+     * last visit in the sweep (paper Step 3; default).  1: from the flushed
+     * posterior Q_v + psi-(Omega_latest(v), Q_v) at the end of each sweep. */
+    int32_t hd_mode;
+    /* Saturation of V2C magnitudes entering the check rule (default 20). */
+    float lmax;
+    /* Normalisation factor of the min-sum baselines (default 0.75). */
+    float alpha;
+    /* CBP_KERNEL_AUTO or one CBP_KERNEL_* value (CBP_EUNSUPPORTED if that
+     * layout is unavailable for the code). */
+    int32_t kernel;
+    /* Debug dump of the decoder state after sweep dump_sweep (0 = off) for
+     * frames [0, dump_frames): float32 device buffers, frame-major, each may
+     * be NULL.  CBP: dump_q = latest V2C Q [N], dump_r = C2V R [E, CSR edge
+     * order], dump_om = check-belief Omega in the LLR domain [M], dump_lam =
+     * flushed posterior [N].  Min-sum baselines: dump_lam = posterior, dump_r
+     * = R.  Rows of frames that stopped before dump_sweep are not written. */
+    int32_t dump_sweep;
+    int64_t dump_frames;
+    float *dump_q;
+    float *dump_r;
+    float *dump_om;
+    float *dump_lam;
+    /* Optional caller-provided device workspace (see cbp_workspace_size); if
+     * NULL or too small the call allocates one stream-ordered. */
+    void *workspace;
+    size_t workspace_bytes;
+} cbp_opts_t;
+
+/* Fill *opts with the defaults listed above. */
+void cbp_opts_default(cbp_opts_t *opts);
+
+/* ---- decoders ---------------------------------------------------------- */
+/*
+ * Decode `batch` frames.
+ *   llr_in    device float32 [batch][N]: channel LLRs ln Pr(y|x=0)/Pr(y|x=1)
+ *             (Sec. IV-C Step 1), L > 0 favours bit 0.
+ *   bits_out  device uint8   [batch][N]: hard decisions, 0/1 (Lambda = 0 -> 0).
+ *   iters_out device int32   [batch]: sweeps executed, 0..max_iter (0 when
+ *             [L < 0] already has a zero syndrome).  A frame with
+ *             iters_out == max_iter may have failed: test with cbp_syndrome.
+ *   max_iter  >= 0; 0 outputs [L < 0].  batch == 0 is a no-op.
+ *   opts      NULL for defaults.
+ *   stream    hipStream_t as void* (NULL = default stream).
+ *
+ * cbp_decode: CBP, Sec. IV-C Steps 1-3 (B2V eq. equ_s4e18, V2C eq. equ_s4e19,
+ *   posterior eq. equ_s4e20, C2B eq. equ_s4e21, commits eqs. equ_s4e22/23);
+ *   rows in index order, a row's V2C messages folded in ascending column order;
+ *   a check not yet updated in this decode contributes a zero B2V message; the
+ *   commit of Step 2(1)e stores R(c_j -> v) before R(c_i -> v) is read.
+ * lbp_nms_decode: layered BP (Sec. II-B, eqs. equ_s2e10/equ_s2e12) with the
+ *   normalized min-sum check rule alpha * prod sgn * min |Q| (|Q| <= lmax).
+ * fbp_nms_decode: flooding BP (Sec. II-A, eqs. equ_s2e3/equ_s2e6/equ_s2e7)
+ *   with the same normalized min-sum check rule.
+ */
+int cbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
+               int32_t *iters_out, int32_t max_iter, int64_t batch,
+               const cbp_opts_t *opts, void *stream);
+int lbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
+                   int32_t *iters_out, int32_t max_iter, int64_t batch,
+                   const cbp_opts_t *opts, void *stream);
+int fbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
+                   int32_t *iters_out, int32_t max_iter, int64_t batch,
+                   const cbp_opts_t *opts, void *stream);
+
+/* Device workspace (bytes) the given decoder needs for `batch` frames with
+ * these options; decoder: 0 = cbp_decode, 1 = lbp_nms_decode, 2 = fbp_nms_decode. */
+int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch,
+                       const cbp_opts_t *opts, size_t *bytes);
+
+/*
+ * Syndrome test (the stopping test of FBP, Sec. II-A): ok_out[f] = 1 if
+ * H bits[f]^T = 0 over GF(2), else 0.  bits: device uint8 [batch][N] (0/1);
+ * ok_out: device uint8 [batch].
+ */
+int cbp_syndrome(const cbp_code_t *code, const uint8_t *bits, uint8_t *ok_out, int64_t batch,
+                 void *stream);
+
+/* ---- diagnostics --------------------------------------------------------- */
+const char *cbp_strerror(int status);
+const char *cbp_last_error(void);
+/* Library version, 100 * major + minor. */
+int32_t cbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBP_H */

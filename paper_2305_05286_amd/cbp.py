@@ -1,0 +1,243 @@
+"""Python binding of libcbp.so (include/cbp.h): argument marshalling only.
+
+Every decoding step runs in the HIP kernels of the shared library; PyTorch
+provides device memory and the current stream.  If the library has not been
+built this module raises on use (there is no fallback path).
+
+    from paper_2305_05286_amd import cbp
+    code = cbp.Code.from_workload(workload_code)
+    bits, iters = cbp.cbp_decode(code, llr_cuda_f32, max_iter=50)
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+from typing import Optional
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libcbp.so"
+
+CBP_OK, CBP_EINVAL, CBP_EUNSUPPORTED, CBP_EHIP, CBP_ENOMEM = 0, -1, -2, -3, -4
+KERNELS = {"auto": 0, "qc_reg": 1, "qc_stream": 2, "sparse": 4}
+DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2}
+
+# exported names declared in include/cbp.h
+EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info",
+           "cbp_opts_default", "cbp_decode", "lbp_nms_decode", "fbp_nms_decode",
+           "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
+           "cbp_version")
+
+
+class CbpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    """Mirror of cbp_opts_t."""
+    _fields_ = [
+        ("stop_rule", ctypes.c_int32),
+        ("hd_mode", ctypes.c_int32),
+        ("lmax", ctypes.c_float),
+        ("alpha", ctypes.c_float),
+        ("kernel", ctypes.c_int32),
+        ("dump_sweep", ctypes.c_int32),
+        ("dump_frames", ctypes.c_int64),
+        ("dump_q", ctypes.c_void_p),
+        ("dump_r", ctypes.c_void_p),
+        ("dump_om", ctypes.c_void_p),
+        ("dump_lam", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcbp.so (raises if it is missing: build it with paper_2305_05286_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2305_05286_amd.build`")
+        L = ctypes.CDLL(str(LIB_PATH))
+        i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+        L.cbp_code_from_csr.argtypes = [i32, i32, vp, vp, ctypes.POINTER(vp)]
+        L.cbp_code_from_qc.argtypes = [i32, i32, i32, vp, ctypes.POINTER(vp)]
+        L.cbp_code_free.argtypes = [vp]
+        L.cbp_code_free.restype = None
+        L.cbp_code_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.cbp_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.cbp_opts_default.restype = None
+        for name in ("cbp_decode", "lbp_nms_decode", "fbp_nms_decode"):
+            getattr(L, name).argtypes = [vp, vp, vp, vp, i32, i64, ctypes.POINTER(Opts), vp]
+            getattr(L, name).restype = ctypes.c_int
+        L.cbp_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(Opts), ctypes.POINTER(sz)]
+        L.cbp_syndrome.argtypes = [vp, vp, vp, i64, vp]
+        L.cbp_strerror.argtypes = [ctypes.c_int]
+        L.cbp_strerror.restype = ctypes.c_char_p
+        L.cbp_last_error.argtypes = []
+        L.cbp_last_error.restype = ctypes.c_char_p
+        L.cbp_version.argtypes = []
+        L.cbp_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != CBP_OK:
+        L = lib()
+        raise CbpError(status, f"{L.cbp_strerror(status).decode()}: {L.cbp_last_error().decode()}")
+
+
+class Code:
+    """Owning wrapper of a cbp_code_t handle."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        M, N, Z, K = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        E = ctypes.c_int64()
+        check(lib().cbp_code_info(handle, ctypes.byref(M), ctypes.byref(N), ctypes.byref(E),
+                                  ctypes.byref(Z), ctypes.byref(K)))
+        self.M, self.N, self.E, self.Z, self.kernels = M.value, N.value, E.value, Z.value, K.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def from_csr(cls, M: int, N: int, row_ptr, col_idx) -> "Code":
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        h = ctypes.c_void_p()
+        check(lib().cbp_code_from_csr(M, N, rp.ctypes.data, ci.ctypes.data, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_qc(cls, shifts, Z: int) -> "Code":
+        sh = np.ascontiguousarray(shifts, dtype=np.int32)
+        mb, nb = sh.shape
+        h = ctypes.c_void_p()
+        check(lib().cbp_code_from_qc(mb, nb, Z, sh.ctypes.data, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_workload(cls, code) -> "Code":
+        """From a paper_2305_05286_amd.workload.Code (QC if it has shifts)."""
+        if getattr(code, "shifts", None) is not None:
+            return cls.from_qc(code.shifts, code.Z)
+        return cls.from_csr(code.M, code.N, code.row_ptr, code.col_idx)
+
+    def has_kernel(self, name: str) -> bool:
+        return bool(self.kernels & KERNELS[name])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cbp_code_free(h)
+            self._h = None
+
+
+def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=None,
+          workspace=None) -> Opts:
+    o = Opts()
+    lib().cbp_opts_default(ctypes.byref(o))
+    o.stop_rule, o.hd_mode, o.lmax, o.alpha = stop_rule, hd_mode, lmax, alpha
+    o.kernel = KERNELS[kernel]
+    if dump is not None:
+        o.dump_sweep = dump["sweep"]
+        o.dump_frames = dump["frames"]
+        for k in ("q", "r", "om", "lam"):
+            t = dump.get(k)
+            setattr(o, f"dump_{k}", t.data_ptr() if t is not None else None)
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, lmax=20.0,
+         alpha=0.75, kernel="auto", dump_sweep: int = 0, dump_frames: int = 0,
+         workspace=None, out=None, stream=None):
+    import torch
+    if not (isinstance(llr, torch.Tensor) and llr.is_cuda and llr.dtype == torch.float32):
+        raise TypeError("llr must be a float32 CUDA tensor")
+    if llr.dim() != 2 or llr.shape[1] != code.N:
+        raise ValueError(f"llr must be [batch, {code.N}]")
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        bits = torch.empty((B, code.N), dtype=torch.uint8, device=dev)
+        iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    else:
+        bits, iters = out
+    dump = None
+    if dump_sweep > 0 and dump_frames > 0:
+        nd = min(dump_frames, B)
+        dump = {"sweep": dump_sweep, "frames": nd}
+        dump["lam"] = torch.full((nd, code.N), float("nan"), device=dev)
+        dump["r"] = torch.full((nd, code.E), float("nan"), device=dev)
+        if which == "cbp":
+            dump["q"] = torch.full((nd, code.N), float("nan"), device=dev)
+            dump["om"] = torch.full((nd, code.M), float("nan"), device=dev)
+    o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode",
+                         "fbp_nms": "fbp_nms_decode"}[which])
+    with torch.cuda.device(dev):
+        check(fn(code.handle, llr.data_ptr(), bits.data_ptr(), iters.data_ptr(), int(max_iter),
+                 B, ctypes.byref(o), ctypes.c_void_p(s.cuda_stream)))
+    if dump is not None:
+        return bits, iters, dump
+    return bits, iters
+
+
+def cbp_decode(code: Code, llr, max_iter: int, **kw):
+    """CBP decoding (Sec. IV-C).  Returns (bits uint8 [B,N], iters int32 [B]) on llr's device,
+    plus a dump dict when dump_sweep/dump_frames are given."""
+    return _run("cbp", code, llr, max_iter, **kw)
+
+
+def lbp_nms_decode(code: Code, llr, max_iter: int, **kw):
+    """Layered normalized min-sum baseline (same arguments as cbp_decode)."""
+    return _run("lbp_nms", code, llr, max_iter, **kw)
+
+
+def fbp_nms_decode(code: Code, llr, max_iter: int, **kw):
+    """Flooding normalized min-sum baseline (same arguments as cbp_decode)."""
+    return _run("fbp_nms", code, llr, max_iter, **kw)
+
+
+def decode(code: Code, llr, max_iter: int, algo: str = "cbp", **kw):
+    return _run(algo, code, llr, max_iter, **kw)
+
+
+def cbp_syndrome(code: Code, bits, stream=None):
+    """ok uint8 [B]: 1 where H bits^T = 0."""
+    import torch
+    if not (bits.is_cuda and bits.dtype == torch.uint8 and bits.dim() == 2 and bits.shape[1] == code.N):
+        raise ValueError("bits must be a uint8 CUDA tensor [batch, N]")
+    bits = bits.contiguous()
+    ok = torch.empty((bits.shape[0],), dtype=torch.uint8, device=bits.device)
+    s = stream if stream is not None else torch.cuda.current_stream(bits.device)
+    with torch.cuda.device(bits.device):
+        check(lib().cbp_syndrome(code.handle, bits.data_ptr(), ok.data_ptr(), bits.shape[0],
+                                 ctypes.c_void_p(s.cuda_stream)))
+    return ok
+
+
+def workspace_size(code: Code, decoder: str, batch: int, **kw) -> int:
+    o = _opts(**kw)
+    n = ctypes.c_size_t()
+    check(lib().cbp_workspace_size(code.handle, DECODERS[decoder], batch, ctypes.byref(o),
+                                   ctypes.byref(n)))
+    return n.value
+
+
+def version() -> int:
+    return int(lib().cbp_version())

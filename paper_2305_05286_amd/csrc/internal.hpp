@@ -1,0 +1,66 @@
+// Internal interfaces between the C ABI (abi.cpp) and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cbp {
+
+enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2 };
+
+struct Params {
+    float a;       // phi(lmax): lower clamp of |Q| entering phi
+    float lmax;    // upper clamp
+    float alpha;   // min-sum normalisation
+    int stop_rule; // 0 syndrome, 2 fixed sweeps
+    int hd_mode;   // CBP: 0 V2C-phase decision, 1 flushed posterior
+};
+
+struct Dump {
+    int sweep;       // 0 = off
+    int64_t frames;  // frames [0, frames) are dumped
+    float *q, *r, *om, *lam;
+};
+
+// Device tables of a CSR code for the one-frame-per-lane kernels.
+struct SparseDev {
+    int M, N, E;
+    const int *row_ptr;   // [M+1]
+    const int *col_idx;   // [E]
+    const int *edge_row;  // [E]  row of each edge
+    const int *pred_edge; // [E]  edge of the cyclically previous row of the same column
+    const int *pred_row;  // [E]  row of pred_edge
+    const uint8_t *first; // [E]  1 if this is the lowest row of its column
+    const int *last_edge; // [N]  edge of the highest row of each column
+};
+
+// Frame-interleaved workspace of the sparse kernels: element (index, frame)
+// lives at array[index * stride + frame].
+struct SparseWs {
+    int64_t stride;
+    float *a0, *a1, *a2, *a3, *a4;  // meaning depends on the algorithm
+    uint8_t *xb;
+};
+
+size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames);
+SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base);
+hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
+                         int32_t *iters, int64_t f0, int64_t nf, int max_iter,
+                         const Params &p, const SparseWs &ws, const Dump &d, hipStream_t s);
+hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
+                           hipStream_t s);
+hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
+
+// ---- QC register-resident kernels (compiled base patterns) ----------------
+// Number of compiled base patterns and the pattern table for matching.
+int qc_reg_count();
+// Fills mb, nb, Z and a pointer to the mb*nb 0/1 pattern of entry k.
+void qc_reg_entry(int k, int *mb, int *nb, int *Z, const uint8_t **pattern);
+// Host shift table of entry k for a base matrix (mb*nb, -1 = zero block):
+// writes 2*E ints to out (E = edges of the base pattern), returns their count.
+int qc_reg_shift_table(int k, const int *shifts, int *out);
+// Launch entry k.  sht: device copy of the entry's shift table.
+hipError_t launch_qc_reg(int k, int algo, const int *sht, const float *llr, uint8_t *bits,
+                         int32_t *iters, int64_t batch, int max_iter, const Params &p,
+                         const Dump &d, int *counter, int device, hipStream_t s);
+
+}  // namespace cbp

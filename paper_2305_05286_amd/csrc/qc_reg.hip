@@ -1,0 +1,484 @@
+// Register-resident decoders for quasi-cyclic codes whose base pattern is
+// compiled in (qc_graphs.inc); circulant shifts are runtime arguments.
+//
+// Layout.  A frame occupies Z lanes ("a slot"); lane l owns variable l of
+// every block-column b (v = b*Z + l): its latest V2C message Q[b], the phi of
+// that message as folded into its latest check PQ[b], the C2V message of each
+// of its edges R[e] and its hard decisions (bit b of xb) all live in VGPRs.
+// Block-row r is one layer of the sweep: its Z rows share no variable, so the
+// Z lanes update them at once with exactly the result of the paper's
+// row-by-row order.  Row k of block-row r meets variable (k + s) mod Z of
+// block-column b, i.e. lane l talks to row (l - s) mod Z: the only cross-lane
+// traffic is through LDS, one rotated (bank-conflict-free) access per edge:
+//   phase 1 (lane = variable): B2V from the latest check's belief (LDS read),
+//            V2C, hard decision, phi of the new V2C -> exchange slot of its row;
+//   phase 2 (lane = row k):    fold the row's exchange entries into the
+//            check-belief (max term, rest-of-sum, sign parity) -> LDS.
+// Two barriers per layer.  Workgroups hold lcm(Z, 64)/Z slots (Z = 96: two
+// frames in three waves) and are persistent: a slot whose frame stops (at a
+// sweep boundary) writes its outputs and claims the next frame from a global
+// counter, so long-running frames do not hold the rest of the chip.
+#include <type_traits>
+#include <utility>
+
+#include "internal.hpp"
+#include "phi.hpp"
+
+namespace cbp {
+namespace {
+
+#include "qc_graphs.inc"
+
+template <int B, int E, class F>
+__host__ __device__ __forceinline__ constexpr void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <class G>
+constexpr int count_edges() {
+    int n = 0;
+    for (int i = 0; i < G::MB * G::NB; ++i) n += G::P[i] ? 1 : 0;
+    return n;
+}
+
+template <class G>
+constexpr int slots_for() {
+    int s = 1;
+    while ((s * G::Z) % 64 != 0) ++s;
+    return s;
+}
+
+// Compile-time description of a base pattern: edges in sweep order
+// (block-row major, block-column ascending).
+template <class G>
+struct Tab {
+    static constexpr int MB = G::MB, NB = G::NB, E = count_edges<G>();
+    int er[E], eb[E], epred[E], ejpos[E];
+    bool efirst[E];
+    int rstart[MB + 1], dc[MB], csr_off[MB];
+    int elast[NB];
+    int dcmax;
+};
+
+template <class G>
+constexpr Tab<G> make_tab() {
+    Tab<G> T{};
+    int e = 0;
+    for (int r = 0; r < G::MB; ++r) {
+        T.rstart[r] = e;
+        for (int b = 0; b < G::NB; ++b)
+            if (G::P[r * G::NB + b]) {
+                T.er[e] = r;
+                T.eb[e] = b;
+                T.ejpos[e] = e - T.rstart[r];
+                ++e;
+            }
+        T.dc[r] = e - T.rstart[r];
+    }
+    T.rstart[G::MB] = e;
+    for (int b = 0; b < G::NB; ++b) {
+        int first = -1, last = -1;
+        for (int k = 0; k < e; ++k)
+            if (T.eb[k] == b) {
+                if (first < 0) first = k;
+                last = k;
+            }
+        T.elast[b] = last;
+        int prev = last;  // the latest check of a column's first row is its last row
+        for (int k = 0; k < e; ++k)
+            if (T.eb[k] == b) {
+                T.epred[k] = prev;
+                T.efirst[k] = (k == first);
+                prev = k;
+            }
+    }
+    int off = 0, mx = 0;
+    for (int r = 0; r < G::MB; ++r) {
+        T.csr_off[r] = off;
+        off += T.dc[r] * G::Z;
+        mx = T.dc[r] > mx ? T.dc[r] : mx;
+    }
+    T.dcmax = mx;
+    return T;
+}
+
+template <class G>
+struct TabOf {
+    static constexpr Tab<G> T = make_tab<G>();
+};
+
+template <class G>
+struct QcArgs {
+    static constexpr int E = count_edges<G>();
+    const float *llr;
+    uint8_t *bits;
+    int32_t *iters;
+    unsigned int *counter;
+    int64_t batch;
+    int max_iter;
+    Params p;
+    Dump d;
+    // device table [2E]: [e] = shift of the block of edge e, [E + e] = shift
+    // of the block of the latest-check edge of e
+    const int *sht;
+};
+
+// Opaque copies: recomputing a lane's rotated LDS indices per layer is cheaper
+// than letting the compiler hoist all of them (two per edge) into VGPRs.
+__device__ __forceinline__ int opaque_v(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+template <class T>
+__device__ __forceinline__ const T *opaque_s(const T *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// (x mod Z) for x in (-Z, 2Z)
+template <int Z>
+__device__ __forceinline__ int wrap(int x) {
+    x += (x < 0) ? Z : 0;
+    return x - ((x >= Z) ? Z : 0);
+}
+
+template <class G, int kAlgo>
+__global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G> A) {
+    using TT = TabOf<G>;
+    constexpr int MB = G::MB, NB = G::NB, Z = G::Z, E = count_edges<G>();
+    constexpr int SL = slots_for<G>(), DCM = TT::T.dcmax;
+    constexpr int64_t N = (int64_t)NB * Z;
+    using Mask = std::conditional_t<(NB > 32), uint64_t, uint32_t>;
+
+    __shared__ float2 sOm[(kAlgo == kCBP) ? SL : 1][(kAlgo == kCBP) ? MB * Z : 1];
+    __shared__ float2 sRow[SL][Z];
+    __shared__ float sX[SL][DCM][Z];
+    __shared__ Mask sXB[SL][Z];
+    __shared__ unsigned int sF[SL];
+    __shared__ int sBad[2][SL];
+    __shared__ int sAct[SL], sFresh[SL];
+
+    const int slot = threadIdx.x / Z;
+    const int l = threadIdx.x - slot * Z;
+    const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
+
+    // CBP: Q = latest V2C, PQ = phi(clamped Q) as folded.  NMS: Q = posterior
+    // Lambda, PQ = flooding accumulator of the new C2V messages.
+    float Q[NB], PQ[NB], R[E];
+    Mask xb = 0;
+    int64_t f;
+    int t = 0, it = 0;
+
+    auto load = [&](int64_t fr) {
+        xb = 0;
+        static_for<0, NB>([&](auto bc) {
+            constexpr int b = bc;
+            const float v = A.llr[fr * N + b * Z + l];
+            Q[b] = v;
+            PQ[b] = 0.0f;
+            if (v < 0.0f) xb |= Mask(1) << b;
+        });
+        static_for<0, E>([&](auto ec) { R[decltype(ec)::value] = 0.0f; });
+    };
+
+    if (l == 0) sF[slot] = atomicAdd(A.counter, 1u);
+    __syncthreads();
+    f = sF[slot];
+    if (f < A.batch) load(f);
+
+    for (;;) {
+        // ---------------- syndrome of the current decisions --------------
+        const int pb = it & 1;
+        ++it;
+        if (l == 0) sBad[pb][slot] = 0;
+        sXB[slot][l] = xb;
+        __syncthreads();
+        uint32_t bad = 0;
+        static_for<0, MB>([&](auto rc) {
+            constexpr int r = rc;
+            uint32_t par = 0;
+            const int lv = opaque_v(l);
+            const int *sh = opaque_s(A.sht);
+            static_for<TT::T.rstart[r], TT::T.rstart[r + 1]>([&](auto ec) {
+                constexpr int e = ec;
+                constexpr int b = TT::T.eb[e];
+                const int idx = wrap<Z>(lv + sh[e]);
+                par ^= (uint32_t)(sXB[slot][idx] >> b) & 1u;
+            });
+            bad |= par;
+        });
+        if (bad) sBad[pb][slot] = 1;
+        __syncthreads();
+        const bool ok = sBad[pb][slot] == 0;
+        const bool have = f < A.batch;
+        const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok);
+        const bool claim = done && have;
+        if (claim) {
+            static_for<0, NB>([&](auto bc) {
+                constexpr int b = bc;
+                A.bits[f * N + b * Z + l] = (uint8_t)((xb >> b) & 1u);
+            });
+            if (l == 0) {
+                A.iters[f] = t;
+                sF[slot] = atomicAdd(A.counter, 1u);
+            }
+        }
+        __syncthreads();
+        if (claim) {
+            f = sF[slot];
+            t = 0;
+            if (f < A.batch) load(f);
+        }
+        if (l == 0) {
+            sAct[slot] = f < A.batch;
+            sFresh[slot] = claim && f < A.batch;
+        }
+        __syncthreads();
+        bool anyAct = false, anyFresh = false;
+        static_for<0, SL>([&](auto sc) {
+            anyAct |= sAct[decltype(sc)::value] != 0;
+            anyFresh |= sFresh[decltype(sc)::value] != 0;
+        });
+        if (!anyAct) break;
+        if (anyFresh) continue;  // pre-check the new frames first
+
+        // ---------------- one sweep over the layers -------------------------
+        const bool first = (t == 0);
+        static_for<0, MB>([&](auto rc) {
+            constexpr int r = rc;
+            constexpr int e0 = TT::T.rstart[r], e1 = TT::T.rstart[r + 1];
+            float qk[e1 - e0];
+            const int lv = opaque_v(l);
+            const int *sh = opaque_s(A.sht);
+            // phase 1: lane = variable
+            static_for<e0, e1>([&](auto ec) {
+                constexpr int e = ec;
+                constexpr int b = TT::T.eb[e], j = e - e0;
+                if constexpr (kAlgo == kCBP) {
+                    constexpr int ep = TT::T.epred[e], rp = TT::T.er[ep];
+                    // B2V (eq. equ_s4e18) from the latest check's belief
+                    const float2 om = sOm[slot][rp * Z + wrap<Z>(lv - sh[E + e])];
+                    const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
+                    float rn = with_sign(phi32(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+                    if constexpr (TT::T.efirst[e]) {
+                        rn = first ? 0.0f : rn;       // no latest check yet
+                        R[ep] = first ? R[ep] : rn;   // commit R(c_j -> v) first
+                    } else {
+                        R[ep] = rn;
+                    }
+                    const float lam = Q[b] + rn;      // eq. equ_s4e20
+                    xb = (lam < 0.0f) ? (xb | (Mask(1) << b)) : (xb & ~(Mask(1) << b));
+                    const float qn = lam - R[e];      // V2C, eq. equ_s4e19
+                    const float fq = phiq32(qn, a, lmax);
+                    Q[b] = qn;
+                    PQ[b] = fq;
+                    sX[slot][j][wrap<Z>(lv - sh[e])] = with_sign(fq, qn < 0.0f);
+                } else {
+                    const float q = Q[b] - R[e];      // eq. equ_s2e10 / equ_s2e3
+                    qk[j] = q;
+                    sX[slot][j][wrap<Z>(lv - sh[e])] =
+                        with_sign(__builtin_fminf(__builtin_fabsf(q), lmax), q < 0.0f);
+                }
+            });
+            __syncthreads();
+            // phase 2: lane = row l of this layer
+            {
+                bool par = false;
+                if constexpr (kAlgo == kCBP) {
+                    float Mx = 0.0f, Sr = 0.0f;
+                    static_for<0, e1 - e0>([&](auto jc) {
+                        const float x = sX[slot][decltype(jc)::value][l];
+                        par ^= sign_bit(x);
+                        fold(Mx, Sr, abs_bits(x));    // C2B, eq. equ_s4e21
+                    });
+                    sOm[slot][r * Z + l] = make_float2(with_sign(Mx, par), Sr);  // eq. equ_s4e23
+                } else {
+                    float m1 = __builtin_inff(), m2 = __builtin_inff();
+                    static_for<0, e1 - e0>([&](auto jc) {
+                        const float x = sX[slot][decltype(jc)::value][l];
+                        par ^= sign_bit(x);
+                        const float ax = abs_bits(x);
+                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
+                        m1 = __builtin_fminf(m1, ax);
+                    });
+                    sRow[slot][l] = make_float2(with_sign(m1, par), m2);
+                }
+            }
+            __syncthreads();
+            if constexpr (kAlgo != kCBP) {
+                // phase 3: lane = variable, normalized min-sum C2V
+                static_for<e0, e1>([&](auto ec) {
+                    constexpr int e = ec;
+                    constexpr int b = TT::T.eb[e], j = e - e0;
+                    const float2 rw = sRow[slot][wrap<Z>(lv - sh[e])];
+                    const float aq = __builtin_fminf(__builtin_fabsf(qk[j]), lmax);
+                    const float m1 = abs_bits(rw.x);
+                    const float rn = with_sign(alpha * ((aq == m1) ? rw.y : m1),
+                                               sign_bit(rw.x) ^ (qk[j] < 0.0f));
+                    R[e] = rn;
+                    if constexpr (kAlgo == kLBPNMS) Q[b] = qk[j] + rn;  // eq. equ_s2e12
+                    else PQ[b] += rn;
+                });
+            }
+        });
+        ++t;
+
+        // ---------------- end of sweep ------------------------------------
+        if constexpr (kAlgo == kFBPNMS) {
+            if (f < A.batch)
+                static_for<0, NB>([&](auto bc) {
+                    constexpr int b = bc;
+                    Q[b] = A.llr[f * N + b * Z + l] + PQ[b];  // eq. equ_s2e6
+                    PQ[b] = 0.0f;
+                });
+        }
+        if constexpr (kAlgo != kCBP) {
+            xb = 0;
+            static_for<0, NB>([&](auto bc) {
+                constexpr int b = bc;
+                if (Q[b] < 0.0f) xb |= Mask(1) << b;
+            });
+        }
+        auto flushed = [&](auto bc) {
+            constexpr int b = bc;
+            constexpr int el = TT::T.elast[b], rl = TT::T.er[el];
+            const float2 om = sOm[slot][rl * Z + wrap<Z>(opaque_v(l) - opaque_s(A.sht)[el])];
+            const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
+            return Q[b] + with_sign(phi32(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+        };
+        if constexpr (kAlgo == kCBP) {
+            if (A.p.hd_mode == 1) {
+                xb = 0;
+                static_for<0, NB>([&](auto bc) {
+                    if (flushed(bc) < 0.0f) xb |= Mask(1) << decltype(bc)::value;
+                });
+            }
+        }
+        if (t == A.d.sweep && f < A.d.frames) {
+            const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
+            static_for<0, NB>([&](auto bc) {
+                constexpr int b = bc;
+                if constexpr (kAlgo == kCBP) {
+                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b];
+                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(bc);
+                } else {
+                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = Q[b];
+                }
+            });
+            if (A.d.r)
+                static_for<0, E>([&](auto ec) {
+                    constexpr int e = ec;
+                    constexpr int r = TT::T.er[e];
+                    const int k = wrap<Z>(l - A.sht[e]);
+                    A.d.r[f * Etot + TT::T.csr_off[r] + k * TT::T.dc[r] + TT::T.ejpos[e]] = R[e];
+                });
+            if constexpr (kAlgo == kCBP) {
+                if (A.d.om)
+                    static_for<0, MB>([&](auto rc) {
+                        constexpr int r = rc;
+                        const float2 om = sOm[slot][r * Z + l];
+                        A.d.om[f * M + r * Z + l] =
+                            with_sign(phi32(abs_bits(om.x) + om.y), sign_bit(om.x));
+                    });
+            }
+        }
+    }
+}
+
+template <class G>
+void graph_entry(int *mb, int *nb, int *Z, const uint8_t **pat) {
+    *mb = G::MB;
+    *nb = G::NB;
+    *Z = G::Z;
+    *pat = G::P;
+}
+
+template <class G>
+int graph_shift_table(const int *shifts, int *out) {
+    using TT = TabOf<G>;
+    constexpr int E = count_edges<G>();
+    for (int e = 0; e < E; ++e) {
+        out[e] = shifts[TT::T.er[e] * G::NB + TT::T.eb[e]];
+        const int ep = TT::T.epred[e];
+        out[E + e] = shifts[TT::T.er[ep] * G::NB + TT::T.eb[ep]];
+    }
+    return 2 * E;
+}
+
+template <class G, int kAlgo>
+hipError_t launch_graph(const int *sht, const float *llr, uint8_t *bits, int32_t *iters,
+                        int64_t batch, int max_iter, const Params &p, const Dump &d,
+                        int *counter, int device, hipStream_t s) {
+    constexpr int SL = slots_for<G>(), threads = SL * G::Z;
+    QcArgs<G> A{};
+    A.llr = llr;
+    A.bits = bits;
+    A.iters = iters;
+    A.counter = (unsigned int *)counter;
+    A.batch = batch;
+    A.max_iter = max_iter;
+    A.p = p;
+    A.d = d;
+    A.sht = sht;
+    // persistent grid: as many workgroups as fit on the device at once
+    static int cached_blocks[64] = {0};
+    const int dev = device < 64 ? device : 0;
+    if (cached_blocks[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(qc_reg_kernel<G, kAlgo>), threads, 0);
+        if (err != hipSuccess) return err;
+        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+        if (err != hipSuccess) return err;
+        cached_blocks[dev] = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    }
+    const int64_t need = (batch + SL - 1) / SL;
+    const int blocks = (int)(need < cached_blocks[dev] ? need : cached_blocks[dev]);
+    hipError_t err = launch_fill_i32(counter, 1, 0, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((qc_reg_kernel<G, kAlgo>), dim3(blocks), dim3(threads), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int qc_reg_count() { return CBP_QC_GRAPH_COUNT; }
+
+void qc_reg_entry(int k, int *mb, int *nb, int *Z, const uint8_t **pattern) {
+#define CBP_ENTRY(K, G) \
+    if (k == K) graph_entry<G>(mb, nb, Z, pattern);
+    CBP_QC_GRAPHS(CBP_ENTRY)
+#undef CBP_ENTRY
+}
+
+int qc_reg_shift_table(int k, const int *shifts, int *out) {
+#define CBP_TABLE(K, G) \
+    if (k == K) return graph_shift_table<G>(shifts, out);
+    CBP_QC_GRAPHS(CBP_TABLE)
+#undef CBP_TABLE
+    return 0;
+}
+
+hipError_t launch_qc_reg(int k, int algo, const int *sht, const float *llr, uint8_t *bits,
+                         int32_t *iters, int64_t batch, int max_iter, const Params &p,
+                         const Dump &d, int *counter, int device, hipStream_t s) {
+#define CBP_LAUNCH(K, G)                                                                      \
+    if (k == K) {                                                                             \
+        if (algo == kCBP)                                                                     \
+            return launch_graph<G, kCBP>(sht, llr, bits, iters, batch, max_iter, p, d,     \
+                                         counter, device, s);                                 \
+        if (algo == kLBPNMS)                                                                  \
+            return launch_graph<G, kLBPNMS>(sht, llr, bits, iters, batch, max_iter, p, d,  \
+                                            counter, device, s);                              \
+        return launch_graph<G, kFBPNMS>(sht, llr, bits, iters, batch, max_iter, p, d,      \
+                                        counter, device, s);                                  \
+    }
+    CBP_QC_GRAPHS(CBP_LAUNCH)
+#undef CBP_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cbp

@@ -1,0 +1,290 @@
+// One frame per lane, any parity-check matrix (CSR).
+//
+// Every lane of a wave runs the whole sweep of its own frame in the paper's
+// row order; since all lanes share the code, the row/edge loops and the table
+// reads are wave-uniform (scalar loads) and the per-frame state is stored
+// frame-interleaved (index-major, frame-minor) so that each access of a wave
+// is one contiguous 256-byte line.  Frames that have stopped are masked off;
+// the wave leaves its loop once every lane has stopped.
+#include "internal.hpp"
+#include "phi.hpp"
+
+namespace cbp {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ bool lane_syndrome_ok(const SparseDev &g, const uint8_t *xb, int64_t S, int64_t lf) {
+    uint32_t bad = 0;
+    for (int i = 0; i < g.M; ++i) {
+        uint32_t p = 0;
+        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) p ^= xb[(int64_t)g.col_idx[e] * S + lf];
+        bad |= p;
+    }
+    return bad == 0;
+}
+
+__device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int64_t lf,
+                          uint8_t *bits, int32_t *iters, int64_t f, int t) {
+    for (int v = 0; v < g.N; ++v) bits[f * g.N + v] = xb[(int64_t)v * S + lf];
+    iters[f] = t;
+}
+
+// --------------------------------------------------------------------------
+// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (phi of the clamped Q folded
+// into the latest check), a2 = R[E], a3 = OmM[M] (max phi term, sign bit =
+// parity), a4 = OmS[M] (rest of the phi sum), xb = hard decisions [N].
+// --------------------------------------------------------------------------
+__device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v) {
+    const int64_t S = w.stride;
+    const int e = g.last_edge[v];
+    const int j = g.edge_row[e];
+    const float q = w.a0[(int64_t)v * S + lf];
+    const float om = w.a3[(int64_t)j * S + lf];
+    const float d = excl_sum(abs_bits(om), w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf]);
+    return q + with_sign(phi32(d), sign_bit(om) ^ (q < 0.0f));
+}
+
+__global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
+    SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
+    int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
+    Dump d) {
+    const int64_t lf = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    const bool valid = lf < nf;
+    const int64_t f = f0 + lf;
+    const int64_t S = w.stride;
+    float *Q = w.a0, *PQ = w.a1, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
+    uint8_t *xb = w.xb;
+    bool active = valid;
+    // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
+    if (valid) {
+        for (int v = 0; v < g.N; ++v) {
+            const float l = llr[f * g.N + v];
+            Q[(int64_t)v * S + lf] = l;
+            xb[(int64_t)v * S + lf] = l < 0.0f;
+        }
+        for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+        if (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) {
+            write_out(g, xb, S, lf, bits, iters, f, 0);
+            active = false;
+        }
+    }
+    for (int t = 1; t <= max_iter; ++t) {
+        if (__ballot(active) == 0) break;
+        if (active) {
+            // Step 2: check-nodes in index order
+            for (int i = 0; i < g.M; ++i) {
+                float Mx = 0.0f, Sr = 0.0f;
+                bool par = false;
+                for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+                    const int v = g.col_idx[e];
+                    const int64_t iv = (int64_t)v * S + lf;
+                    const float q = Q[iv];
+                    float rn = 0.0f;
+                    if (!(t == 1 && g.first[e])) {
+                        // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
+                        // from its belief, then committed to R(c_j -> v) first.
+                        const int64_t ij = (int64_t)g.pred_row[e] * S + lf;
+                        const float om = OmM[ij];
+                        const float dd = excl_sum(abs_bits(om), OmS[ij], PQ[iv]);
+                        rn = with_sign(phi32(dd), sign_bit(om) ^ (q < 0.0f));
+                        R[(int64_t)g.pred_edge[e] * S + lf] = rn;
+                    }
+                    const float lam = q + rn;                 // eq. equ_s4e20
+                    xb[iv] = lam < 0.0f;                      // eq. equ_s2e7
+                    const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
+                    const float fq = phiq32(qn, p.a, p.lmax);
+                    Q[iv] = qn;
+                    PQ[iv] = fq;
+                    fold(Mx, Sr, fq);                         // C2B, eq. equ_s4e21
+                    par ^= (qn < 0.0f);
+                }
+                OmM[(int64_t)i * S + lf] = with_sign(Mx, par);  // eq. equ_s4e23
+                OmS[(int64_t)i * S + lf] = Sr;
+            }
+            if (p.hd_mode == 1)
+                for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed(g, w, lf, v) < 0.0f;
+            if (t == d.sweep && f < d.frames) {
+                for (int v = 0; v < g.N; ++v) {
+                    if (d.q) d.q[f * g.N + v] = Q[(int64_t)v * S + lf];
+                    if (d.lam) d.lam[f * g.N + v] = cbp_flushed(g, w, lf, v);
+                }
+                if (d.r)
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf];
+                if (d.om)
+                    for (int i = 0; i < g.M; ++i) {
+                        const float om = OmM[(int64_t)i * S + lf];
+                        const float s = abs_bits(om) + OmS[(int64_t)i * S + lf];
+                        d.om[f * g.M + i] = with_sign(phi32(s), sign_bit(om));
+                    }
+            }
+            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
+            if (stop) {
+                write_out(g, xb, S, lf, bits, iters, f, t);
+                active = false;
+            }
+        }
+    }
+    if (active) write_out(g, xb, S, lf, bits, iters, f, max_iter);  // max_iter == 0
+}
+
+// --------------------------------------------------------------------------
+// Normalized min-sum baselines.  ws: a0 = Lambda[N], a1 = R[E],
+// a2 = Lambda accumulator of the flooding schedule [N].
+// --------------------------------------------------------------------------
+template <bool kFlood>
+__global__ __launch_bounds__(kWave) void nms_sparse_kernel(
+    SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
+    int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
+    Dump d) {
+    const int64_t lf = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    const bool valid = lf < nf;
+    const int64_t f = f0 + lf;
+    const int64_t S = w.stride;
+    float *Lam = w.a0, *R = w.a1, *Acc = w.a2;
+    uint8_t *xb = w.xb;
+    bool active = valid;
+    if (valid) {
+        for (int v = 0; v < g.N; ++v) {
+            const float l = llr[f * g.N + v];
+            Lam[(int64_t)v * S + lf] = l;
+            xb[(int64_t)v * S + lf] = l < 0.0f;
+        }
+        for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+        if (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) {
+            write_out(g, xb, S, lf, bits, iters, f, 0);
+            active = false;
+        }
+    }
+    for (int t = 1; t <= max_iter; ++t) {
+        if (__ballot(active) == 0) break;
+        if (active) {
+            if (kFlood)
+                for (int v = 0; v < g.N; ++v) Acc[(int64_t)v * S + lf] = 0.0f;
+            for (int i = 0; i < g.M; ++i) {
+                const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+                float m1 = __builtin_inff(), m2 = __builtin_inff();
+                bool par = false;
+                for (int e = e0; e < e1; ++e) {
+                    const float q = Lam[(int64_t)g.col_idx[e] * S + lf] - R[(int64_t)e * S + lf];
+                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                    m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
+                    m1 = __builtin_fminf(m1, aq);
+                    par ^= (q < 0.0f);
+                }
+                for (int e = e0; e < e1; ++e) {
+                    const int64_t iv = (int64_t)g.col_idx[e] * S + lf;
+                    const int64_t ie = (int64_t)e * S + lf;
+                    const float q = Lam[iv] - R[ie];
+                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                    const float rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
+                    R[ie] = rn;
+                    if (kFlood) Acc[iv] += rn;
+                    else Lam[iv] = q + rn;  // eq. equ_s2e12
+                }
+            }
+            if (kFlood)
+                for (int v = 0; v < g.N; ++v) {
+                    const int64_t iv = (int64_t)v * S + lf;
+                    Lam[iv] = llr[f * g.N + v] + Acc[iv];  // eq. equ_s2e6
+                }
+            for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = Lam[(int64_t)v * S + lf] < 0.0f;
+            if (t == d.sweep && f < d.frames) {
+                if (d.lam)
+                    for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[(int64_t)v * S + lf];
+                if (d.r)
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf];
+            }
+            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
+            if (stop) {
+                write_out(g, xb, S, lf, bits, iters, f, t);
+                active = false;
+            }
+        }
+    }
+    if (active) write_out(g, xb, S, lf, bits, iters, f, max_iter);
+}
+
+__global__ __launch_bounds__(256) void syndrome_kernel(SparseDev g, const uint8_t *__restrict__ bits,
+                                                       uint8_t *__restrict__ ok, int64_t batch) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= batch) return;
+    uint32_t bad = 0;
+    for (int i = 0; i < g.M; ++i) {
+        uint32_t par = 0;
+        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) par ^= bits[f * g.N + g.col_idx[e]] & 1u;
+        bad |= par;
+    }
+    ok[f] = bad == 0;
+}
+
+__global__ void fill_i32_kernel(int *p, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+}  // namespace
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames) {
+    const int64_t S = round_up(frames, kWave);
+    int64_t floats = algo == kCBP ? (2LL * g.N + g.E + 2LL * g.M) : (2LL * g.N + g.E);
+    // each array starts on a 256-byte boundary
+    return (size_t)(floats * S * 4 + (int64_t)g.N * S + 8 * 256);
+}
+
+SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base) {
+    SparseWs w{};
+    w.stride = round_up(frames, kWave);
+    const int64_t S = w.stride;
+    char *p = (char *)base;
+    auto take = [&](int64_t bytes) {
+        char *r = p;
+        p += round_up(bytes, 256);
+        return r;
+    };
+    if (algo == kCBP) {
+        w.a0 = (float *)take(4LL * g.N * S);
+        w.a1 = (float *)take(4LL * g.N * S);
+        w.a2 = (float *)take(4LL * g.E * S);
+        w.a3 = (float *)take(4LL * g.M * S);
+        w.a4 = (float *)take(4LL * g.M * S);
+    } else {
+        w.a0 = (float *)take(4LL * g.N * S);
+        w.a1 = (float *)take(4LL * g.E * S);
+        w.a2 = (float *)take(4LL * g.N * S);
+    }
+    w.xb = (uint8_t *)take((int64_t)g.N * S);
+    return w;
+}
+
+hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
+                         int32_t *iters, int64_t f0, int64_t nf, int max_iter, const Params &p,
+                         const SparseWs &ws, const Dump &d, hipStream_t s) {
+    const dim3 grid((unsigned)((nf + kWave - 1) / kWave)), block(kWave);
+    if (algo == kCBP)
+        hipLaunchKernelGGL(cbp_sparse_kernel, grid, block, 0, s, g, llr, bits, iters, f0, nf,
+                           max_iter, p, ws, d);
+    else if (algo == kLBPNMS)
+        hipLaunchKernelGGL(nms_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, f0,
+                           nf, max_iter, p, ws, d);
+    else
+        hipLaunchKernelGGL(nms_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, f0,
+                           nf, max_iter, p, ws, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
+                           hipStream_t s) {
+    const dim3 grid((unsigned)((batch + 255) / 256)), block(256);
+    hipLaunchKernelGGL(syndrome_kernel, grid, block, 0, s, g, bits, ok, batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *ptr, int n, int value, hipStream_t s) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ptr, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace cbp

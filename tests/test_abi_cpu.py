@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: the library loads, exports what include/cbp.h
+declares, and its host-side validation returns the documented errors."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2305_05286_amd import cbp
+from paper_2305_05286_amd.workload import get_code
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not cbp.LIB_PATH.exists():
+        from paper_2305_05286_amd.build import build
+        build(verbose=False)
+    return cbp.lib()
+
+
+def declared_functions():
+    text = (ROOT / "include" / "cbp.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_function(L):
+    names = declared_functions()
+    assert len(names) >= 12
+    assert set(names) == set(cbp.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_opts_defaults_and_layout(L):
+    o = cbp.Opts()
+    L.cbp_opts_default(ctypes.byref(o))
+    assert (o.stop_rule, o.hd_mode, o.kernel, o.dump_sweep) == (0, 0, 0, 0)
+    assert o.lmax == 20.0 and o.alpha == 0.75
+    # 6 x 4-byte fields, int64, 6 pointer-sized fields (C natural alignment)
+    assert ctypes.sizeof(cbp.Opts) == 80 and cbp.Opts.dump_frames.offset == 24
+
+
+def test_strerror_and_version(L):
+    assert L.cbp_strerror(0) == b"ok"
+    assert L.cbp_strerror(-1) == b"invalid argument"
+    assert L.cbp_strerror(-2) == b"unsupported"
+    assert cbp.version() >= 100
+
+
+def test_code_handles(L):
+    c = cbp.Code.from_workload(get_code("qc2304"))
+    assert (c.M, c.N, c.E, c.Z) == (1152, 2304, 7296, 96)
+    assert c.has_kernel("qc_reg") and c.has_kernel("sparse")
+    c1 = cbp.Code.from_workload(get_code("reg36_n96"))
+    assert (c1.M, c1.N, c1.E, c1.Z) == (48, 96, 288, 0)
+    assert not c1.has_kernel("qc_reg")
+    # same base pattern, other shifts: still the compiled pattern
+    c2 = cbp.Code.from_workload(get_code("qc2304_alt"))
+    assert c2.has_kernel("qc_reg")
+    # a base pattern that is not compiled in
+    c3 = cbp.Code.from_workload(get_code("qc26112"))
+    assert not c3.has_kernel("qc_reg")
+
+
+@pytest.mark.parametrize("rp,ci,why", [
+    ([0, 1, 3], [0, 1, 2], "degree"),          # row of degree 1
+    ([0, 2, 4], [1, 0, 1, 2], "ascending"),    # not ascending
+    ([0, 2, 4], [0, 1, 1, 5], "range"),        # column out of range
+    ([0, 2, 4], [0, 1, 0, 1], "no edge"),      # column 2 unused
+])
+def test_csr_validation(L, rp, ci, why):
+    with pytest.raises(cbp.CbpError) as ei:
+        cbp.Code.from_csr(2, 3, rp, ci)
+    assert ei.value.status == cbp.CBP_EINVAL
+
+
+def test_qc_validation(L):
+    with pytest.raises(cbp.CbpError):
+        cbp.Code.from_qc(np.array([[0, 5], [1, -2]]), 4)  # -2 and 5 out of range
+    h = ctypes.c_void_p()
+    assert L.cbp_code_from_qc(0, 2, 4, None, ctypes.byref(h)) == cbp.CBP_EINVAL
+
+
+def test_decode_argument_errors_without_gpu(L):
+    c = cbp.Code.from_workload(get_code("reg36_n96"))
+    o = cbp.Opts()
+    L.cbp_opts_default(ctypes.byref(o))
+    # NULL code
+    assert L.cbp_decode(None, None, None, None, 10, 4, None, None) == cbp.CBP_EINVAL
+    # batch == 0 is a no-op even with NULL buffers
+    assert L.cbp_decode(c.handle, None, None, None, 10, 0, None, None) == cbp.CBP_OK
+    # negative sizes
+    assert L.cbp_decode(c.handle, None, None, None, -1, 0, None, None) == cbp.CBP_EINVAL
+    assert L.lbp_nms_decode(c.handle, None, None, None, 5, -3, None, None) == cbp.CBP_EINVAL
+    # NULL buffers with frames
+    assert L.fbp_nms_decode(c.handle, None, None, None, 5, 8, None, None) == cbp.CBP_EINVAL
+    # option errors are reported before any device work
+    fake = ctypes.c_void_p(16)
+    o.stop_rule = 1
+    assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+    o.stop_rule = 0
+    o.kernel = cbp.KERNELS["qc_reg"]
+    assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+    assert b"register-resident" in L.cbp_last_error()
+    o.kernel = 0
+    o.lmax = -1.0
+    assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    o.lmax = 20.0
+    o.hd_mode = 1
+    assert L.lbp_nms_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    assert L.cbp_syndrome(None, None, None, 3, None) == cbp.CBP_EINVAL
+
+
+def test_workspace_sizes(L):
+    c = cbp.Code.from_workload(get_code("reg36_n96"))
+    n = cbp.workspace_size(c, "cbp", 2000)
+    S = 2048  # frames padded to whole waves
+    assert n >= (2 * 96 + 288 + 2 * 48) * 4 * S + 96 * S
+    assert cbp.workspace_size(c, "cbp", 0) == 0
+    q = cbp.Code.from_workload(get_code("qc2304"))
+    assert 0 < cbp.workspace_size(q, "cbp", 131072) <= 4096

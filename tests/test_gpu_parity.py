@@ -1,0 +1,213 @@
+"""GPU decoders through the C ABI against the FP64 oracle on the same inputs.
+
+Bar: hard decisions and iteration counts identical on >= 99.9% of frames
+(per SNR point), FP32 messages within 1e-4 * max(|x64|, 1) of FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_05286_amd import cbp
+from paper_2305_05286_amd.workload import encode, get_code, make_frames, noiseless_llrs
+
+from helpers import syndrome
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PARITY = 0.999
+MSG_TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(code_w, llr, max_iter, algo="cbp", **kw):
+    c = cbp.Code.from_workload(code_w)
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    out = cbp.decode(c, t, max_iter, algo, **kw)
+    torch.cuda.synchronize()
+    bits, iters = out[0].cpu().numpy(), out[1].cpu().numpy()
+    if len(out) == 3:
+        return bits, iters, {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in out[2].items()}
+    return bits, iters
+
+
+def agree(gb, gi, ob, oi):
+    return ((gb == ob).all(axis=1) & (gi == oi))
+
+
+# ------------------------------------------------------- decisions / iterations
+
+CASES = [
+    # (code, algo, kernel, snr list, frames, max_iter)
+    ("reg36_n96", "cbp", "sparse", [1.0, 2.0, 3.0], 2000, 30),
+    ("qc2304", "cbp", "qc_reg", [1.5, 2.0, 2.5], 4096, 50),
+    ("qc2304_alt", "cbp", "qc_reg", [2.0], 2001, 50),
+    ("qc_t16", "cbp", "qc_reg", [1.0, 2.5], 2003, 30),
+    ("qc_t64s", "cbp", "qc_reg", [1.0, 2.5], 1999, 30),
+    ("qc_t64s", "cbp", "sparse", [2.0], 1000, 30),
+    ("qc2304", "cbp", "sparse", [2.0], 500, 50),
+    ("reg36_n96", "lbp_nms", "sparse", [2.0, 3.0], 2000, 30),
+    ("reg36_n96", "fbp_nms", "sparse", [2.0, 3.0], 2000, 30),
+    ("qc2304", "lbp_nms", "qc_reg", [2.0, 2.5], 4096, 50),
+    ("qc2304", "fbp_nms", "qc_reg", [2.0, 2.5], 4096, 50),
+    ("qc_t64s", "lbp_nms", "qc_reg", [2.0], 2000, 30),
+    ("qc_t16", "fbp_nms", "qc_reg", [2.0], 2000, 30),
+]
+
+
+@pytest.mark.parametrize("name,algo,kernel,snrs,B,max_iter", CASES,
+                         ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in CASES])
+def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_iter):
+    code = get_code(name)
+    for k, snr in enumerate(snrs):
+        llr, cw = make_frames(code, snr, B, key=(21, k))
+        say(f"[gpu] {name} {algo} {kernel} snr={snr} B={B}")
+        gb, gi = run_gpu(code, llr, max_iter, algo, kernel=kernel)
+        o = oracle.decode(code, llr, max_iter, algo)
+        ok = agree(gb, gi, o["bits"], o["iters"])
+        conv = o["iters"] < max_iter
+        say(f"    parity {ok.mean():.5f} (converged {ok[conv].mean() if conv.any() else 1:.5f}, "
+            f"failed {ok[~conv].mean() if (~conv).any() else 1:.5f}), mean iters gpu "
+            f"{gi.mean():.3f} oracle {o['iters'].mean():.3f}, FER {(o['bits'] != cw).any(1).mean():.4f}")
+        assert ok.mean() >= PARITY, (snr, ok.mean())
+        # stopped frames carry codewords
+        stopped = gi < max_iter
+        assert (syndrome(code, gb[stopped]) == 0).all()
+
+
+# ------------------------------------------------------------------ messages
+
+MSG_CASES = [("reg36_n96", "cbp", "sparse"), ("qc2304", "cbp", "qc_reg"),
+             ("qc_t64s", "cbp", "qc_reg"), ("qc2304", "lbp_nms", "qc_reg"),
+             ("qc2304", "fbp_nms", "qc_reg"), ("reg36_n96", "lbp_nms", "sparse")]
+
+
+@pytest.mark.parametrize("name,algo,kernel", MSG_CASES, ids=[f"{a}-{b}-{c}" for a, b, c in MSG_CASES])
+def test_messages_match_fp64(name, algo, kernel):
+    code = get_code(name)
+    llr, _ = make_frames(code, 2.0, 64, key=(22,))
+    for k in [1, 2, 3, 5]:
+        say(f"[gpu] messages {name} {algo} {kernel} sweep {k}")
+        gb, gi, d = run_gpu(code, llr, k, algo, kernel=kernel, stop_rule=2, dump_sweep=k,
+                            dump_frames=64)
+        o = oracle.decode(code, llr, k, algo, stop_rule=2, dump_sweep=k, ndump=64)
+        keys = ["lam", "r"] + (["q", "om"] if algo == "cbp" else [])
+        for key in keys:
+            ref = o[{"lam": "Lam", "r": "R", "q": "Q", "om": "Om"}[key]]
+            got = d[key].astype(np.float64)
+            err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+            say(f"    {key}: max err {err.max():.3e}  p99.99 {np.quantile(err, 0.9999):.3e}")
+            assert err.max() <= MSG_TOL, (key, k, err.max())
+
+
+# ------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc2304", "qc_t16"])
+def test_edge_cases(name):
+    code = get_code(name)
+    say(f"[gpu] edge cases {name}")
+    llr, cw = make_frames(code, 1.5, 130, key=(23,))
+    for algo in ["cbp", "lbp_nms", "fbp_nms"]:
+        # max_iter = 0: [L < 0], no sweep
+        gb, gi = run_gpu(code, llr, 0, algo)
+        assert (gi == 0).all() and np.array_equal(gb, (llr < 0).astype(np.uint8))
+        # noiseless input stops before the first sweep
+        nl, ncw = noiseless_llrs(code, 37, 3.0)
+        gb, gi = run_gpu(code, nl, 10, algo)
+        assert (gi == 0).all() and np.array_equal(gb, ncw)
+        # all-zero LLRs: Lambda = 0 decides 0, the zero word is a codeword
+        gb, gi = run_gpu(code, np.zeros((5, code.N), np.float32), 10, algo)
+        assert (gi == 0).all() and not gb.any()
+        # fixed number of sweeps
+        gb, gi = run_gpu(code, llr[:33], 4, algo, stop_rule=2)
+        o = oracle.decode(code, llr[:33], 4, algo, stop_rule=2)
+        assert (gi == 4).all() and agree(gb, gi, o["bits"], o["iters"]).mean() >= 0.99
+        # batch of one, and saturated inputs
+        big = np.where(llr[:3] < 0, -1e4, 1e4).astype(np.float32)
+        big[:, ::7] *= -1
+        gb, gi = run_gpu(code, big, 20, algo)
+        o = oracle.decode(code, big, 20, algo)
+        assert np.array_equal(gi, o["iters"]) and np.array_equal(gb, o["bits"])
+        gb, gi = run_gpu(code, llr[:1], 20, algo)
+        o = oracle.decode(code, llr[:1], 20, algo)
+        assert np.array_equal(gi, o["iters"]) and np.array_equal(gb, o["bits"])
+    # batch 0 is a no-op
+    c = cbp.Code.from_workload(code)
+    bits, iters = cbp.cbp_decode(c, torch.zeros((0, code.N), device="cuda"), 10)
+    assert bits.shape == (0, code.N)
+
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc2304"])
+def test_flushed_decision_mode(name):
+    code = get_code(name)
+    llr, _ = make_frames(code, 2.0, 1000, key=(24,))
+    say(f"[gpu] hd_mode=1 {name}")
+    gb, gi = run_gpu(code, llr, 30, "cbp", hd_mode=1)
+    o = oracle.decode(code, llr, 30, "cbp", hd_mode=1)
+    assert agree(gb, gi, o["bits"], o["iters"]).mean() >= PARITY
+    # flushed CBP decisions are layered BP's
+    l = oracle.decode(code, llr, 30, "lbp")
+    assert agree(gb, gi, l["bits"], l["iters"]).mean() >= PARITY
+
+
+@pytest.mark.parametrize("name,kernel", [("qc2304", "qc_reg"), ("reg36_n96", "sparse")])
+def test_symmetry_and_determinism(name, kernel):
+    code = get_code(name)
+    llr, _ = make_frames(code, 1.5, 512, key=(25,))
+    rng = np.random.default_rng(5)
+    c = encode(code, rng.integers(0, 2, size=(512, code.K), dtype=np.uint8))
+    say(f"[gpu] symmetry {name}")
+    for algo in ["cbp", "lbp_nms", "fbp_nms"]:
+        a = run_gpu(code, llr, 25, algo, kernel=kernel)
+        b = run_gpu(code, llr * (1 - 2 * c.astype(np.float32)), 25, algo, kernel=kernel)
+        a2 = run_gpu(code, llr, 25, algo, kernel=kernel)
+        assert np.array_equal(a[0], a2[0]) and np.array_equal(a[1], a2[1])
+        assert np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0] ^ c, b[0])
+
+
+def test_syndrome_entry_point():
+    code = get_code("qc2304")
+    llr, cw = make_frames(code, 1.0, 300, key=(26,))
+    bits = (llr < 0).astype(np.uint8)
+    bits[:100] = cw[:100]
+    c = cbp.Code.from_workload(code)
+    say("[gpu] syndrome")
+    ok = cbp.cbp_syndrome(c, torch.from_numpy(bits).cuda()).cpu().numpy()
+    ref = (syndrome(code, bits) == 0).all(axis=1)
+    assert np.array_equal(ok.astype(bool), ref) and ok[:100].all()
+
+
+def test_kernel_selection_errors():
+    code = get_code("reg36_n96")
+    c = cbp.Code.from_workload(code)
+    t = torch.zeros((4, code.N), device="cuda")
+    with pytest.raises(cbp.CbpError) as ei:
+        cbp.cbp_decode(c, t, 5, kernel="qc_reg")
+    assert ei.value.status == cbp.CBP_EUNSUPPORTED
+    with pytest.raises(cbp.CbpError) as ei:
+        cbp.cbp_decode(c, t, 5, stop_rule=1)
+    assert ei.value.status == cbp.CBP_EUNSUPPORTED
+
+
+def test_full_batch_sampled_parity():
+    # the benchmark's configuration: 131072 frames of the n=2304 code in one
+    # launch, checked on frames sampled across the batch
+    code = get_code("qc2304")
+    B = 131072
+    llr, cw = make_frames(code, 2.0, B, key=(27,))
+    say(f"[gpu] full batch B={B}")
+    gb, gi = run_gpu(code, llr, 50, "cbp")
+    idx = np.unique(np.linspace(0, B - 1, 384).astype(np.int64))
+    o = oracle.decode(code, llr[idx], 50, "cbp")
+    ok = agree(gb[idx], gi[idx], o["bits"], o["iters"])
+    say(f"    sampled parity {ok.mean():.5f}")
+    assert ok.mean() >= PARITY
+    stopped = gi < 50
+    assert (syndrome(code, gb[stopped][:20000]) == 0).all()
