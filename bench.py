@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Throughput of CBP decoding on one MI355X, at matched frame-error rate.
+
+Workload: the n=2304 rate-1/2 QC code (12x24 base, Z=96), 131072 frames of
+synthetic BPSK/AWGN FP32 LLRs per batch, at most 50 sweeps, early stop on a
+zero syndrome.  The run
+
+  1. sweeps Eb/N0 = 1.0 .. 2.5 dB (step 0.25) with CBP and the layered and
+     flooding normalized min-sum baselines (alpha = 0.75) on identical inputs,
+     recording FER / BER / mean sweeps / decoded info Gbit/s per point;
+  2. interpolates, per decoder, the Eb/N0 where FER = 1e-2 and 1e-3
+     (log-linear between points) and the Gbit/s there;
+  3. times W warm-up + K decodes of one batch at the sweep point nearest
+     CBP's FER = 1e-3 crossing (inputs resident in HBM) and reports that
+     decoded info Gbit/s as `value`;
+  4. reports the roofline of the CBP kernel (algorithmic state bytes per
+     launch over its average duration, HIP events on the launch stream) and
+     the FP64 CPU oracle timed on a bounded sample of the same batch.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "decoded info Gbit/s at matched FER (CBP vs layered min-sum); % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+DECODERS = ("cbp", "lbp_nms", "fbp_nms")
+KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update((ROOT / p).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(iters: np.ndarray, E: int, M: int, N: int) -> float:
+    """CBP state bytes per frame: I (20E + 4M + E/8) + 5N + 4 (FP32 messages).
+
+    Per edge-update: read R(c_i->v) 4, write R(c_j->v) 4, read and write Q_v 8,
+    read Omega_cj 4; per check-update write Omega 4; per sweep E syndrome bits;
+    per frame LLR in (4N), bits out (N) and the sweep count (4)."""
+    per_sweep = 20.0 * E + 4.0 * M + E / 8.0
+    return float(iters.astype(np.float64).sum() * per_sweep + len(iters) * (5.0 * N + 4.0))
+
+
+def crossing(snrs, fers, target, floor):
+    """Eb/N0 where FER falls through target (log-linear), or None.  A point
+    with no frame error counts as `floor` (half an error in the batch)."""
+    for i in range(len(snrs) - 1):
+        f0, f1 = max(fers[i], floor), max(fers[i + 1], floor)
+        if f0 >= target > f1:
+            l0, l1 = math.log10(f0), math.log10(f1)
+            return snrs[i] + (math.log10(target) - l0) / (l1 - l0) * (snrs[i + 1] - snrs[i])
+    return None
+
+
+def interp(x, xs, ys):
+    return float(np.interp(x, xs, ys))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=131072)
+    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--ebn0", type=float, default=None,
+                    help="operating Eb/N0 of the timed loop (default: from the sweep)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the Eb/N0 sweep")
+    ap.add_argument("--decoders", default="cbp,lbp_nms,fbp_nms",
+                    help="decoders in the timed loop (the first one is `value`)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; frames are independent, "
+                                   "so N GPUs would each run the same kernel on 1/N of the batch"}))
+        return 2
+
+    import torch
+
+    from paper_2305_05286_amd import cbp
+    from paper_2305_05286_amd.workload import get_code, make_frames
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return 0
+
+    code = get_code("qc2304")
+    handle = cbp.Code.from_workload(code)
+    B, MI = args.frames, args.max_iter
+    K_info = code.K
+    decoders = [d for d in args.decoders.split(",") if d]
+    stream = torch.cuda.current_stream(dev)
+
+    def decode(algo, llr_t, out, ws):
+        return cbp.decode(handle, llr_t, MI, algo, out=out, workspace=ws)
+
+    bits = torch.empty((B, code.N), dtype=torch.uint8, device=dev)
+    iters = torch.empty((B,), dtype=torch.int32, device=dev)
+    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+
+    def load(snr):
+        t0 = time.time()
+        llr, cw = make_frames(code, snr, B, key=(2024, int(round(snr * 100))))
+        llr_t = torch.from_numpy(llr).to(dev)
+        cw_t = torch.from_numpy(cw[:, :K_info]).to(dev)
+        log(f"[bench] generated {B} frames at {snr:.2f} dB in {time.time() - t0:.1f}s")
+        return llr, llr_t, cw_t
+
+    def timed(algo, llr_t, reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for s, e in ev:
+            s.record(stream)
+            decode(algo, llr_t, (bits, iters), ws)
+            e.record(stream)
+        torch.cuda.synchronize()
+        return [s.elapsed_time(e) / 1e3 for s, e in ev]
+
+    def quality(cw_t):
+        fe = (bits[:, :K_info] != cw_t).any(dim=1)
+        be = (bits[:, :K_info] != cw_t).sum()
+        it = iters.to(torch.float64)
+        return {"fer": fe.float().mean().item(), "ber": be.item() / (B * K_info),
+                "mean_iters": it.mean().item(), "failures": int((iters >= MI).sum().item())}
+
+    # ---------------- 1. Eb/N0 sweep ---------------------------------------
+    sweep = {d: [] for d in DECODERS}
+    snrs = [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]
+    if not args.no_sweep:
+        for snr in snrs:
+            _, llr_t, cw_t = load(snr)
+            for algo in DECODERS:
+                decode(algo, llr_t, (bits, iters), ws)  # warm-up
+                t = float(np.median(timed(algo, llr_t, 2)))
+                q = quality(cw_t)
+                q.update(ebn0_db=snr, seconds=t, gbps=B * K_info / t / 1e9)
+                sweep[algo].append(q)
+                log(f"[bench] {snr:.2f} dB {algo:8s} FER {q['fer']:.2e} iters {q['mean_iters']:.2f} "
+                    f"{q['gbps']:.1f} Gbit/s")
+            del llr_t, cw_t
+    matched = {}
+    if not args.no_sweep:
+        for T in (1e-2, 1e-3):
+            row = {}
+            for algo in DECODERS:
+                xs = [p["ebn0_db"] for p in sweep[algo]]
+                x = crossing(xs, [p["fer"] for p in sweep[algo]], T, 0.5 / B)
+                row[algo] = None if x is None else {
+                    "ebn0_db": round(x, 4), "gbps": round(interp(x, xs, [p["gbps"] for p in sweep[algo]]), 3)}
+            c, l = row.get("cbp"), row.get("lbp_nms")
+            if c and l:
+                row["cbp_over_lbp_nms_gbps"] = round(c["gbps"] / l["gbps"], 4)
+                row["cbp_minus_lbp_nms_db"] = round(c["ebn0_db"] - l["ebn0_db"], 4)
+            matched[f"fer_{T:g}"] = row
+
+    # ---------------- 2. timed loop at the operating point ------------------
+    op = args.ebn0
+    if op is None:
+        x = (matched.get("fer_0.001", {}).get("cbp") or {}).get("ebn0_db") if matched else None
+        op = snrs[int(np.argmin([abs(s - x) for s in snrs]))] if x is not None else 2.0
+    llr, llr_t, cw_t = load(op)
+    results = {}
+    for algo in decoders:
+        for _ in range(args.warmup):
+            decode(algo, llr_t, (bits, iters), ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        times = timed(algo, llr_t, args.steps)
+        wall = time.perf_counter() - t0
+        q = quality(cw_t)
+        it_np = iters.cpu().numpy()
+        results[algo] = {"times": times, "wall": wall, "quality": q, "iters": it_np,
+                         "gbps": B * K_info * args.steps / sum(times) / 1e9}
+        log(f"[bench] timed {algo}: {args.steps} x {np.mean(times) * 1e3:.2f} ms, "
+            f"{results[algo]['gbps']:.1f} Gbit/s, FER {q['fer']:.2e}, iters {q['mean_iters']:.2f}")
+    head = results[decoders[0]]
+    ms = float(np.mean(head["times"]) * 1e3)
+
+    # ---------------- 3. roofline of the CBP kernel --------------------------
+    roof = None
+    if "cbp" in results:
+        r = results["cbp"]
+        byts = algorithmic_bytes(r["iters"], code.E, code.M, code.N)
+        dur = float(np.mean(r["times"]))
+        ach = byts / dur / 1e9
+        traffic = None
+        tf = ROOT / "profiles" / "traffic_qc2304_cbp.json"
+        if tf.exists():
+            t = json.loads(tf.read_text())
+            if t.get("kernel_hash") == kernel_hash() and abs(t.get("ebn0_db", -1) - op) < 1e-9:
+                traffic = t.get("hbm_bytes_per_launch")
+        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "qc_reg_kernel<QcGraph0, CBP>",
+                "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(dur * 1e3, 4),
+                "frame_sweeps_per_s": float(r["iters"].sum()) / dur}
+
+    # ---------------- 4. CPU baseline: the FP64 oracle ----------------------
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        cal = 256
+        t0 = time.perf_counter()
+        oracle.decode(code, llr[:cal], MI, "cbp")
+        per = (time.perf_counter() - t0) / cal
+        n = int(min(B, max(cal, args.cpu_seconds / max(per, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.decode(code, llr[:n], MI, "cbp")
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(n * K_info / dt / 1e9, 6), "unit": "Gbit/s",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"first {n} of the {B} timed frames ({op} dB), FP64 CBP oracle, {dt:.1f}s"}
+        log(f"[bench] cpu oracle: {n} frames in {dt:.1f}s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(head["gbps"], 3),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"QC-LDPC n=2304 (12x24 base, Z=96, rate 1/2), {B} frames/batch, "
+                               f"BPSK/AWGN Eb/N0 {op} dB, FP32 LLRs, max {MI} sweeps, "
+                               f"decoder {decoders[0]}",
+                   "code": "qc2304", "batch": B, "ebn0_db": op, "max_iter": MI,
+                   "decoder": decoders[0], "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "operating_point": {a: {"gbps": round(v["gbps"], 3), **{k: (round(x, 6) if isinstance(x, float) else x)
+                                                               for k, x in v["quality"].items()}}
+                            for a, v in results.items()},
+        "matched_fer": matched or None,
+        "sweep": {a: [{k: (round(x, 6) if isinstance(x, float) else x) for k, x in p.items()} for p in v]
+                  for a, v in sweep.items()} if not args.no_sweep else None,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
