@@ -2,8 +2,8 @@
 // compiled in (qc_graphs.inc); circulant shifts are runtime arguments.
 //
 // Layout.  A frame occupies Z lanes ("a slot"); lane l owns variable l of
-// every block-column b (v = b*Z + l): its latest V2C message Q[b], the phi of
-// that message as folded into its latest check PQ[b], the C2V message of each
+// every block-column b (v = b*Z + l): its latest V2C message Q[b], the psi
+// (phi / ln2) of that message as folded into its latest check PQ[b], the C2V message of each
 // of its edges R[e] and its hard decisions (bit b of xb) all live in VGPRs.
 // Block-row r is one layer of the sweep: its Z rows share no variable, so the
 // Z lanes update them at once with exactly the result of the paper's
@@ -11,7 +11,7 @@
 // block-column b, i.e. lane l talks to row (l - s) mod Z: the only cross-lane
 // traffic is through LDS, one rotated (bank-conflict-free) access per edge:
 //   phase 1 (lane = variable): B2V from the latest check's belief (LDS read),
-//            V2C, hard decision, phi of the new V2C -> exchange slot of its row;
+//            V2C, hard decision, psi of the new V2C -> exchange slot of its row;
 //   phase 2 (lane = row k):    fold the row's exchange entries into the
 //            check-belief (max term, rest-of-sum, sign parity) -> LDS.
 // Two barriers per layer.  Workgroups hold lcm(Z, 64)/Z slots (Z = 96: two
@@ -23,6 +23,7 @@
 
 #include "internal.hpp"
 #include "phi.hpp"
+
 
 namespace cbp {
 namespace {
@@ -138,6 +139,16 @@ __device__ __forceinline__ const T *opaque_s(const T *p) {
     return p;
 }
 
+// Occupancy target (waves per SIMD) handed to the register allocator.  The
+// per-lane state is ~2 NB + E registers; measured on MI355X with the n=2304
+// code, CBP is fastest at 3 (168 VGPRs, a few spills outside the layer loop;
+// 2 leaves the SIMDs idle at the barriers, 4 spills in the loop), layered
+// min-sum at 4 and flooding min-sum at 3.
+template <int kAlgo>
+constexpr int waves_per_simd() {
+    return kAlgo == kLBPNMS ? 4 : 3;
+}
+
 // (x mod Z) for x in (-Z, 2Z)
 template <int Z>
 __device__ __forceinline__ int wrap(int x) {
@@ -146,7 +157,7 @@ __device__ __forceinline__ int wrap(int x) {
 }
 
 template <class G, int kAlgo>
-__global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G> A) {
+__global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) void qc_reg_kernel(QcArgs<G> A) {
     using TT = TabOf<G>;
     constexpr int MB = G::MB, NB = G::NB, Z = G::Z, E = count_edges<G>();
     constexpr int SL = slots_for<G>(), DCM = TT::T.dcmax;
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G>
     const int l = threadIdx.x - slot * Z;
     const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
 
-    // CBP: Q = latest V2C, PQ = phi(clamped Q) as folded.  NMS: Q = posterior
+    // CBP: Q = latest V2C, PQ = psi(clamped Q) as folded.  NMS: Q = posterior
     // Lambda, PQ = flooding accumulator of the new C2V messages.
     float Q[NB], PQ[NB], R[E];
     Mask xb = 0;
@@ -262,7 +273,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G>
                     // B2V (eq. equ_s4e18) from the latest check's belief
                     const float2 om = sOm[slot][rp * Z + wrap<Z>(lv - sh[E + e])];
                     const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-                    float rn = with_sign(phi32(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+                    float rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
                     if constexpr (TT::T.efirst[e]) {
                         rn = first ? 0.0f : rn;       // no latest check yet
                         R[ep] = first ? R[ep] : rn;   // commit R(c_j -> v) first
@@ -272,7 +283,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G>
                     const float lam = Q[b] + rn;      // eq. equ_s4e20
                     xb = (lam < 0.0f) ? (xb | (Mask(1) << b)) : (xb & ~(Mask(1) << b));
                     const float qn = lam - R[e];      // V2C, eq. equ_s4e19
-                    const float fq = phiq32(qn, a, lmax);
+                    const float fq = psiq_clamped(qn, a, lmax);
                     Q[b] = qn;
                     PQ[b] = fq;
                     sX[slot][j][wrap<Z>(lv - sh[e])] = with_sign(fq, qn < 0.0f);
@@ -347,7 +358,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G>
             constexpr int el = TT::T.elast[b], rl = TT::T.er[el];
             const float2 om = sOm[slot][rl * Z + wrap<Z>(opaque_v(l) - opaque_s(A.sht)[el])];
             const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-            return Q[b] + with_sign(phi32(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+            return Q[b] + with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
         };
         if constexpr (kAlgo == kCBP) {
             if (A.p.hd_mode == 1) {
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z) void qc_reg_kernel(QcArgs<G>
                         constexpr int r = rc;
                         const float2 om = sOm[slot][r * Z + l];
                         A.d.om[f * M + r * Z + l] =
-                            with_sign(phi32(abs_bits(om.x) + om.y), sign_bit(om.x));
+                            with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x));
                     });
             }
         }

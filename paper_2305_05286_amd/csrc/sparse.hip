@@ -31,9 +31,9 @@ __device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int6
 }
 
 // --------------------------------------------------------------------------
-// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (phi of the clamped Q folded
-// into the latest check), a2 = R[E], a3 = OmM[M] (max phi term, sign bit =
-// parity), a4 = OmS[M] (rest of the phi sum), xb = hard decisions [N].
+// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (psi = phi/ln2 of the clamped
+// Q folded into the latest check), a2 = R[E], a3 = OmM[M] (max psi term, sign
+// bit = parity), a4 = OmS[M] (rest of the psi sum), xb = hard decisions [N].
 // --------------------------------------------------------------------------
 __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v) {
     const int64_t S = w.stride;
@@ -42,7 +42,7 @@ __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, 
     const float q = w.a0[(int64_t)v * S + lf];
     const float om = w.a3[(int64_t)j * S + lf];
     const float d = excl_sum(abs_bits(om), w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf]);
-    return q + with_sign(phi32(d), sign_bit(om) ^ (q < 0.0f));
+    return q + with_sign(r_psi(d), sign_bit(om) ^ (q < 0.0f));
 }
 
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
@@ -87,13 +87,13 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                         const int64_t ij = (int64_t)g.pred_row[e] * S + lf;
                         const float om = OmM[ij];
                         const float dd = excl_sum(abs_bits(om), OmS[ij], PQ[iv]);
-                        rn = with_sign(phi32(dd), sign_bit(om) ^ (q < 0.0f));
+                        rn = with_sign(r_psi(dd), sign_bit(om) ^ (q < 0.0f));
                         R[(int64_t)g.pred_edge[e] * S + lf] = rn;
                     }
                     const float lam = q + rn;                 // eq. equ_s4e20
                     xb[iv] = lam < 0.0f;                      // eq. equ_s2e7
                     const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
-                    const float fq = phiq32(qn, p.a, p.lmax);
+                    const float fq = psiq_clamped(qn, p.a, p.lmax);
                     Q[iv] = qn;
                     PQ[iv] = fq;
                     fold(Mx, Sr, fq);                         // C2B, eq. equ_s4e21
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                     for (int i = 0; i < g.M; ++i) {
                         const float om = OmM[(int64_t)i * S + lf];
                         const float s = abs_bits(om) + OmS[(int64_t)i * S + lf];
-                        d.om[f * g.M + i] = with_sign(phi32(s), sign_bit(om));
+                        d.om[f * g.M + i] = with_sign(r_psi(s), sign_bit(om));
                     }
             }
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
