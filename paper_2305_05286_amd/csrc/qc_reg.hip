@@ -156,7 +156,10 @@ __device__ __forceinline__ int wrap(int x) {
     return x - ((x >= Z) ? Z : 0);
 }
 
-template <class G, int kAlgo>
+// kDbg: the instantiation that also serves hd_mode = 1 and the state dumps;
+// the production instantiation carries neither (cold code still costs
+// registers in a kernel this close to its register budget).
+template <class G, int kAlgo, bool kDbg>
 __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) void qc_reg_kernel(QcArgs<G> A) {
     using TT = TabOf<G>;
     constexpr int MB = G::MB, NB = G::NB, Z = G::Z, E = count_edges<G>();
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
             return Q[b] + with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
         };
-        if constexpr (kAlgo == kCBP) {
+        if constexpr (kAlgo == kCBP && kDbg) {
             if (A.p.hd_mode == 1) {
                 xb = 0;
                 static_for<0, NB>([&](auto bc) {
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 });
             }
         }
-        if (t == A.d.sweep && f < A.d.frames) {
+        if (kDbg && t == A.d.sweep && f < A.d.frames) {
             const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
@@ -419,7 +422,7 @@ int graph_shift_table(const int *shifts, int *out) {
     return 2 * E;
 }
 
-template <class G, int kAlgo>
+template <class G, int kAlgo, bool kDbg>
 hipError_t launch_graph(const int *sht, const float *llr, uint8_t *bits, int32_t *iters,
                         int64_t batch, int max_iter, const Params &p, const Dump &d,
                         int *counter, int device, hipStream_t s) {
@@ -440,7 +443,7 @@ hipError_t launch_graph(const int *sht, const float *llr, uint8_t *bits, int32_t
     if (cached_blocks[dev] == 0) {
         int per_cu = 0, cus = 0;
         hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(qc_reg_kernel<G, kAlgo>), threads, 0);
+            &per_cu, reinterpret_cast<const void *>(qc_reg_kernel<G, kAlgo, kDbg>), threads, 0);
         if (err != hipSuccess) return err;
         err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
         if (err != hipSuccess) return err;
@@ -450,7 +453,7 @@ hipError_t launch_graph(const int *sht, const float *llr, uint8_t *bits, int32_t
     const int blocks = (int)(need < cached_blocks[dev] ? need : cached_blocks[dev]);
     hipError_t err = launch_fill_i32(counter, 1, 0, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((qc_reg_kernel<G, kAlgo>), dim3(blocks), dim3(threads), 0, s, A);
+    hipLaunchKernelGGL((qc_reg_kernel<G, kAlgo, kDbg>), dim3(blocks), dim3(threads), 0, s, A);
     return hipGetLastError();
 }
 
@@ -478,15 +481,26 @@ hipError_t launch_qc_reg(int k, int algo, const int *sht, const float *llr, uint
                          const Dump &d, int *counter, int device, hipStream_t s) {
 #define CBP_LAUNCH(K, G)                                                                      \
     if (k == K) {                                                                             \
+        if (dbg) {                                                                            \
+            if (algo == kCBP)                                                                 \
+                return launch_graph<G, kCBP, true>(sht, llr, bits, iters, batch, max_iter, p, \
+                                                   d, counter, device, s);                    \
+            if (algo == kLBPNMS)                                                              \
+                return launch_graph<G, kLBPNMS, true>(sht, llr, bits, iters, batch, max_iter, \
+                                                      p, d, counter, device, s);              \
+            return launch_graph<G, kFBPNMS, true>(sht, llr, bits, iters, batch, max_iter, p,  \
+                                                  d, counter, device, s);                     \
+        }                                                                                     \
         if (algo == kCBP)                                                                     \
-            return launch_graph<G, kCBP>(sht, llr, bits, iters, batch, max_iter, p, d,     \
-                                         counter, device, s);                                 \
+            return launch_graph<G, kCBP, false>(sht, llr, bits, iters, batch, max_iter, p, d, \
+                                                counter, device, s);                          \
         if (algo == kLBPNMS)                                                                  \
-            return launch_graph<G, kLBPNMS>(sht, llr, bits, iters, batch, max_iter, p, d,  \
-                                            counter, device, s);                              \
-        return launch_graph<G, kFBPNMS>(sht, llr, bits, iters, batch, max_iter, p, d,      \
-                                        counter, device, s);                                  \
+            return launch_graph<G, kLBPNMS, false>(sht, llr, bits, iters, batch, max_iter, p, \
+                                                   d, counter, device, s);                    \
+        return launch_graph<G, kFBPNMS, false>(sht, llr, bits, iters, batch, max_iter, p, d,  \
+                                               counter, device, s);                           \
     }
+    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1;
     CBP_QC_GRAPHS(CBP_LAUNCH)
 #undef CBP_LAUNCH
     return hipErrorInvalidValue;
