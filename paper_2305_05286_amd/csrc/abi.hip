@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -42,6 +43,8 @@ struct DevTables {
     void *buf = nullptr;
     SparseDev g{};
     const int *qc_sht = nullptr;  // shift table of the register-resident kernel
+    QcStreamDev qs{};             // base structure of the streamed kernel
+    bool qs_ready = false;
 };
 
 }  // namespace
@@ -55,6 +58,7 @@ struct cbp_code {
     int mb = 0, nb = 0, Z = 0;
     std::vector<int> shifts;
     int qc_reg_id = -1;
+    int qE = 0, qdcmax = 0;  // base edges and max block-row degree (QC codes)
     std::mutex mu;
     DevTables dev[kMaxDevices];
 };
@@ -112,7 +116,7 @@ int check_csr(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_i
 double phi64(double x) { return std::log1p(2.0 / std::expm1(x)); }
 
 int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
-                  const int **qc_sht = nullptr) {
+                  const int **qc_sht = nullptr, const QcStreamDev **qs = nullptr) {
     cbp_code *c = const_cast<cbp_code *>(cc);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -129,7 +133,49 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             sht.resize(2 * (size_t)c->mb * c->nb);
             sht.resize(qc_reg_shift_table(c->qc_reg_id, c->shifts.data(), sht.data()));
         }
-        const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size();
+        // streamed-kernel edge table (QC codes)
+        std::vector<int> qt;
+        int qE = 0, dcmax = 0;
+        if (c->qc) {
+            const int mb = c->mb, nb = c->nb;
+            std::vector<int> rstart(mb + 1), eb, esh, er, ep, epr, epsh, efirst, elast(nb, -1);
+            for (int r = 0; r < mb; ++r) {
+                rstart[r] = (int)eb.size();
+                for (int b = 0; b < nb; ++b)
+                    if (c->shifts[r * nb + b] >= 0) {
+                        eb.push_back(b);
+                        esh.push_back(c->shifts[r * nb + b]);
+                        er.push_back(r);
+                    }
+                dcmax = std::max(dcmax, (int)eb.size() - rstart[r]);
+            }
+            qE = (int)eb.size();
+            rstart[mb] = qE;
+            ep.assign(qE, 0);
+            efirst.assign(qE, 0);
+            std::vector<int> firstq(nb, -1);
+            for (int e = 0; e < qE; ++e) {
+                const int b = eb[e];
+                if (firstq[b] < 0) {
+                    firstq[b] = e;
+                    efirst[e] = 1;
+                } else {
+                    ep[e] = elast[b];
+                }
+                elast[b] = e;
+            }
+            for (int b = 0; b < nb; ++b)
+                if (firstq[b] >= 0) ep[firstq[b]] = elast[b];
+            epr.resize(qE);
+            epsh.resize(qE);
+            for (int e = 0; e < qE; ++e) {
+                epr[e] = er[ep[e]];
+                epsh[e] = esh[ep[e]];
+            }
+            for (auto *v : {&rstart, &eb, &esh, &er, &ep, &epr, &epsh, &efirst, &elast})
+                qt.insert(qt.end(), v->begin(), v->end());
+        }
+        const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size() + qt.size();
         const size_t bytes = ints * 4 + (size_t)E + 64;
         void *buf = nullptr;
         e = hipMalloc(&buf, bytes);
@@ -149,6 +195,8 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         std::memcpy(p, c->last_edge.data(), 4 * (size_t)N);
         p += N;
         if (!sht.empty()) std::memcpy(p, sht.data(), 4 * sht.size());
+        p += sht.size();
+        if (!qt.empty()) std::memcpy(p, qt.data(), 4 * qt.size());
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy((char *)buf + ints * 4, c->first.data(), (size_t)E, hipMemcpyHostToDevice);
@@ -173,12 +221,41 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         t.g.last_edge = d;
         d += N;
         t.qc_sht = sht.empty() ? nullptr : d;
+        d += sht.size();
+        if (c->qc) {
+            QcStreamDev &q = t.qs;
+            q.Z = c->Z;
+            q.mb = c->mb;
+            q.nb = c->nb;
+            q.E = qE;
+            q.dcmax = dcmax;
+            q.rstart = d;
+            d += c->mb + 1;
+            q.eb = d;
+            d += qE;
+            q.esh = d;
+            d += qE;
+            q.er = d;
+            d += qE;
+            q.ep = d;
+            d += qE;
+            q.epr = d;
+            d += qE;
+            q.epsh = d;
+            d += qE;
+            q.efirst = d;
+            d += qE;
+            q.elast = d;
+            d += c->nb;
+            t.qs_ready = true;
+        }
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;
     }
     *g = &t.g;
     if (qc_sht) *qc_sht = t.qc_sht;
+    if (qs) *qs = t.qs_ready ? &t.qs : nullptr;
     return CBP_OK;
 }
 
@@ -204,11 +281,15 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     if (!std::isfinite(o->alpha) || !(o->alpha > 0.0f)) return fail(CBP_EINVAL, "alpha must be positive");
     if (o->dump_sweep < 0 || o->dump_frames < 0) return fail(CBP_EINVAL, "negative dump option");
     int k = o->kernel;
-    if (k == CBP_KERNEL_AUTO) k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : CBP_KERNEL_SPARSE;
+    const bool stream_ok = code->qc && code->Z <= 1024;
+    if (k == CBP_KERNEL_AUTO)
+        k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : stream_ok ? CBP_KERNEL_QC_STREAM : CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_QC_REG && code->qc_reg_id < 0)
         return fail(CBP_EUNSUPPORTED, "no register-resident kernel is compiled for this base pattern");
-    if (k == CBP_KERNEL_QC_STREAM) return fail(CBP_EUNSUPPORTED, "streamed QC kernel not available in this build");
-    if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_SPARSE) return fail(CBP_EINVAL, "unknown kernel %d", o->kernel);
+    if (k == CBP_KERNEL_QC_STREAM && !stream_ok)
+        return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024");
+    if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE)
+        return fail(CBP_EINVAL, "unknown kernel %d", o->kernel);
     r->kernel = k;
     r->p.lmax = o->lmax;
     r->p.a = (float)phi64((double)o->lmax);
@@ -237,8 +318,38 @@ int64_t sparse_chunk_frames(int algo, const SparseDev &g, int64_t batch) {
     return batch < n ? batch : n;
 }
 
-size_t needed_ws(int algo, const SparseDev &g, int kernel, int64_t batch) {
+// Streamed QC kernel: at most this many frames (slots) in flight per call,
+// which bounds its workspace (e.g. 2048 x 0.68 MB for the n = 26112 code).
+constexpr int64_t kStreamMaxSlots = 2048;
+
+QcStreamDev stream_shape_of(const cbp_code_t *c) {
+    QcStreamDev q{};
+    q.Z = c->Z;
+    q.mb = c->mb;
+    q.nb = c->nb;
+    q.E = c->qE;
+    q.dcmax = c->qdcmax;
+    return q;
+}
+
+int64_t stream_groups_cap(const QcStreamDev &q, int64_t batch) {
+    int slots, threads;
+    size_t lds;
+    qc_stream_shape(q, &slots, &threads, &lds);
+    const int64_t need = (batch + slots - 1) / slots;
+    const int64_t cap = std::max<int64_t>(1, kStreamMaxSlots / slots);
+    return std::min(need, cap);
+}
+
+size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch) {
     if (kernel == CBP_KERNEL_QC_REG) return 256;
+    if (kernel == CBP_KERNEL_QC_STREAM) {
+        const QcStreamDev q = stream_shape_of(code);
+        int slots, threads;
+        size_t lds;
+        qc_stream_shape(q, &slots, &threads, &lds);
+        return 256 + (size_t)stream_groups_cap(q, batch) * slots * qc_stream_slot_bytes(algo, q);
+    }
     return sparse_ws_bytes(algo, g, sparse_chunk_frames(algo, g, batch));
 }
 
@@ -256,10 +367,11 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     int dev = 0;
     const SparseDev *g = nullptr;
     const int *qc_sht = nullptr;
-    rc = ensure_device(code, &dev, &g, &qc_sht);
+    const QcStreamDev *qs = nullptr;
+    rc = ensure_device(code, &dev, &g, &qc_sht, &qs);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const size_t need = needed_ws(algo, *g, r.kernel, batch);
+    const size_t need = needed_ws(algo, code, *g, r.kernel, batch);
     void *ws = r.ws;
     bool own = false;
     if (!ws || r.ws_bytes < need) {
@@ -271,6 +383,11 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     if (r.kernel == CBP_KERNEL_QC_REG) {
         e = launch_qc_reg(code->qc_reg_id, algo, qc_sht, llr, bits, iters, batch,
                           max_iter, r.p, r.d, (int *)ws, dev, s);
+    } else if (r.kernel == CBP_KERNEL_QC_STREAM) {
+        const int64_t cap = stream_groups_cap(*qs, batch);
+        const int64_t groups = std::min<int64_t>(cap, qc_stream_groups(algo, *qs, dev));
+        e = launch_qc_stream(algo, *qs, llr, bits, iters, batch, max_iter, r.p, r.d, (int)groups,
+                             (char *)ws + 256, (int *)ws, s);
     } else {
         const int64_t chunk = sparse_chunk_frames(algo, *g, batch);
         SparseWs w = sparse_ws_carve(algo, *g, chunk, ws);
@@ -348,6 +465,12 @@ int cbp_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, c
     c->nb = nb;
     c->Z = Z;
     c->shifts.assign(shifts, shifts + mb * nb);
+    for (int r = 0; r < mb; ++r) {
+        int d = 0;
+        for (int b = 0; b < nb; ++b) d += shifts[r * nb + b] >= 0;
+        c->qE += d;
+        c->qdcmax = std::max(c->qdcmax, d);
+    }
     for (int k = 0; k < qc_reg_count(); ++k) {
         int kmb, knb, kz;
         const uint8_t *pat;
@@ -383,7 +506,9 @@ int cbp_code_info(const cbp_code_t *c, int32_t *M, int32_t *N, int64_t *E, int32
     if (N) *N = c->N;
     if (E) *E = c->E;
     if (Z) *Z = c->qc ? c->Z : 0;
-    if (kernels) *kernels = CBP_KERNEL_SPARSE | (c->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : 0);
+    if (kernels)
+        *kernels = CBP_KERNEL_SPARSE | (c->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : 0) |
+                   (c->qc && c->Z <= 1024 ? CBP_KERNEL_QC_STREAM : 0);
     return CBP_OK;
 }
 
@@ -416,7 +541,7 @@ int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch, c
     g.M = code->M;
     g.N = code->N;
     g.E = (int)code->E;
-    *bytes = batch == 0 ? 0 : needed_ws(decoder, g, r.kernel, batch);
+    *bytes = batch == 0 ? 0 : needed_ws(decoder, code, g, r.kernel, batch);
     return CBP_OK;
 }
 

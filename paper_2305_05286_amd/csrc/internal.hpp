@@ -50,6 +50,27 @@ hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 
+// ---- QC streamed kernels (any base matrix) ---------------------------------
+// Base structure in sweep order (block-row major, block-column ascending).
+struct QcStreamDev {
+    int Z, mb, nb, E, dcmax, slots;
+    const int *rstart;  // [mb+1] first edge of each block-row
+    const int *eb;      // [E] block-column of the edge
+    const int *esh;     // [E] circulant shift of the edge
+    const int *er;      // [E] block-row of the edge
+    const int *ep;      // [E] latest-check edge (cyclically previous block-row of the column)
+    const int *epr;     // [E] block-row of ep
+    const int *epsh;    // [E] shift of ep
+    const int *efirst;  // [E] 1 if the edge's block-row is the first of its column
+    const int *elast;   // [nb] last edge of each block-column
+};
+int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g);
+void qc_stream_shape(const QcStreamDev &g, int *slots, int *threads, size_t *lds);
+int qc_stream_groups(int algo, const QcStreamDev &g, int device);
+hipError_t launch_qc_stream(int algo, const QcStreamDev &g, const float *llr, uint8_t *bits,
+                            int32_t *iters, int64_t batch, int max_iter, const Params &p,
+                            const Dump &d, int groups, void *ws, int *counter, hipStream_t s);
+
 // ---- QC register-resident kernels (compiled base patterns) ----------------
 // Number of compiled base patterns and the pattern table for matching.
 int qc_reg_count();

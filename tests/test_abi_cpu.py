@@ -63,7 +63,8 @@ def test_code_handles(L):
     assert c2.has_kernel("qc_reg")
     # a base pattern that is not compiled in
     c3 = cbp.Code.from_workload(get_code("qc26112"))
-    assert not c3.has_kernel("qc_reg")
+    assert not c3.has_kernel("qc_reg") and c3.has_kernel("qc_stream")
+    assert not c1.has_kernel("qc_stream")
 
 
 @pytest.mark.parametrize("rp,ci,why", [
@@ -123,3 +124,9 @@ def test_workspace_sizes(L):
     assert cbp.workspace_size(c, "cbp", 0) == 0
     q = cbp.Code.from_workload(get_code("qc2304"))
     assert 0 < cbp.workspace_size(q, "cbp", 131072) <= 4096
+    # streamed kernel: one slot of state per frame in flight, at most 2048 slots
+    big = cbp.Code.from_workload(get_code("qc26112"))
+    per_slot = 4 * (2 * 26112 + 76800) + 8 * 17664 + 26112
+    n = cbp.workspace_size(big, "cbp", 4096)
+    assert 2048 * per_slot <= n <= 2048 * (per_slot + 512) + 256
+    assert cbp.workspace_size(big, "cbp", 3) <= 3 * (per_slot + 512) + 256

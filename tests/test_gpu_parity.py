@@ -59,6 +59,13 @@ CASES = [
     ("qc2304", "fbp_nms", "qc_reg", [2.0, 2.5], 4096, 50),
     ("qc_t64s", "lbp_nms", "qc_reg", [2.0], 2000, 30),
     ("qc_t16", "fbp_nms", "qc_reg", [2.0], 2000, 30),
+    ("qc26112", "cbp", "qc_stream", [1.0, 1.25], 256, 25),
+    ("qc26112", "lbp_nms", "qc_stream", [1.25], 256, 25),
+    ("qc26112", "fbp_nms", "qc_stream", [1.25], 256, 25),
+    ("qc2304", "cbp", "qc_stream", [1.75], 2000, 50),
+    ("qc2304", "lbp_nms", "qc_stream", [1.75], 2000, 50),
+    ("qc_t16", "cbp", "qc_stream", [1.5], 1001, 30),
+    ("qc_t64s", "fbp_nms", "qc_stream", [1.5], 1001, 30),
 ]
 
 
@@ -94,7 +101,9 @@ def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_
 
 MSG_CASES = [("reg36_n96", "cbp", "sparse"), ("qc2304", "cbp", "qc_reg"),
              ("qc_t64s", "cbp", "qc_reg"), ("qc2304", "lbp_nms", "qc_reg"),
-             ("qc2304", "fbp_nms", "qc_reg"), ("reg36_n96", "lbp_nms", "sparse")]
+             ("qc2304", "fbp_nms", "qc_reg"), ("reg36_n96", "lbp_nms", "sparse"),
+             ("qc_t64s", "cbp", "qc_stream"), ("qc2304", "cbp", "qc_stream"),
+             ("qc2304", "fbp_nms", "qc_stream")]
 
 
 @pytest.mark.parametrize("name,algo,kernel", MSG_CASES, ids=[f"{a}-{b}-{c}" for a, b, c in MSG_CASES])
@@ -152,12 +161,13 @@ def test_edge_cases(name):
     assert bits.shape == (0, code.N)
 
 
-@pytest.mark.parametrize("name", ["reg36_n96", "qc2304"])
-def test_flushed_decision_mode(name):
+@pytest.mark.parametrize("name,kernel", [("reg36_n96", "sparse"), ("qc2304", "qc_reg"),
+                                         ("qc2304", "qc_stream")])
+def test_flushed_decision_mode(name, kernel):
     code = get_code(name)
     llr, _ = make_frames(code, 2.0, 1000, key=(24,))
-    say(f"[gpu] hd_mode=1 {name}")
-    gb, gi = run_gpu(code, llr, 30, "cbp", hd_mode=1)
+    say(f"[gpu] hd_mode=1 {name} {kernel}")
+    gb, gi = run_gpu(code, llr, 30, "cbp", hd_mode=1, kernel=kernel)
     o = oracle.decode(code, llr, 30, "cbp", hd_mode=1)
     conv = o["iters"] < 30
     ok = agree(gb, gi, o["bits"], o["iters"])
@@ -169,7 +179,8 @@ def test_flushed_decision_mode(name):
     assert (gi == l["iters"]).mean() >= PARITY and ok[l["iters"] < 30].mean() >= PARITY
 
 
-@pytest.mark.parametrize("name,kernel", [("qc2304", "qc_reg"), ("reg36_n96", "sparse")])
+@pytest.mark.parametrize("name,kernel", [("qc2304", "qc_reg"), ("reg36_n96", "sparse"),
+                                         ("qc_t16", "qc_stream")])
 def test_symmetry_and_determinism(name, kernel):
     code = get_code(name)
     llr, _ = make_frames(code, 1.5, 512, key=(25,))
