@@ -22,7 +22,6 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -38,18 +37,10 @@ sys.path.insert(0, str(ROOT))
 METRIC = "decoded info Gbit/s at matched FER (CBP vs layered min-sum); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 DECODERS = ("cbp", "lbp_nms", "fbp_nms")
-KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        h.update((ROOT / p).read_bytes())
-    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(iters: np.ndarray, E: int, M: int, N: int) -> float:
@@ -91,6 +82,8 @@ def main() -> int:
                     help="decoders in the timed loop (the first one is `value`)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n=26112 code (streamed kernel) section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -104,6 +97,7 @@ def main() -> int:
     import torch
 
     from paper_2305_05286_amd import cbp
+    from paper_2305_05286_amd.profiling import kernel_hash
     from paper_2305_05286_amd.workload import get_code, make_frames
 
     dev = torch.device("cuda:0")
@@ -212,7 +206,7 @@ def main() -> int:
     ms = float(np.mean(head["times"]) * 1e3)
 
     # ---------------- 3. roofline of the CBP kernel --------------------------
-    roof = None
+    roof = roof_alu = None
     if "cbp" in results:
         r = results["cbp"]
         byts = algorithmic_bytes(r["iters"], code.E, code.M, code.N)
@@ -229,8 +223,54 @@ def main() -> int:
                 "kernel": "qc_reg_kernel<QcGraph0, CBP>",
                 "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(dur * 1e3, 4),
                 "frame_sweeps_per_s": float(r["iters"].sum()) / dur}
+        # The state of this kernel lives in VGPRs and LDS; its binding limit is
+        # VALU issue: SQ_INSTS_VALU per launch (committed counter pass) over the
+        # live launch duration, against 256 CU x 4 SIMD x 2.4 GHz / 4 cycles
+        # per wave64 instruction = 614.4 G wave-instructions/s.
+        vf = ROOT / "profiles" / "valu_qc2304_cbp.json"
+        if vf.exists():
+            v = json.loads(vf.read_text())
+            if v.get("kernel_hash") == kernel_hash() and abs(v.get("ebn0_db", -1) - op) < 1e-9:
+                peak = 256 * 4 * 2.4e9 / 4 / 1e9
+                a_ = v["valu_wave_instructions_per_launch"] / dur / 1e9
+                roof_alu = {"bound": "alu", "achieved": round(a_, 2), "peak": peak,
+                            "unit": "G VALU wave-instr/s", "frac": round(a_ / peak, 4),
+                            "valu_wave_instructions_per_launch": v["valu_wave_instructions_per_launch"]}
 
-    # ---------------- 4. CPU baseline: the FP64 oracle ----------------------
+    # ---------------- 4. the n=26112 code (streamed kernel) ----------------
+    large = None
+    if not args.no_large:
+        del llr_t, cw_t
+        torch.cuda.empty_cache()
+        big = get_code("qc26112")
+        bh = cbp.Code.from_workload(big)
+        nb_frames, big_snr, big_mi = 4096, 1.0, 25
+        bl, bc = make_frames(big, big_snr, nb_frames, key=(2026, 100))
+        bl_t = torch.from_numpy(bl).to(dev)
+        bc_t = torch.from_numpy(bc[:, :big.K]).to(dev)
+        bbits = torch.empty((nb_frames, big.N), dtype=torch.uint8, device=dev)
+        bit = torch.empty((nb_frames,), dtype=torch.int32, device=dev)
+        bws = torch.empty(cbp.workspace_size(bh, "cbp", nb_frames), dtype=torch.uint8, device=dev)
+        large = {"code": "qc26112 (46x68 base, Z=384, n=26112, k=8448)", "frames": nb_frames,
+                 "ebn0_db": big_snr, "max_iter": big_mi, "kernel": "qc_stream"}
+        for algo in DECODERS:
+            cbp.decode(bh, bl_t, big_mi, algo, out=(bbits, bit), workspace=bws)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+            for s_, e_ in ev:
+                s_.record(stream)
+                cbp.decode(bh, bl_t, big_mi, algo, out=(bbits, bit), workspace=bws)
+                e_.record(stream)
+            torch.cuda.synchronize()
+            t = float(np.median([s_.elapsed_time(e_) for s_, e_ in ev])) / 1e3
+            fer = (bbits[:, :big.K] != bc_t).any(dim=1).float().mean().item()
+            its = bit.double().mean().item()
+            large[algo] = {"ms": round(t * 1e3, 3), "gbps": round(nb_frames * big.K / t / 1e9, 3),
+                           "fer": fer, "mean_iters": round(its, 3),
+                           "edge_updates_per_s": nb_frames * its * big.E / t}
+            log(f"[bench] n=26112 {algo}: {t * 1e3:.2f} ms, FER {fer:.2e}, iters {its:.2f}")
+        del bl_t, bc_t, bbits, bit, bws
+
+    # ---------------- 5. CPU baseline: the FP64 oracle ----------------------
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -266,11 +306,13 @@ def main() -> int:
                    "code": "qc2304", "batch": B, "ebn0_db": op, "max_iter": MI,
                    "decoder": decoders[0], "parallelism": "single GPU"},
         "roofline": roof,
+        "roofline_alu": roof_alu,
         "cpu_baseline": cpu,
         "operating_point": {a: {"gbps": round(v["gbps"], 3), **{k: (round(x, 6) if isinstance(x, float) else x)
                                                                for k, x in v["quality"].items()}}
                             for a, v in results.items()},
         "matched_fer": matched or None,
+        "large_code": large,
         "sweep": {a: [{k: (round(x, 6) if isinstance(x, float) else x) for k, x in p.items()} for p in v]
                   for a, v in sweep.items()} if not args.no_sweep else None,
     }
