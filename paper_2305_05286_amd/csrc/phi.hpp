@@ -94,6 +94,17 @@ __device__ __forceinline__ float abs_bits(float v) {
     return __int_as_float(__float_as_int(v) & 0x7fffffff);
 }
 
+// Sign handling on raw bits.  The register-resident kernels canonicalise the
+// channel LLRs (L + 0.0f turns -0.0 into +0.0).  Then every V2C message and
+// posterior is nonzero or +0.0 (a sum can only be -0.0 if both terms are, and
+// x - x = +0.0), so its sign bit equals [value < 0] (sgn(0) = +1) and signs
+// combine with integer XOR.  (A C2V message can be -0.0 when its magnitude
+// underflows; added to anything it acts as +0.0.)
+__device__ __forceinline__ uint32_t fbits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ float or_sign(float mag, uint32_t sign_src) {
+    return __uint_as_float(__float_as_uint(mag) | (sign_src & 0x80000000u));
+}
+
 // psi-domain magnitude of a row belief (Mx = max term, S = rest) excluding f.
 __device__ __forceinline__ float excl_sum(float Mx, float S, float f) {
     return (f == Mx) ? S : Mx + (S - f);

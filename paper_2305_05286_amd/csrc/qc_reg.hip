@@ -167,10 +167,13 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     constexpr int64_t N = (int64_t)NB * Z;
     using Mask = std::conditional_t<(NB > 32), uint64_t, uint32_t>;
 
+    // The exchange buffer, the min-sum row states and the decision words are
+    // stored twice ([i] and [i + Z]) so that every rotated read (index i + s,
+    // 0 <= i, s < Z) needs no wrap-around.
     __shared__ float2 sOm[(kAlgo == kCBP) ? SL : 1][(kAlgo == kCBP) ? MB * Z : 1];
-    __shared__ float2 sRow[SL][Z];
-    __shared__ float sX[SL][DCM][Z];
-    __shared__ Mask sXB[SL][Z];
+    __shared__ float2 sRow[(kAlgo == kCBP) ? 1 : SL][(kAlgo == kCBP) ? 1 : 2 * Z];
+    __shared__ float sX[SL][DCM][2 * Z];
+    __shared__ Mask sXB[SL][2 * Z];
     __shared__ unsigned int sF[SL];
     __shared__ int sBad[2][SL];
     __shared__ int sAct[SL], sFresh[SL];
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         xb = 0;
         static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            const float v = A.llr[fr * N + b * Z + l];
+            const float v = A.llr[fr * N + b * Z + l] + 0.0f;  // -0.0 -> +0.0
             Q[b] = v;
             PQ[b] = 0.0f;
             if (v < 0.0f) xb |= Mask(1) << b;
@@ -209,6 +212,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         ++it;
         if (l == 0) sBad[pb][slot] = 0;
         sXB[slot][l] = xb;
+        sXB[slot][l + Z] = xb;
         __syncthreads();
         uint32_t bad = 0;
         static_for<0, MB>([&](auto rc) {
@@ -219,8 +223,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             static_for<TT::T.rstart[r], TT::T.rstart[r + 1]>([&](auto ec) {
                 constexpr int e = ec;
                 constexpr int b = TT::T.eb[e];
-                const int idx = wrap<Z>(lv + sh[e]);
-                par ^= (uint32_t)(sXB[slot][idx] >> b) & 1u;
+                par ^= (uint32_t)(sXB[slot][lv + sh[e]] >> b) & 1u;  // row l meets lane l + s
             });
             bad |= par;
         });
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     // B2V (eq. equ_s4e18) from the latest check's belief
                     const float2 om = sOm[slot][rp * Z + wrap<Z>(lv - sh[E + e])];
                     const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-                    float rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+                    float rn = or_sign(r_psi(dd), fbits(om.x) ^ fbits(Q[b]));
                     if constexpr (TT::T.efirst[e]) {
                         rn = first ? 0.0f : rn;       // no latest check yet
                         R[ep] = first ? R[ep] : rn;   // commit R(c_j -> v) first
@@ -284,41 +287,51 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                         R[ep] = rn;
                     }
                     const float lam = Q[b] + rn;      // eq. equ_s4e20
-                    xb = (lam < 0.0f) ? (xb | (Mask(1) << b)) : (xb & ~(Mask(1) << b));
+                    xb = (xb & ~(Mask(1) << b)) | (Mask(fbits(lam) >> 31) << b);  // [lam < 0]
                     const float qn = lam - R[e];      // V2C, eq. equ_s4e19
                     const float fq = psiq_clamped(qn, a, lmax);
                     Q[b] = qn;
                     PQ[b] = fq;
-                    sX[slot][j][wrap<Z>(lv - sh[e])] = with_sign(fq, qn < 0.0f);
+                    const float xv = or_sign(fq, fbits(qn));
+                    sX[slot][j][lv] = xv;
+                    sX[slot][j][lv + Z] = xv;
                 } else {
                     const float q = Q[b] - R[e];      // eq. equ_s2e10 / equ_s2e3
                     qk[j] = q;
-                    sX[slot][j][wrap<Z>(lv - sh[e])] =
-                        with_sign(__builtin_fminf(__builtin_fabsf(q), lmax), q < 0.0f);
+                    const float xv = or_sign(__builtin_fminf(__builtin_fabsf(q), lmax), fbits(q));
+                    sX[slot][j][lv] = xv;
+                    sX[slot][j][lv + Z] = xv;
                 }
             });
             __syncthreads();
-            // phase 2: lane = row l of this layer
+            // phase 2: lane = row l of this layer; its entry from block-column
+            // b_j was written by lane (l + s_j) mod Z
             {
-                bool par = false;
+                uint32_t par = 0;
+                const int lr = opaque_v(l);
+                const int *shr = opaque_s(A.sht);
                 if constexpr (kAlgo == kCBP) {
                     float Mx = 0.0f, Sr = 0.0f;
                     static_for<0, e1 - e0>([&](auto jc) {
-                        const float x = sX[slot][decltype(jc)::value][l];
-                        par ^= sign_bit(x);
+                        constexpr int j = jc;
+                        const float x = sX[slot][j][lr + shr[e0 + j]];
+                        par ^= fbits(x);
                         fold(Mx, Sr, abs_bits(x));    // C2B, eq. equ_s4e21
                     });
-                    sOm[slot][r * Z + l] = make_float2(with_sign(Mx, par), Sr);  // eq. equ_s4e23
+                    sOm[slot][r * Z + l] = make_float2(or_sign(Mx, par), Sr);  // eq. equ_s4e23
                 } else {
                     float m1 = __builtin_inff(), m2 = __builtin_inff();
                     static_for<0, e1 - e0>([&](auto jc) {
-                        const float x = sX[slot][decltype(jc)::value][l];
-                        par ^= sign_bit(x);
+                        constexpr int j = jc;
+                        const float x = sX[slot][j][lr + shr[e0 + j]];
+                        par ^= fbits(x);
                         const float ax = abs_bits(x);
                         m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
                         m1 = __builtin_fminf(m1, ax);
                     });
-                    sRow[slot][l] = make_float2(with_sign(m1, par), m2);
+                    const float2 rs = make_float2(or_sign(m1, par), m2);
+                    sRow[slot][l] = rs;
+                    sRow[slot][l + Z] = rs;
                 }
             }
             __syncthreads();
@@ -327,11 +340,10 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 static_for<e0, e1>([&](auto ec) {
                     constexpr int e = ec;
                     constexpr int b = TT::T.eb[e], j = e - e0;
-                    const float2 rw = sRow[slot][wrap<Z>(lv - sh[e])];
+                    const float2 rw = sRow[slot][lv + Z - sh[e]];
                     const float aq = __builtin_fminf(__builtin_fabsf(qk[j]), lmax);
                     const float m1 = abs_bits(rw.x);
-                    const float rn = with_sign(alpha * ((aq == m1) ? rw.y : m1),
-                                               sign_bit(rw.x) ^ (qk[j] < 0.0f));
+                    const float rn = or_sign(alpha * ((aq == m1) ? rw.y : m1), fbits(rw.x) ^ fbits(qk[j]));
                     R[e] = rn;
                     if constexpr (kAlgo == kLBPNMS) Q[b] = qk[j] + rn;  // eq. equ_s2e12
                     else PQ[b] += rn;
@@ -345,7 +357,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             if (f < A.batch)
                 static_for<0, NB>([&](auto bc) {
                     constexpr int b = bc;
-                    Q[b] = A.llr[f * N + b * Z + l] + PQ[b];  // eq. equ_s2e6
+                    Q[b] = (A.llr[f * N + b * Z + l] + 0.0f) + PQ[b];  // eq. equ_s2e6
                     PQ[b] = 0.0f;
                 });
         }
