@@ -12,10 +12,12 @@
 //     d >= 1/ln2: t * UR(t^2), t = 2^-d,      UR(s) ~ 2 atanh(sqrt s)/sqrt s
 //
 // (the large-argument forms are phi = ln((1+t)/(1-t)) = 2 atanh t with
-// t = e^-x).  Each polynomial is a degree-4 weighted least-squares fit for
-// relative error (max 1.1e-8 .. 1.3e-8 on its interval); with v_log_f32 and
-// v_exp_f32 the two functions stay within 1e-6 (psi_q, x <= 20) and 2e-7
-// (r_psi) relative of phi.  Large sums underflow to denormals / 0.
+// t = e^-x; the small-argument forms keep 1 - t from cancelling).  Each range
+// needs one hardware transcendental (v_log_f32 / v_exp_f32) and a degree-4
+// polynomial, a weighted least-squares fit for relative error (max 1.1e-8 ..
+// 1.3e-8 on its interval); the two functions stay within 1e-6 (psi_q,
+// x <= 20) and 2e-7 (r_psi) relative of phi.  Large sums underflow to
+// denormals / 0.
 //
 // Check-belief representation.  The paper keeps Omega in the LLR domain and
 // recovers an excluded C2V message through psi- (eq. equ_s4e13), i.e. a
@@ -39,16 +41,17 @@ constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kInvLn2 = 1.4426950408889634f;
 
+// Both ranges are evaluated and one result selected: the lanes of a wave
+// almost always straddle the split, and branching then costs more than the
+// second polynomial (measured on MI355X: 10% of the CBP kernel).
 __device__ __forceinline__ float psi_q(float x) {
-    if (x < 1.0f) {
-        const float y = x * x;
-        float p = 3.346680023241788e-05f;
-        p = __builtin_fmaf(p, y, -0.0004139537049923092f);
-        p = __builtin_fmaf(p, y, 0.004163993522524834f);
-        p = __builtin_fmaf(p, y, -0.041666336357593536f);
-        p = __builtin_fmaf(p, y, 0.5f);
-        return -__builtin_amdgcn_logf(x * p);
-    }
+    const float y = x * x;
+    float p = 3.346680023241788e-05f;
+    p = __builtin_fmaf(p, y, -0.0004139537049923092f);
+    p = __builtin_fmaf(p, y, 0.004163993522524834f);
+    p = __builtin_fmaf(p, y, -0.041666336357593536f);
+    p = __builtin_fmaf(p, y, 0.5f);
+    const float small = -__builtin_amdgcn_logf(x * p);
     const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
     const float s = t * t;
     float u = 0.42938604950904846f;
@@ -56,19 +59,17 @@ __device__ __forceinline__ float psi_q(float x) {
     u = __builtin_fmaf(u, s, 0.5777652859687805f);
     u = __builtin_fmaf(u, s, 0.961784839630127f);
     u = __builtin_fmaf(u, s, 2.885390043258667f);
-    return t * u;
+    return x < 1.0f ? small : t * u;
 }
 
 __device__ __forceinline__ float r_psi(float d) {
-    if (d < kInvLn2) {
-        const float u = d * d;
-        float p = 1.2360707160041784e-06f;
-        p = __builtin_fmaf(p, u, -3.182218279107474e-05f);
-        p = __builtin_fmaf(p, u, 0.0006662501837126911f);
-        p = __builtin_fmaf(p, u, -0.01387591753154993f);
-        p = __builtin_fmaf(p, u, 0.3465735912322998f);
-        return -kLn2 * __builtin_amdgcn_logf(d * p);
-    }
+    const float uu = d * d;
+    float p = 1.2360707160041784e-06f;
+    p = __builtin_fmaf(p, uu, -3.182218279107474e-05f);
+    p = __builtin_fmaf(p, uu, 0.0006662501837126911f);
+    p = __builtin_fmaf(p, uu, -0.01387591753154993f);
+    p = __builtin_fmaf(p, uu, 0.3465735912322998f);
+    const float small = -kLn2 * __builtin_amdgcn_logf(d * p);
     const float t = __builtin_amdgcn_exp2f(-d);
     const float s = t * t;
     float w = 0.2976277470588684f;
@@ -76,7 +77,7 @@ __device__ __forceinline__ float r_psi(float d) {
     w = __builtin_fmaf(w, s, 0.4004763960838318f);
     w = __builtin_fmaf(w, s, 0.6666584610939026f);
     w = __builtin_fmaf(w, s, 2.0f);
-    return t * w;
+    return d < kInvLn2 ? small : t * w;
 }
 
 // psi of a V2C magnitude clamped to [a, lmax], a = phi(lmax) (saturation of
