@@ -5,8 +5,9 @@ Workload: the n=2304 rate-1/2 QC code (12x24 base, Z=96), 131072 frames of
 synthetic BPSK/AWGN FP32 LLRs per batch, at most 50 sweeps, early stop on a
 zero syndrome.  The run
 
-  1. sweeps Eb/N0 = 1.0 .. 2.5 dB (step 0.25) with CBP and the layered and
-     flooding normalized min-sum baselines (alpha = 0.75) on identical inputs,
+  1. sweeps Eb/N0 = 1.0 .. 2.5 dB (step 0.25) with CBP (log-tanh and its
+     normalized min-sum form) and the layered and flooding normalized
+     min-sum baselines (alpha = 0.75) on identical inputs,
      recording FER / BER / mean sweeps / decoded info Gbit/s per point;
   2. interpolates, per decoder, the Eb/N0 where FER = 1e-2 and 1e-3
      (log-linear between points) and the Gbit/s there;
@@ -36,7 +37,7 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "decoded info Gbit/s at matched FER (CBP vs layered min-sum); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-DECODERS = ("cbp", "lbp_nms", "fbp_nms")
+DECODERS = ("cbp", "cbp_nms", "lbp_nms", "fbp_nms")
 
 
 def log(*a):
@@ -78,7 +79,7 @@ def main() -> int:
     ap.add_argument("--ebn0", type=float, default=None,
                     help="operating Eb/N0 of the timed loop (default: from the sweep)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Eb/N0 sweep")
-    ap.add_argument("--decoders", default="cbp,lbp_nms,fbp_nms",
+    ap.add_argument("--decoders", default="cbp,cbp_nms,lbp_nms,fbp_nms",
                     help="decoders in the timed loop (the first one is `value`)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")

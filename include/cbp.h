@@ -71,6 +71,9 @@ int cbp_code_info(const cbp_code_t *code, int32_t *M, int32_t *N, int64_t *E, in
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
 #define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, frame-interleaved state     */
 
+#define CBP_RULE_LOG_TANH 0
+#define CBP_RULE_MIN_SUM 1
+
 typedef struct {
     /* 0: stop when the syndrome H x^T = 0, tested on [L < 0] before the first
      *    sweep and after every sweep (default).  2: run exactly max_iter sweeps.
@@ -88,13 +91,21 @@ typedef struct {
     /* CBP_KERNEL_AUTO or one CBP_KERNEL_* value (CBP_EUNSUPPORTED if that
      * layout is unavailable for the code). */
     int32_t kernel;
+    /* cbp_decode check rule.  CBP_RULE_LOG_TANH (default): B2V and C2B with
+     * phi (eqs. equ_s4e18, equ_s4e21).  CBP_RULE_MIN_SUM: the normalized
+     * min-sum form of Sec. IV-D: each check keeps the two smallest clamped
+     * |Q| (unscaled) and the sign parity of its V2C messages; B2V = parity *
+     * sgn(Q) * alpha * (|Q| == min1 ? min2 : min1). */
+    int32_t check_rule;
     /* Debug dump of the decoder state after sweep dump_sweep (0 = off) for
      * frames [0, dump_frames): float32 device buffers, frame-major, each may
      * be NULL.  CBP: dump_q = latest V2C Q [N], dump_r = C2V R [E, CSR edge
-     * order], dump_om = check-belief Omega in the LLR domain [M], dump_lam =
-     * flushed posterior [N].  Min-sum baselines: dump_lam = posterior, dump_r
-     * = R.  Rows of frames that stopped before dump_sweep are not written. */
+     * order], dump_om = check-belief Omega in the LLR domain [M] (min-sum
+     * rule: parity * alpha * min1), dump_lam = flushed posterior [N].
+     * Min-sum baselines: dump_lam = posterior, dump_r = R.  Rows of frames
+     * that stopped before dump_sweep are not written. */
     int32_t dump_sweep;
+    int32_t reserved0;
     int64_t dump_frames;
     float *dump_q;
     float *dump_r;

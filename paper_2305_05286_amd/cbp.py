@@ -20,6 +20,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libcbp.so"
 
 CBP_OK, CBP_EINVAL, CBP_EUNSUPPORTED, CBP_EHIP, CBP_ENOMEM = 0, -1, -2, -3, -4
 KERNELS = {"auto": 0, "qc_reg": 1, "qc_stream": 2, "sparse": 4}
+RULES = {"log_tanh": 0, "min_sum": 1}
 DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2}
 
 # exported names declared in include/cbp.h
@@ -43,7 +44,9 @@ class Opts(ctypes.Structure):
         ("lmax", ctypes.c_float),
         ("alpha", ctypes.c_float),
         ("kernel", ctypes.c_int32),
+        ("check_rule", ctypes.c_int32),
         ("dump_sweep", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
         ("dump_frames", ctypes.c_int64),
         ("dump_q", ctypes.c_void_p),
         ("dump_r", ctypes.c_void_p),
@@ -143,11 +146,12 @@ class Code:
 
 
 def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=None,
-          workspace=None) -> Opts:
+          workspace=None, check_rule="log_tanh") -> Opts:
     o = Opts()
     lib().cbp_opts_default(ctypes.byref(o))
     o.stop_rule, o.hd_mode, o.lmax, o.alpha = stop_rule, hd_mode, lmax, alpha
     o.kernel = KERNELS[kernel]
+    o.check_rule = RULES[check_rule]
     if dump is not None:
         o.dump_sweep = dump["sweep"]
         o.dump_frames = dump["frames"]
@@ -162,7 +166,7 @@ def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=Non
 
 def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, lmax=20.0,
          alpha=0.75, kernel="auto", dump_sweep: int = 0, dump_frames: int = 0,
-         workspace=None, out=None, stream=None):
+         workspace=None, out=None, stream=None, check_rule="log_tanh"):
     import torch
     if not (isinstance(llr, torch.Tensor) and llr.is_cuda and llr.dtype == torch.float32):
         raise TypeError("llr must be a float32 CUDA tensor")
@@ -182,10 +186,12 @@ def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, 
         dump = {"sweep": dump_sweep, "frames": nd}
         dump["lam"] = torch.full((nd, code.N), float("nan"), device=dev)
         dump["r"] = torch.full((nd, code.E), float("nan"), device=dev)
-        if which == "cbp":
+        if which in ("cbp", "cbp_nms"):
             dump["q"] = torch.full((nd, code.N), float("nan"), device=dev)
             dump["om"] = torch.full((nd, code.M), float("nan"), device=dev)
-    o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace)
+    if which == "cbp_nms":  # CBP with the normalized min-sum rule of Sec. IV-D
+        which, check_rule = "cbp", "min_sum"
+    o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace, check_rule)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode",
                          "fbp_nms": "fbp_nms_decode"}[which])
@@ -214,6 +220,7 @@ def fbp_nms_decode(code: Code, llr, max_iter: int, **kw):
 
 
 def decode(code: Code, llr, max_iter: int, algo: str = "cbp", **kw):
+    """algo: "cbp", "cbp_nms" (cbp_decode with the min-sum rule), "lbp_nms", "fbp_nms"."""
     return _run(algo, code, llr, max_iter, **kw)
 
 

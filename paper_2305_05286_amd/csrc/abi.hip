@@ -275,10 +275,13 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
         return fail(CBP_EUNSUPPORTED, "stop_rule 1 (consecutive positive check-beliefs) is not implemented on the GPU");
     if (o->stop_rule != 0 && o->stop_rule != 2) return fail(CBP_EINVAL, "stop_rule must be 0 or 2");
     if (o->hd_mode != 0 && o->hd_mode != 1) return fail(CBP_EINVAL, "hd_mode must be 0 or 1");
-    if (o->hd_mode == 1 && algo != kCBP) return fail(CBP_EINVAL, "hd_mode 1 applies to cbp_decode only");
+    if (o->hd_mode == 1 && algo != kCBP && algo != kCBPNMS)
+        return fail(CBP_EINVAL, "hd_mode 1 applies to cbp_decode only");
     if (!(o->lmax > 0.0f) || !std::isfinite(o->lmax) || o->lmax > 80.0f)
         return fail(CBP_EINVAL, "lmax must be in (0, 80]");
     if (!std::isfinite(o->alpha) || !(o->alpha > 0.0f)) return fail(CBP_EINVAL, "alpha must be positive");
+    if (o->check_rule != CBP_RULE_LOG_TANH && o->check_rule != CBP_RULE_MIN_SUM)
+        return fail(CBP_EINVAL, "check_rule must be CBP_RULE_LOG_TANH or CBP_RULE_MIN_SUM");
     if (o->dump_sweep < 0 || o->dump_frames < 0) return fail(CBP_EINVAL, "negative dump option");
     int k = o->kernel;
     const bool stream_ok = code->qc && code->Z <= 1024;
@@ -514,7 +517,8 @@ int cbp_code_info(const cbp_code_t *c, int32_t *M, int32_t *N, int64_t *E, int32
 
 int cbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out, int32_t *iters_out,
                int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
-    return decode(kCBP, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
+    const int algo = (opts && opts->check_rule == CBP_RULE_MIN_SUM) ? kCBPNMS : kCBP;
+    return decode(algo, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
 }
 
 int lbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
@@ -533,6 +537,7 @@ int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch, c
                        size_t *bytes) {
     if (!code || !bytes) return fail(CBP_EINVAL, "code/bytes is NULL");
     if (decoder < 0 || decoder > 2) return fail(CBP_EINVAL, "decoder must be 0, 1 or 2");
+    if (decoder == 0 && opts && opts->check_rule == CBP_RULE_MIN_SUM) decoder = kCBPNMS;
     if (batch < 0) return fail(CBP_EINVAL, "batch < 0");
     Resolved r;
     int rc = resolve_opts(code, decoder, batch, opts, &r);

@@ -5,7 +5,9 @@
 
 namespace cbp {
 
-enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2 };
+// kCBPNMS: CBP with the normalized min-sum check rule (cbp_decode with
+// CBP_RULE_MIN_SUM).
+enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2, kCBPNMS = 3 };
 
 struct Params {
     float a;       // phi(lmax): lower clamp of |Q| entering phi

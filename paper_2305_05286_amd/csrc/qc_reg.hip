@@ -143,7 +143,7 @@ __device__ __forceinline__ const T *opaque_s(const T *p) {
 // per-lane state is ~2 NB + E registers; measured on MI355X with the n=2304
 // code, CBP is fastest at 3 (168 VGPRs, a few spills outside the layer loop;
 // 2 leaves the SIMDs idle at the barriers, 4 spills in the loop), layered
-// min-sum at 4 and flooding min-sum at 3.
+// min-sum at 4, flooding min-sum and min-sum CBP at 3.
 template <int kAlgo>
 constexpr int waves_per_simd() {
     return kAlgo == kLBPNMS ? 4 : 3;
@@ -166,12 +166,16 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     constexpr int SL = slots_for<G>(), DCM = TT::T.dcmax;
     constexpr int64_t N = (int64_t)NB * Z;
     using Mask = std::conditional_t<(NB > 32), uint64_t, uint32_t>;
+    // CBP in either check rule keeps check-beliefs; every rule but log-tanh
+    // CBP folds a row into (min1, min2, parity)
+    constexpr bool kBelief = kAlgo == kCBP || kAlgo == kCBPNMS;
+    constexpr bool kMinRow = kAlgo != kCBP;
 
     // The exchange buffer, the min-sum row states and the decision words are
     // stored twice ([i] and [i + Z]) so that every rotated read (index i + s,
     // 0 <= i, s < Z) needs no wrap-around.
-    __shared__ float2 sOm[(kAlgo == kCBP) ? SL : 1][(kAlgo == kCBP) ? MB * Z : 1];
-    __shared__ float2 sRow[(kAlgo == kCBP) ? 1 : SL][(kAlgo == kCBP) ? 1 : 2 * Z];
+    __shared__ float2 sOm[kBelief ? SL : 1][kBelief ? MB * Z : 1];
+    __shared__ float2 sRow[kBelief ? 1 : SL][kBelief ? 1 : 2 * Z];
     __shared__ float sX[SL][DCM][2 * Z];
     __shared__ Mask sXB[SL][2 * Z];
     __shared__ unsigned int sF[SL];
@@ -274,12 +278,19 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             static_for<e0, e1>([&](auto ec) {
                 constexpr int e = ec;
                 constexpr int b = TT::T.eb[e], j = e - e0;
-                if constexpr (kAlgo == kCBP) {
+                if constexpr (kBelief) {
                     constexpr int ep = TT::T.epred[e], rp = TT::T.er[ep];
                     // B2V (eq. equ_s4e18) from the latest check's belief
                     const float2 om = sOm[slot][rp * Z + wrap<Z>(lv - sh[E + e])];
-                    const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-                    float rn = or_sign(r_psi(dd), fbits(om.x) ^ fbits(Q[b]));
+                    float rn;
+                    if constexpr (kAlgo == kCBP) {
+                        const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
+                        rn = or_sign(r_psi(dd), fbits(om.x) ^ fbits(Q[b]));
+                    } else {  // min-sum rule (eq. equ_s4e18xx)
+                        const float aq = __builtin_fminf(__builtin_fabsf(Q[b]), lmax);
+                        const float m1 = abs_bits(om.x);
+                        rn = or_sign(alpha * ((aq == m1) ? om.y : m1), fbits(om.x) ^ fbits(Q[b]));
+                    }
                     if constexpr (TT::T.efirst[e]) {
                         rn = first ? 0.0f : rn;       // no latest check yet
                         R[ep] = first ? R[ep] : rn;   // commit R(c_j -> v) first
@@ -289,9 +300,14 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     const float lam = Q[b] + rn;      // eq. equ_s4e20
                     xb = (xb & ~(Mask(1) << b)) | (Mask(fbits(lam) >> 31) << b);  // [lam < 0]
                     const float qn = lam - R[e];      // V2C, eq. equ_s4e19
-                    const float fq = psiq_clamped(qn, a, lmax);
+                    float fq;
+                    if constexpr (kAlgo == kCBP) {
+                        fq = psiq_clamped(qn, a, lmax);
+                        PQ[b] = fq;
+                    } else {
+                        fq = __builtin_fminf(__builtin_fabsf(qn), lmax);
+                    }
                     Q[b] = qn;
-                    PQ[b] = fq;
                     const float xv = or_sign(fq, fbits(qn));
                     sX[slot][j][lv] = xv;
                     sX[slot][j][lv + Z] = xv;
@@ -310,7 +326,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 uint32_t par = 0;
                 const int lr = opaque_v(l);
                 const int *shr = opaque_s(A.sht);
-                if constexpr (kAlgo == kCBP) {
+                if constexpr (!kMinRow) {
                     float Mx = 0.0f, Sr = 0.0f;
                     static_for<0, e1 - e0>([&](auto jc) {
                         constexpr int j = jc;
@@ -330,12 +346,16 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                         m1 = __builtin_fminf(m1, ax);
                     });
                     const float2 rs = make_float2(or_sign(m1, par), m2);
-                    sRow[slot][l] = rs;
-                    sRow[slot][l + Z] = rs;
+                    if constexpr (kBelief) {
+                        sOm[slot][r * Z + l] = rs;  // C2B, eq. equ_s4e21xx
+                    } else {
+                        sRow[slot][l] = rs;
+                        sRow[slot][l + Z] = rs;
+                    }
                 }
             }
             __syncthreads();
-            if constexpr (kAlgo != kCBP) {
+            if constexpr (!kBelief) {
                 // phase 3: lane = variable, normalized min-sum C2V
                 static_for<e0, e1>([&](auto ec) {
                     constexpr int e = ec;
@@ -361,7 +381,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     PQ[b] = 0.0f;
                 });
         }
-        if constexpr (kAlgo != kCBP) {
+        if constexpr (!kBelief) {
             xb = 0;
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
@@ -372,10 +392,16 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             constexpr int b = bc;
             constexpr int el = TT::T.elast[b], rl = TT::T.er[el];
             const float2 om = sOm[slot][rl * Z + wrap<Z>(opaque_v(l) - opaque_s(A.sht)[el])];
-            const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-            return Q[b] + with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+            if constexpr (kAlgo == kCBP) {
+                const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
+                return Q[b] + with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+            } else {
+                const float aq = __builtin_fminf(__builtin_fabsf(Q[b]), lmax);
+                const float m1 = abs_bits(om.x);
+                return Q[b] + with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (Q[b] < 0.0f));
+            }
         };
-        if constexpr (kAlgo == kCBP && kDbg) {
+        if constexpr (kBelief && kDbg) {
             if (A.p.hd_mode == 1) {
                 xb = 0;
                 static_for<0, NB>([&](auto bc) {
@@ -387,7 +413,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
-                if constexpr (kAlgo == kCBP) {
+                if constexpr (kBelief) {
                     if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b];
                     if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(bc);
                 } else {
@@ -401,13 +427,14 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     const int k = wrap<Z>(l - A.sht[e]);
                     A.d.r[f * Etot + TT::T.csr_off[r] + k * TT::T.dc[r] + TT::T.ejpos[e]] = R[e];
                 });
-            if constexpr (kAlgo == kCBP) {
+            if constexpr (kBelief) {
                 if (A.d.om)
                     static_for<0, MB>([&](auto rc) {
                         constexpr int r = rc;
                         const float2 om = sOm[slot][r * Z + l];
                         A.d.om[f * M + r * Z + l] =
-                            with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x));
+                            kAlgo == kCBP ? with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x))
+                                          : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
                     });
             }
         }
@@ -491,30 +518,32 @@ int qc_reg_shift_table(int k, const int *shifts, int *out) {
 hipError_t launch_qc_reg(int k, int algo, const int *sht, const float *llr, uint8_t *bits,
                          int32_t *iters, int64_t batch, int max_iter, const Params &p,
                          const Dump &d, int *counter, int device, hipStream_t s) {
+#define CBP_LAUNCH_ALGO(G, DBG)                                                               \
+    switch (algo) {                                                                           \
+    case kCBP:                                                                                \
+        return launch_graph<G, kCBP, DBG>(sht, llr, bits, iters, batch, max_iter, p, d,       \
+                                          counter, device, s);                                \
+    case kLBPNMS:                                                                             \
+        return launch_graph<G, kLBPNMS, DBG>(sht, llr, bits, iters, batch, max_iter, p, d,    \
+                                             counter, device, s);                             \
+    case kFBPNMS:                                                                             \
+        return launch_graph<G, kFBPNMS, DBG>(sht, llr, bits, iters, batch, max_iter, p, d,    \
+                                             counter, device, s);                             \
+    default:                                                                                  \
+        return launch_graph<G, kCBPNMS, DBG>(sht, llr, bits, iters, batch, max_iter, p, d,    \
+                                             counter, device, s);                             \
+    }
 #define CBP_LAUNCH(K, G)                                                                      \
     if (k == K) {                                                                             \
         if (dbg) {                                                                            \
-            if (algo == kCBP)                                                                 \
-                return launch_graph<G, kCBP, true>(sht, llr, bits, iters, batch, max_iter, p, \
-                                                   d, counter, device, s);                    \
-            if (algo == kLBPNMS)                                                              \
-                return launch_graph<G, kLBPNMS, true>(sht, llr, bits, iters, batch, max_iter, \
-                                                      p, d, counter, device, s);              \
-            return launch_graph<G, kFBPNMS, true>(sht, llr, bits, iters, batch, max_iter, p,  \
-                                                  d, counter, device, s);                     \
+            CBP_LAUNCH_ALGO(G, true)                                                          \
         }                                                                                     \
-        if (algo == kCBP)                                                                     \
-            return launch_graph<G, kCBP, false>(sht, llr, bits, iters, batch, max_iter, p, d, \
-                                                counter, device, s);                          \
-        if (algo == kLBPNMS)                                                                  \
-            return launch_graph<G, kLBPNMS, false>(sht, llr, bits, iters, batch, max_iter, p, \
-                                                   d, counter, device, s);                    \
-        return launch_graph<G, kFBPNMS, false>(sht, llr, bits, iters, batch, max_iter, p, d,  \
-                                               counter, device, s);                           \
+        CBP_LAUNCH_ALGO(G, false)                                                             \
     }
     const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1;
     CBP_QC_GRAPHS(CBP_LAUNCH)
 #undef CBP_LAUNCH
+#undef CBP_LAUNCH_ALGO
     return hipErrorInvalidValue;
 }
 

@@ -55,13 +55,14 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
     int *sAct = sFlags + 3 * SL;                                    // [SL]
     int *sFresh = sFlags + 4 * SL;                                  // [SL]
 
+    constexpr bool kBelief = kAlgo == kCBP || kAlgo == kCBPNMS;
     const int64_t gslot = (int64_t)blockIdx.x * SL + slot;
     char *base = A.ws + gslot * A.ws_stride;
     float *Q = reinterpret_cast<float *>(base);
     float *PQ = Q + N;
     float *R = PQ + N;
     float2 *OM = reinterpret_cast<float2 *>(base + ((4 * (2 * N + (int64_t)E * Z) + 7) & ~(int64_t)7));
-    uint8_t *XB = reinterpret_cast<uint8_t *>(OM + (kAlgo == kCBP ? (int64_t)MB * Z : 0));  // slot end = qc_stream_slot_bytes
+    uint8_t *XB = reinterpret_cast<uint8_t *>(OM + (kBelief ? (int64_t)MB * Z : 0));  // slot end = qc_stream_slot_bytes
 
     const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
 
@@ -139,23 +140,34 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
                 const int iv = b * Z + l;
                 int kc = l - g.esh[e];
                 kc += (kc < 0) ? Z : 0;
-                if constexpr (kAlgo == kCBP) {
+                if constexpr (kBelief) {
                     const float q = Q[iv];
                     float rn = 0.0f;
                     if (!(first && g.efirst[e])) {
                         int kp = l - g.epsh[e];
                         kp += (kp < 0) ? Z : 0;
                         const float2 om = OM[g.epr[e] * Z + kp];
-                        const float dd = excl_sum(abs_bits(om.x), om.y, PQ[iv]);
-                        rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+                        if constexpr (kAlgo == kCBP) {
+                            const float dd = excl_sum(abs_bits(om.x), om.y, PQ[iv]);
+                            rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+                        } else {
+                            const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
+                            const float m1 = abs_bits(om.x);
+                            rn = with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
+                        }
                         R[(int64_t)g.ep[e] * Z + l] = rn;  // commit R(c_j -> v) first
                     }
                     const float lam = q + rn;
                     XB[iv] = lam < 0.0f;
                     const float qn = lam - R[(int64_t)e * Z + l];
-                    const float fq = psiq_clamped(qn, a, lmax);
+                    float fq;
+                    if constexpr (kAlgo == kCBP) {
+                        fq = psiq_clamped(qn, a, lmax);
+                        PQ[iv] = fq;
+                    } else {
+                        fq = __builtin_fminf(__builtin_fabsf(qn), lmax);
+                    }
                     Q[iv] = qn;
-                    PQ[iv] = fq;
                     sX[(e - e0) * Z + kc] = with_sign(fq, qn < 0.0f);
                 } else {
                     const float q = Q[iv] - R[(int64_t)e * Z + l];
@@ -183,11 +195,12 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
                         m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
                         m1 = __builtin_fminf(m1, ax);
                     }
-                    sRow[l] = make_float2(with_sign(m1, par), m2);
+                    if constexpr (kBelief) OM[r * Z + l] = make_float2(with_sign(m1, par), m2);
+                    else sRow[l] = make_float2(with_sign(m1, par), m2);
                 }
             }
             __syncthreads();
-            if constexpr (kAlgo != kCBP) {
+            if constexpr (!kBelief) {
                 // phase 3: lane = variable
                 for (int e = e0; e < e1; ++e) {
                     const int b = g.eb[e];
@@ -208,7 +221,7 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
         ++t;
 
         // ---------------- end of sweep ------------------------------------
-        if constexpr (kAlgo != kCBP) {
+        if constexpr (!kBelief) {
             for (int b = 0; b < NB; ++b) {
                 const int iv = b * Z + l;
                 float lam = Q[iv];
@@ -226,17 +239,23 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
             k += (k < 0) ? Z : 0;
             const float2 om = OM[g.er[el] * Z + k];
             const float q = Q[b * Z + l];
-            const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b * Z + l]);
-            return q + with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+            if constexpr (kAlgo == kCBP) {
+                const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b * Z + l]);
+                return q + with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+            } else {
+                const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
+                const float m1 = abs_bits(om.x);
+                return q + with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
+            }
         };
-        if constexpr (kAlgo == kCBP) {
+        if constexpr (kBelief) {
             if (A.p.hd_mode == 1)
                 for (int b = 0; b < NB; ++b) XB[b * Z + l] = flushed(b) < 0.0f;
         }
         if (t == A.d.sweep && f < A.d.frames) {
             const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
             for (int b = 0; b < NB; ++b) {
-                if constexpr (kAlgo == kCBP) {
+                if constexpr (kBelief) {
                     if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b * Z + l];
                     if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(b);
                 } else {
@@ -252,12 +271,13 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
                     A.d.r[f * Etot + (int64_t)g.rstart[r] * Z + (int64_t)k * dc + (e - g.rstart[r])] =
                         R[(int64_t)e * Z + l];
                 }
-            if constexpr (kAlgo == kCBP) {
+            if constexpr (kBelief) {
                 if (A.d.om)
                     for (int r = 0; r < MB; ++r) {
                         const float2 om = OM[r * Z + l];
                         A.d.om[f * M + (int64_t)r * Z + l] =
-                            with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x));
+                            kAlgo == kCBP ? with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x))
+                                          : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
                     }
             }
         }
@@ -278,7 +298,7 @@ int slots_per_group(int Z) {
 int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g) {
     const int64_t N = (int64_t)g.nb * g.Z;
     int64_t b = round_up(4 * (2 * N + (int64_t)g.E * g.Z), 8);
-    if (algo == kCBP) b += 8LL * g.mb * g.Z;
+    if (algo == kCBP || algo == kCBPNMS) b += 8LL * g.mb * g.Z;
     b += N;
     return round_up(b, 256);
 }
@@ -296,9 +316,10 @@ int qc_stream_groups(int algo, const QcStreamDev &g, int device) {
     size_t lds;
     qc_stream_shape(g, &slots, &threads, &lds);
     int per_cu = 0, cus = 0;
-    const void *fn = algo == kCBP ? reinterpret_cast<const void *>(qc_stream_kernel<kCBP>)
+    const void *fn = algo == kCBP      ? reinterpret_cast<const void *>(qc_stream_kernel<kCBP>)
                      : algo == kLBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kLBPNMS>)
-                                       : reinterpret_cast<const void *>(qc_stream_kernel<kFBPNMS>);
+                     : algo == kFBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kFBPNMS>)
+                                       : reinterpret_cast<const void *>(qc_stream_kernel<kCBPNMS>);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 1;
     return (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
@@ -329,8 +350,10 @@ hipError_t launch_qc_stream(int algo, const QcStreamDev &g, const float *llr, ui
         hipLaunchKernelGGL(qc_stream_kernel<kCBP>, dim3(groups), dim3(threads), lds, s, A);
     else if (algo == kLBPNMS)
         hipLaunchKernelGGL(qc_stream_kernel<kLBPNMS>, dim3(groups), dim3(threads), lds, s, A);
-    else
+    else if (algo == kFBPNMS)
         hipLaunchKernelGGL(qc_stream_kernel<kFBPNMS>, dim3(groups), dim3(threads), lds, s, A);
+    else
+        hipLaunchKernelGGL(qc_stream_kernel<kCBPNMS>, dim3(groups), dim3(threads), lds, s, A);
     return hipGetLastError();
 }
 

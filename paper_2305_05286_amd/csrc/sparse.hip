@@ -35,16 +35,30 @@ __device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int6
 // Q folded into the latest check), a2 = R[E], a3 = OmM[M] (max psi term, sign
 // bit = parity), a4 = OmS[M] (rest of the psi sum), xb = hard decisions [N].
 // --------------------------------------------------------------------------
-__device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v) {
+// C2V of a check recovered from its belief (om = max term or min1 with the
+// parity in its sign bit, os = rest of the sum or min2), excluding q.
+template <bool kMin>
+__device__ float b2v(float om, float os, float pq, float q, const Params &p) {
+    if constexpr (!kMin) {
+        return with_sign(r_psi(excl_sum(abs_bits(om), os, pq)), sign_bit(om) ^ (q < 0.0f));
+    } else {
+        const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+        const float m1 = abs_bits(om);
+        return with_sign(p.alpha * ((aq == m1) ? os : m1), sign_bit(om) ^ (q < 0.0f));
+    }
+}
+
+template <bool kMin>
+__device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v, const Params &p) {
     const int64_t S = w.stride;
     const int e = g.last_edge[v];
     const int j = g.edge_row[e];
     const float q = w.a0[(int64_t)v * S + lf];
-    const float om = w.a3[(int64_t)j * S + lf];
-    const float d = excl_sum(abs_bits(om), w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf]);
-    return q + with_sign(r_psi(d), sign_bit(om) ^ (q < 0.0f));
+    return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
 }
 
+// kMin: the normalized min-sum check rule (OmM = min1 | parity, OmS = min2).
+template <bool kMin>
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
@@ -74,7 +88,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
         if (active) {
             // Step 2: check-nodes in index order
             for (int i = 0; i < g.M; ++i) {
-                float Mx = 0.0f, Sr = 0.0f;
+                float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
                 bool par = false;
                 for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
                     const int v = g.col_idx[e];
@@ -85,37 +99,42 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                         // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
                         // from its belief, then committed to R(c_j -> v) first.
                         const int64_t ij = (int64_t)g.pred_row[e] * S + lf;
-                        const float om = OmM[ij];
-                        const float dd = excl_sum(abs_bits(om), OmS[ij], PQ[iv]);
-                        rn = with_sign(r_psi(dd), sign_bit(om) ^ (q < 0.0f));
+                        rn = b2v<kMin>(OmM[ij], OmS[ij], PQ[iv], q, p);
                         R[(int64_t)g.pred_edge[e] * S + lf] = rn;
                     }
                     const float lam = q + rn;                 // eq. equ_s4e20
                     xb[iv] = lam < 0.0f;                      // eq. equ_s2e7
                     const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
-                    const float fq = psiq_clamped(qn, p.a, p.lmax);
                     Q[iv] = qn;
-                    PQ[iv] = fq;
-                    fold(Mx, Sr, fq);                         // C2B, eq. equ_s4e21
+                    if constexpr (!kMin) {
+                        const float fq = psiq_clamped(qn, p.a, p.lmax);
+                        PQ[iv] = fq;
+                        fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
+                    } else {                                  // eq. equ_s4e21xx
+                        const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
+                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
+                        Mx = __builtin_fminf(Mx, aq);
+                    }
                     par ^= (qn < 0.0f);
                 }
                 OmM[(int64_t)i * S + lf] = with_sign(Mx, par);  // eq. equ_s4e23
                 OmS[(int64_t)i * S + lf] = Sr;
             }
             if (p.hd_mode == 1)
-                for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed(g, w, lf, v) < 0.0f;
+                for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed<kMin>(g, w, lf, v, p) < 0.0f;
             if (t == d.sweep && f < d.frames) {
                 for (int v = 0; v < g.N; ++v) {
                     if (d.q) d.q[f * g.N + v] = Q[(int64_t)v * S + lf];
-                    if (d.lam) d.lam[f * g.N + v] = cbp_flushed(g, w, lf, v);
+                    if (d.lam) d.lam[f * g.N + v] = cbp_flushed<kMin>(g, w, lf, v, p);
                 }
                 if (d.r)
                     for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf];
                 if (d.om)
                     for (int i = 0; i < g.M; ++i) {
                         const float om = OmM[(int64_t)i * S + lf];
-                        const float s = abs_bits(om) + OmS[(int64_t)i * S + lf];
-                        d.om[f * g.M + i] = with_sign(r_psi(s), sign_bit(om));
+                        d.om[f * g.M + i] =
+                            kMin ? with_sign(p.alpha * abs_bits(om), sign_bit(om))
+                                 : with_sign(r_psi(abs_bits(om) + OmS[(int64_t)i * S + lf]), sign_bit(om));
                     }
             }
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
@@ -229,7 +248,8 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames) {
     const int64_t S = round_up(frames, kWave);
-    int64_t floats = algo == kCBP ? (2LL * g.N + g.E + 2LL * g.M) : (2LL * g.N + g.E);
+    const bool belief = algo == kCBP || algo == kCBPNMS;
+    int64_t floats = belief ? (2LL * g.N + g.E + 2LL * g.M) : (2LL * g.N + g.E);
     // each array starts on a 256-byte boundary
     return (size_t)(floats * S * 4 + (int64_t)g.N * S + 8 * 256);
 }
@@ -244,7 +264,7 @@ SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *bas
         p += round_up(bytes, 256);
         return r;
     };
-    if (algo == kCBP) {
+    if (algo == kCBP || algo == kCBPNMS) {
         w.a0 = (float *)take(4LL * g.N * S);
         w.a1 = (float *)take(4LL * g.N * S);
         w.a2 = (float *)take(4LL * g.E * S);
@@ -264,7 +284,10 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
                          const SparseWs &ws, const Dump &d, hipStream_t s) {
     const dim3 grid((unsigned)((nf + kWave - 1) / kWave)), block(kWave);
     if (algo == kCBP)
-        hipLaunchKernelGGL(cbp_sparse_kernel, grid, block, 0, s, g, llr, bits, iters, f0, nf,
+        hipLaunchKernelGGL(cbp_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, f0, nf,
+                           max_iter, p, ws, d);
+    else if (algo == kCBPNMS)
+        hipLaunchKernelGGL(cbp_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, f0, nf,
                            max_iter, p, ws, d);
     else if (algo == kLBPNMS)
         hipLaunchKernelGGL(nms_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, f0,

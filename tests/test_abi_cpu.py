@@ -40,8 +40,9 @@ def test_opts_defaults_and_layout(L):
     L.cbp_opts_default(ctypes.byref(o))
     assert (o.stop_rule, o.hd_mode, o.kernel, o.dump_sweep) == (0, 0, 0, 0)
     assert o.lmax == 20.0 and o.alpha == 0.75
-    # 6 x 4-byte fields, int64, 6 pointer-sized fields (C natural alignment)
-    assert ctypes.sizeof(cbp.Opts) == 80 and cbp.Opts.dump_frames.offset == 24
+    # 8 x 4-byte fields, int64, 6 pointer-sized fields (C natural alignment)
+    assert ctypes.sizeof(cbp.Opts) == 88 and cbp.Opts.dump_frames.offset == 32
+    assert o.check_rule == 0
 
 
 def test_strerror_and_version(L):

@@ -66,6 +66,13 @@ CASES = [
     ("qc2304", "lbp_nms", "qc_stream", [1.75], 2000, 50),
     ("qc_t16", "cbp", "qc_stream", [1.5], 1001, 30),
     ("qc_t64s", "fbp_nms", "qc_stream", [1.5], 1001, 30),
+    ("qc2304", "cbp_nms", "qc_reg", [1.75, 2.25], 4096, 50),
+    ("qc2304_alt", "cbp_nms", "qc_reg", [2.0], 2001, 50),
+    ("qc_t64s", "cbp_nms", "qc_reg", [1.5], 1999, 30),
+    ("qc_t16", "cbp_nms", "qc_reg", [1.5], 1001, 30),
+    ("reg36_n96", "cbp_nms", "sparse", [2.0, 3.0], 2000, 30),
+    ("qc26112", "cbp_nms", "qc_stream", [1.0], 256, 25),
+    ("qc2304", "cbp_nms", "qc_stream", [1.75], 1000, 50),
 ]
 
 
@@ -103,7 +110,9 @@ MSG_CASES = [("reg36_n96", "cbp", "sparse"), ("qc2304", "cbp", "qc_reg"),
              ("qc_t64s", "cbp", "qc_reg"), ("qc2304", "lbp_nms", "qc_reg"),
              ("qc2304", "fbp_nms", "qc_reg"), ("reg36_n96", "lbp_nms", "sparse"),
              ("qc_t64s", "cbp", "qc_stream"), ("qc2304", "cbp", "qc_stream"),
-             ("qc2304", "fbp_nms", "qc_stream")]
+             ("qc2304", "fbp_nms", "qc_stream"), ("qc2304", "cbp_nms", "qc_reg"),
+             ("qc_t64s", "cbp_nms", "qc_reg"), ("reg36_n96", "cbp_nms", "sparse"),
+             ("qc_t16", "cbp_nms", "qc_stream")]
 
 
 @pytest.mark.parametrize("name,algo,kernel", MSG_CASES, ids=[f"{a}-{b}-{c}" for a, b, c in MSG_CASES])
@@ -115,7 +124,7 @@ def test_messages_match_fp64(name, algo, kernel):
         gb, gi, d = run_gpu(code, llr, k, algo, kernel=kernel, stop_rule=2, dump_sweep=k,
                             dump_frames=64)
         o = oracle.decode(code, llr, k, algo, stop_rule=2, dump_sweep=k, ndump=64)
-        keys = ["lam", "r"] + (["q", "om"] if algo == "cbp" else [])
+        keys = ["lam", "r"] + (["q", "om"] if algo in ("cbp", "cbp_nms") else [])
         for key in keys:
             ref = o[{"lam": "Lam", "r": "R", "q": "Q", "om": "Om"}[key]]
             got = d[key].astype(np.float64)
@@ -131,7 +140,7 @@ def test_edge_cases(name):
     code = get_code(name)
     say(f"[gpu] edge cases {name}")
     llr, cw = make_frames(code, 1.5, 130, key=(23,))
-    for algo in ["cbp", "lbp_nms", "fbp_nms"]:
+    for algo in ["cbp", "cbp_nms", "lbp_nms", "fbp_nms"]:
         # max_iter = 0: [L < 0], no sweep
         gb, gi = run_gpu(code, llr, 0, algo)
         assert (gi == 0).all() and np.array_equal(gb, (llr < 0).astype(np.uint8))
@@ -187,13 +196,28 @@ def test_symmetry_and_determinism(name, kernel):
     rng = np.random.default_rng(5)
     c = encode(code, rng.integers(0, 2, size=(512, code.K), dtype=np.uint8))
     say(f"[gpu] symmetry {name}")
-    for algo in ["cbp", "lbp_nms", "fbp_nms"]:
+    for algo in ["cbp", "cbp_nms", "lbp_nms", "fbp_nms"]:
         a = run_gpu(code, llr, 25, algo, kernel=kernel)
         b = run_gpu(code, llr * (1 - 2 * c.astype(np.float32)), 25, algo, kernel=kernel)
         a2 = run_gpu(code, llr, 25, algo, kernel=kernel)
         assert np.array_equal(a[0], a2[0]) and np.array_equal(a[1], a2[1])
         assert np.array_equal(a[1], b[1])
         assert np.array_equal(a[0] ^ c, b[0])
+
+
+@pytest.mark.parametrize("name,kernel", [("qc2304", "qc_reg"), ("reg36_n96", "sparse")])
+def test_min_sum_cbp_flushed_decisions(name, kernel):
+    # the min-sum CBP with flushed decisions is layered min-sum (oracle pin)
+    code = get_code(name)
+    llr, _ = make_frames(code, 2.0, 1000, key=(28,))
+    say(f"[gpu] cbp_nms hd_mode=1 {name} {kernel}")
+    gb, gi = run_gpu(code, llr, 30, "cbp_nms", hd_mode=1, kernel=kernel)
+    o = oracle.decode(code, llr, 30, "cbp_nms", hd_mode=1)
+    conv = o["iters"] < 30
+    ok = agree(gb, gi, o["bits"], o["iters"])
+    assert (gi == o["iters"]).mean() >= PARITY and ok[conv].mean() >= PARITY
+    l = oracle.decode(code, llr, 30, "lbp_nms")
+    assert (gi == l["iters"]).mean() >= PARITY
 
 
 def test_syndrome_entry_point():
