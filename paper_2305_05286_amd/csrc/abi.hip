@@ -174,6 +174,16 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             }
             for (auto *v : {&rstart, &eb, &esh, &er, &ep, &epr, &epsh, &efirst, &elast})
                 qt.insert(qt.end(), v->begin(), v->end());
+            // the records start 16-byte aligned in the device buffer
+            const size_t off0 = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size();
+            while ((off0 + qt.size()) % 4) qt.push_back(0);
+            for (int e = 0; e < qE; ++e) {
+                const int last = elast[eb[e]] == e;
+                qt.push_back(eb[e] | last << 29 | efirst[e] << 30);
+                qt.push_back(esh[e]);
+                qt.push_back(ep[e]);
+                qt.push_back(epsh[e] | epr[e] << 16);
+            }
         }
         const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size() + qt.size();
         const size_t bytes = ints * 4 + (size_t)E + 64;
@@ -247,6 +257,9 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             d += qE;
             q.elast = d;
             d += c->nb;
+            d = reinterpret_cast<int *>(((uintptr_t)d + 15) & ~(uintptr_t)15);
+            q.erec = reinterpret_cast<const int4 *>(d);
+            d += 4 * (size_t)qE;
             t.qs_ready = true;
         }
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
@@ -284,13 +297,13 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
         return fail(CBP_EINVAL, "check_rule must be CBP_RULE_LOG_TANH or CBP_RULE_MIN_SUM");
     if (o->dump_sweep < 0 || o->dump_frames < 0) return fail(CBP_EINVAL, "negative dump option");
     int k = o->kernel;
-    const bool stream_ok = code->qc && code->Z <= 1024;
+    const bool stream_ok = code->qc && code->Z <= 1024 && code->mb < 32768 && code->nb < 65536;
     if (k == CBP_KERNEL_AUTO)
         k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : stream_ok ? CBP_KERNEL_QC_STREAM : CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_QC_REG && code->qc_reg_id < 0)
         return fail(CBP_EUNSUPPORTED, "no register-resident kernel is compiled for this base pattern");
     if (k == CBP_KERNEL_QC_STREAM && !stream_ok)
-        return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024");
+        return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024, mb < 32768, nb < 65536");
     if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE)
         return fail(CBP_EINVAL, "unknown kernel %d", o->kernel);
     r->kernel = k;
@@ -511,7 +524,7 @@ int cbp_code_info(const cbp_code_t *c, int32_t *M, int32_t *N, int64_t *E, int32
     if (Z) *Z = c->qc ? c->Z : 0;
     if (kernels)
         *kernels = CBP_KERNEL_SPARSE | (c->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : 0) |
-                   (c->qc && c->Z <= 1024 ? CBP_KERNEL_QC_STREAM : 0);
+                   (c->qc && c->Z <= 1024 && c->mb < 32768 && c->nb < 65536 ? CBP_KERNEL_QC_STREAM : 0);
     return CBP_OK;
 }
 

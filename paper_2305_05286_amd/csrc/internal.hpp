@@ -65,6 +65,11 @@ struct QcStreamDev {
     const int *epsh;    // [E] shift of ep
     const int *efirst;  // [E] 1 if the edge's block-row is the first of its column
     const int *elast;   // [nb] last edge of each block-column
+    // [E] the fields the sweep reads, one 16-byte record per edge:
+    //   x = eb | last << 29 | first << 30  (last: the edge is its column's
+    //       last visit of the sweep; first: efirst), y = esh, z = ep,
+    //   w = epsh | epr << 16
+    const int4 *erec;
 };
 int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g);
 void qc_stream_shape(const QcStreamDev &g, int *slots, int *threads, size_t *lds);

@@ -7,17 +7,30 @@
 // the sweep and the only cross-lane traffic of a layer is one rotated LDS
 // exchange of the new V2C terms plus the rotated reads of the latest checks'
 // beliefs.  The base structure is a runtime edge table (sweep order: layer
-// major, block-column ascending), read with wave-uniform scalar loads.
+// major, block-column ascending), read through the constant address space so
+// that its wave-uniform reads are scalar loads: a vector load there would put
+// a full memory round trip in front of every state access of the edge.
+//
+// The kernel is bound by memory latency (a layer's accesses depend on the
+// edge table and end in a barrier), so what matters is the number of frames
+// in flight: the state per edge is kept to what the method needs and the
+// kernel is compiled for 8 waves per SIMD.
 //
 // Workspace of one slot (element [i][l] of a Z-vector array at i*Z + l, so a
 // lane's accesses are coalesced across the slot):
 //   Q  [NB][Z]  CBP: latest V2C; NMS: posterior Lambda
-//   PQ [NB][Z]  CBP: psi of the folded Q; FBP: accumulator of the new C2V
+//   PQ [NB][Z]  FBP only: accumulator of the new C2V messages
 //   R  [E][Z]   C2V message of every edge
-//   XB [NB][Z]  hard decisions (bytes)
 //   OM [MB][Z]  CBP: check-beliefs (max psi term | parity, rest of the sum)
+//   XB [NB][Z]  hard decisions (bytes)
+// CBP needs no cached psi(|Q_v|): Q_v is still the V2C value the latest check
+// folded, and psi of it is recomputed bit-identically.
 #include "internal.hpp"
 #include "phi.hpp"
+
+#ifndef STREAM_WPE_N
+#define STREAM_WPE_N 8
+#endif
 
 namespace cbp {
 namespace {
@@ -36,8 +49,27 @@ struct StreamArgs {
     int64_t ws_stride;
 };
 
+// Read of a table that no launch writes, as constant memory (scalar loads
+// where the index is wave-uniform).
+template <class T>
+__device__ __forceinline__ T ldc(const T *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+struct Edge {
+    int b, sh, ep, epsh, epr;
+    bool last, first;
+};
+__device__ __forceinline__ Edge edge(const QcStreamDev &g, int e) {
+    const int *rec = reinterpret_cast<const int *>(g.erec) + 4 * (int64_t)e;
+    const int x = ldc(rec, 0), w = ldc(rec, 3);
+    return Edge{x & 0xffff, ldc(rec, 1), ldc(rec, 2), w & 0xffff, w >> 16, ((x >> 29) & 1) != 0,
+                ((x >> 30) & 1) != 0};
+}
+
 template <int kAlgo>
-__global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(STREAM_WPE_N)))
+void qc_stream_kernel(StreamArgs A) {
     extern __shared__ float smem[];
     const QcStreamDev &g = A.g;
     const int Z = g.Z, NB = g.nb, MB = g.mb, E = g.E;
@@ -45,9 +77,11 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
     const int SL = g.slots;
     const int slot = threadIdx.x / Z;
     const int l = threadIdx.x - slot * Z;
-    // LDS: exchange [SL][dcmax][Z] floats, row state [SL][Z] float2, flags
-    const size_t xfloats = ((size_t)SL * g.dcmax * Z + 1) & ~(size_t)1;  // keep sRow 8-byte aligned
+    // LDS: exchange [SL][dcmax][Z] floats, NMS V2C stash [SL][dcmax][Z] floats,
+    // row state [SL][Z] float2, flags
+    const size_t xfloats = ((size_t)2 * SL * g.dcmax * Z + 1) & ~(size_t)1;  // keep sRow 8-byte aligned
     float *sX = smem + (size_t)slot * g.dcmax * Z;
+    float *sQ = smem + (size_t)(SL + slot) * g.dcmax * Z;
     float2 *sRow = reinterpret_cast<float2 *>(smem + xfloats) + (size_t)slot * Z;
     int *sFlags = reinterpret_cast<int *>(smem + xfloats + 2 * (size_t)SL * Z);
     unsigned int *sF = reinterpret_cast<unsigned int *>(sFlags);  // [SL]
@@ -59,9 +93,9 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
     const int64_t gslot = (int64_t)blockIdx.x * SL + slot;
     char *base = A.ws + gslot * A.ws_stride;
     float *Q = reinterpret_cast<float *>(base);
-    float *PQ = Q + N;
-    float *R = PQ + N;
-    float2 *OM = reinterpret_cast<float2 *>(base + ((4 * (2 * N + (int64_t)E * Z) + 7) & ~(int64_t)7));
+    float *PQ = Q + N;                                     // FBP only
+    float *R = Q + (kAlgo == kFBPNMS ? 2 * N : N);
+    float2 *OM = reinterpret_cast<float2 *>(base + ((4 * ((kAlgo == kFBPNMS ? 2 : 1) * N + (int64_t)E * Z) + 7) & ~(int64_t)7));
     uint8_t *XB = reinterpret_cast<uint8_t *>(OM + (kBelief ? (int64_t)MB * Z : 0));  // slot end = qc_stream_slot_bytes
 
     const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
@@ -70,7 +104,7 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
         for (int b = 0; b < NB; ++b) {
             const float v = A.llr[fr * N + (int64_t)b * Z + l];
             Q[b * Z + l] = v;
-            PQ[b * Z + l] = 0.0f;
+            if constexpr (kAlgo == kFBPNMS) PQ[b * Z + l] = 0.0f;
             XB[b * Z + l] = v < 0.0f;
         }
         for (int e = 0; e < E; ++e) R[(int64_t)e * Z + l] = 0.0f;
@@ -91,10 +125,11 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
         uint32_t bad = 0;
         for (int r = 0; r < MB; ++r) {
             uint32_t par = 0;
-            for (int e = g.rstart[r]; e < g.rstart[r + 1]; ++e) {
-                int idx = l + g.esh[e];
+            for (int e = ldc(g.rstart, r); e < ldc(g.rstart, r + 1); ++e) {
+                const Edge ed = edge(g, e);
+                int idx = l + ed.sh;
                 idx -= (idx >= Z) ? Z : 0;
-                par ^= XB[g.eb[e] * Z + idx];
+                par ^= XB[ed.b * Z + idx];
             }
             bad |= par;
         }
@@ -133,44 +168,43 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
         // ---------------- one sweep ---------------------------------------
         const bool first = (t == 0);
         for (int r = 0; r < MB; ++r) {
-            const int e0 = g.rstart[r], e1 = g.rstart[r + 1];
+            const int e0 = ldc(g.rstart, r), e1 = ldc(g.rstart, r + 1);
             // phase 1: lane = variable
             for (int e = e0; e < e1; ++e) {
-                const int b = g.eb[e];
-                const int iv = b * Z + l;
-                int kc = l - g.esh[e];
+                const Edge ed = edge(g, e);
+                const int iv = ed.b * Z + l;
+                int kc = l - ed.sh;
                 kc += (kc < 0) ? Z : 0;
                 if constexpr (kBelief) {
                     const float q = Q[iv];
                     float rn = 0.0f;
-                    if (!(first && g.efirst[e])) {
-                        int kp = l - g.epsh[e];
+                    bool own = false;  // R(c_j -> v) is R(c_i -> v): a degree-1 column
+                    if (!(first && ed.first)) {
+                        int kp = l - ed.epsh;
                         kp += (kp < 0) ? Z : 0;
-                        const float2 om = OM[g.epr[e] * Z + kp];
+                        const float2 om = OM[ed.epr * Z + kp];
                         if constexpr (kAlgo == kCBP) {
-                            const float dd = excl_sum(abs_bits(om.x), om.y, PQ[iv]);
+                            // Q_v is still the V2C value whose psi c_j folded
+                            const float dd = excl_sum(abs_bits(om.x), om.y, psiq_clamped(q, a, lmax));
                             rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
                         } else {
                             const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
                             const float m1 = abs_bits(om.x);
                             rn = with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
                         }
-                        R[(int64_t)g.ep[e] * Z + l] = rn;  // commit R(c_j -> v) first
+                        R[(int64_t)ed.ep * Z + l] = rn;  // commit R(c_j -> v) first
+                        own = ed.ep == e;
                     }
                     const float lam = q + rn;
-                    XB[iv] = lam < 0.0f;
-                    const float qn = lam - R[(int64_t)e * Z + l];
-                    float fq;
-                    if constexpr (kAlgo == kCBP) {
-                        fq = psiq_clamped(qn, a, lmax);
-                        PQ[iv] = fq;
-                    } else {
-                        fq = __builtin_fminf(__builtin_fabsf(qn), lmax);
-                    }
+                    if (ed.last) XB[iv] = lam < 0.0f;  // v's last visit of the sweep decides
+                    const float qn = lam - (own ? rn : R[(int64_t)e * Z + l]);
+                    const float fq = kAlgo == kCBP ? psiq_clamped(qn, a, lmax)
+                                                   : __builtin_fminf(__builtin_fabsf(qn), lmax);
                     Q[iv] = qn;
                     sX[(e - e0) * Z + kc] = with_sign(fq, qn < 0.0f);
                 } else {
                     const float q = Q[iv] - R[(int64_t)e * Z + l];
+                    sQ[(e - e0) * Z + l] = q;  // kept for phase 3
                     sX[(e - e0) * Z + kc] = with_sign(__builtin_fminf(__builtin_fabsf(q), lmax), q < 0.0f);
                 }
             }
@@ -203,12 +237,12 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
             if constexpr (!kBelief) {
                 // phase 3: lane = variable
                 for (int e = e0; e < e1; ++e) {
-                    const int b = g.eb[e];
-                    const int iv = b * Z + l;
-                    int kc = l - g.esh[e];
+                    const Edge ed = edge(g, e);
+                    const int iv = ed.b * Z + l;
+                    int kc = l - ed.sh;
                     kc += (kc < 0) ? Z : 0;
                     const float2 rw = sRow[kc];
-                    const float q = Q[iv] - R[(int64_t)e * Z + l];
+                    const float q = sQ[(e - e0) * Z + l];
                     const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
                     const float m1 = abs_bits(rw.x);
                     const float rn = with_sign(alpha * ((aq == m1) ? rw.y : m1), sign_bit(rw.x) ^ (q < 0.0f));
@@ -234,13 +268,13 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
             }
         }
         auto flushed = [&](int b) {
-            const int el = g.elast[b];
-            int k = l - g.esh[el];
+            const int el = ldc(g.elast, b);
+            int k = l - ldc(g.esh, el);
             k += (k < 0) ? Z : 0;
-            const float2 om = OM[g.er[el] * Z + k];
+            const float2 om = OM[ldc(g.er, el) * Z + k];
             const float q = Q[b * Z + l];
             if constexpr (kAlgo == kCBP) {
-                const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b * Z + l]);
+                const float dd = excl_sum(abs_bits(om.x), om.y, psiq_clamped(q, a, lmax));
                 return q + with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
             } else {
                 const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
@@ -264,12 +298,11 @@ __global__ __launch_bounds__(1024) void qc_stream_kernel(StreamArgs A) {
             }
             if (A.d.r)
                 for (int e = 0; e < E; ++e) {
-                    const int r = g.er[e];
-                    int k = l - g.esh[e];
+                    const int r = ldc(g.er, e);
+                    int k = l - ldc(g.esh, e);
                     k += (k < 0) ? Z : 0;
-                    const int dc = g.rstart[r + 1] - g.rstart[r];
-                    A.d.r[f * Etot + (int64_t)g.rstart[r] * Z + (int64_t)k * dc + (e - g.rstart[r])] =
-                        R[(int64_t)e * Z + l];
+                    const int r0 = ldc(g.rstart, r), dc = ldc(g.rstart, r + 1) - r0;
+                    A.d.r[f * Etot + (int64_t)r0 * Z + (int64_t)k * dc + (e - r0)] = R[(int64_t)e * Z + l];
                 }
             if constexpr (kBelief) {
                 if (A.d.om)
@@ -297,7 +330,7 @@ int slots_per_group(int Z) {
 
 int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g) {
     const int64_t N = (int64_t)g.nb * g.Z;
-    int64_t b = round_up(4 * (2 * N + (int64_t)g.E * g.Z), 8);
+    int64_t b = round_up(4 * ((algo == kFBPNMS ? 2 : 1) * N + (int64_t)g.E * g.Z), 8);
     if (algo == kCBP || algo == kCBPNMS) b += 8LL * g.mb * g.Z;
     b += N;
     return round_up(b, 256);
@@ -307,7 +340,7 @@ void qc_stream_shape(const QcStreamDev &g, int *slots, int *threads, size_t *lds
     const int SL = slots_per_group(g.Z);
     *slots = SL;
     *threads = SL * g.Z;
-    const size_t xfloats = ((size_t)SL * g.dcmax * g.Z + 1) & ~(size_t)1;
+    const size_t xfloats = ((size_t)2 * SL * g.dcmax * g.Z + 1) & ~(size_t)1;
     *lds = xfloats * 4 + (size_t)SL * g.Z * 8 + 8 * 4 * (size_t)SL;
 }
 

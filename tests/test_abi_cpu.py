@@ -127,7 +127,7 @@ def test_workspace_sizes(L):
     assert 0 < cbp.workspace_size(q, "cbp", 131072) <= 4096
     # streamed kernel: one slot of state per frame in flight, at most 2048 slots
     big = cbp.Code.from_workload(get_code("qc26112"))
-    per_slot = 4 * (2 * 26112 + 76800) + 8 * 17664 + 26112
+    per_slot = 4 * (26112 + 76800) + 8 * 17664 + 26112  # Q, R, check-beliefs, decisions
     n = cbp.workspace_size(big, "cbp", 4096)
     assert 2048 * per_slot <= n <= 2048 * (per_slot + 512) + 256
     assert cbp.workspace_size(big, "cbp", 3) <= 3 * (per_slot + 512) + 256
