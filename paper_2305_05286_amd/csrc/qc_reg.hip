@@ -133,10 +133,13 @@ __device__ __forceinline__ int opaque_v(int x) {
     asm volatile("" : "+v"(x));
     return x;
 }
+// The shift table is never written during a launch: read through the
+// constant address space it is loaded with scalar loads into SGPRs (as a
+// generic pointer it would take flat vector loads and a VGPR per shift).
 template <class T>
-__device__ __forceinline__ const T *opaque_s(const T *p) {
+__device__ __forceinline__ const __attribute__((address_space(4))) T *opaque_s(const T *p) {
     asm volatile("" : "+s"(p));
-    return p;
+    return (const __attribute__((address_space(4))) T *)p;
 }
 
 // Occupancy target (waves per SIMD) handed to the register allocator.  The
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             constexpr int r = rc;
             uint32_t par = 0;
             const int lv = opaque_v(l);
-            const int *sh = opaque_s(A.sht);
+            const auto sh = opaque_s(A.sht);
             static_for<TT::T.rstart[r], TT::T.rstart[r + 1]>([&](auto ec) {
                 constexpr int e = ec;
                 constexpr int b = TT::T.eb[e];
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             constexpr int e0 = TT::T.rstart[r], e1 = TT::T.rstart[r + 1];
             float qk[e1 - e0];
             const int lv = opaque_v(l);
-            const int *sh = opaque_s(A.sht);
+            const auto sh = opaque_s(A.sht);
             // phase 1: lane = variable
             static_for<e0, e1>([&](auto ec) {
                 constexpr int e = ec;
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             {
                 uint32_t par = 0;
                 const int lr = opaque_v(l);
-                const int *shr = opaque_s(A.sht);
+                const auto shr = opaque_s(A.sht);
                 if constexpr (!kMinRow) {
                     float Mx = 0.0f, Sr = 0.0f;
                     static_for<0, e1 - e0>([&](auto jc) {
