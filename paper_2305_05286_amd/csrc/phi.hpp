@@ -80,6 +80,36 @@ __device__ __forceinline__ float r_psi(float d) {
     return d < kInvLn2 ? small : t * w;
 }
 
+// phi in log2 units: g(x) = phi(x ln2) / ln2.  Because phi is its own inverse,
+// so is g: with every LLR kept in log2 units (L / ln2) the check rule needs
+// this one function for both directions (g = psi_q on a V2C magnitude, and
+// g = r_psi on a phi-domain sum), and neither range needs a unit conversion:
+//   x <  1/ln2: -log2(x * QA(x^2))
+//   x >= 1/ln2: t * UB(t^2), t = 2^-x
+// (the coefficient sets above; max relative error 1.9e-7 against phi).
+__device__ __forceinline__ float phi2(float x) {
+    const float uu = x * x;
+    float p = 1.2360707160041784e-06f;
+    p = __builtin_fmaf(p, uu, -3.182218279107474e-05f);
+    p = __builtin_fmaf(p, uu, 0.0006662501837126911f);
+    p = __builtin_fmaf(p, uu, -0.01387591753154993f);
+    p = __builtin_fmaf(p, uu, 0.3465735912322998f);
+    const float small = -__builtin_amdgcn_logf(x * p);
+    const float t = __builtin_amdgcn_exp2f(-x);
+    const float s = t * t;
+    float u = 0.42938604950904846f;
+    u = __builtin_fmaf(u, s, 0.39844658970832825f);
+    u = __builtin_fmaf(u, s, 0.5777652859687805f);
+    u = __builtin_fmaf(u, s, 0.961784839630127f);
+    u = __builtin_fmaf(u, s, 2.885390043258667f);
+    return x < kInvLn2 ? small : t * u;
+}
+
+// g of a V2C magnitude (log2 units) clamped to [a2, lmax2], a2 = g(lmax2).
+__device__ __forceinline__ float phi2_clamped(float q, float a2, float lmax2) {
+    return phi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2));
+}
+
 // psi of a V2C magnitude clamped to [a, lmax], a = phi(lmax) (saturation of
 // the messages entering a check).
 __device__ __forceinline__ float psiq_clamped(float q, float a, float lmax) {

@@ -159,6 +159,13 @@ __device__ __forceinline__ int wrap(int x) {
     return x - ((x >= Z) ? Z : 0);
 }
 
+// (x mod Z) for x in (-Z, Z): as unsigned, a negative x exceeds x + Z.
+template <int Z>
+__device__ __forceinline__ int wrap_lo(int x) {
+    const unsigned u = (unsigned)x, v = (unsigned)(x + Z);
+    return (int)(u < v ? u : v);
+}
+
 // kDbg: the instantiation that also serves hd_mode = 1 and the state dumps;
 // the production instantiation carries neither (cold code still costs
 // registers in a kernel this close to its register budget).
@@ -187,9 +194,14 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
 
     const int slot = threadIdx.x / Z;
     const int l = threadIdx.x - slot * Z;
-    const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
+    // The log-tanh rule keeps every LLR in log2 units (L / ln2), where one
+    // function (phi2) serves both directions of the check rule; the min-sum
+    // rules are linear and keep natural units.
+    constexpr bool kLog2 = kAlgo == kCBP;
+    const float us = kLog2 ? kLog2e : 1.0f;
+    const float a = A.p.a * us, lmax = A.p.lmax * us, alpha = A.p.alpha;
 
-    // CBP: Q = latest V2C, PQ = psi(clamped Q) as folded.  NMS: Q = posterior
+    // CBP: Q = latest V2C, PQ = phi2(clamped Q) as folded.  NMS: Q = posterior
     // Lambda, PQ = flooding accumulator of the new C2V messages.
     float Q[NB], PQ[NB], R[E];
     Mask xb = 0;
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         xb = 0;
         static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            const float v = A.llr[fr * N + b * Z + l] + 0.0f;  // -0.0 -> +0.0
+            const float v = A.llr[fr * N + b * Z + l] * us + 0.0f;  // -0.0 -> +0.0
             Q[b] = v;
             PQ[b] = 0.0f;
             if (v < 0.0f) xb |= Mask(1) << b;
@@ -284,11 +296,11 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 if constexpr (kBelief) {
                     constexpr int ep = TT::T.epred[e], rp = TT::T.er[ep];
                     // B2V (eq. equ_s4e18) from the latest check's belief
-                    const float2 om = sOm[slot][rp * Z + wrap<Z>(lv - sh[E + e])];
+                    const float2 om = sOm[slot][rp * Z + wrap_lo<Z>(lv - sh[E + e])];
                     float rn;
                     if constexpr (kAlgo == kCBP) {
                         const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-                        rn = or_sign(r_psi(dd), fbits(om.x) ^ fbits(Q[b]));
+                        rn = or_sign(phi2(dd), fbits(om.x) ^ fbits(Q[b]));
                     } else {  // min-sum rule (eq. equ_s4e18xx)
                         const float aq = __builtin_fminf(__builtin_fabsf(Q[b]), lmax);
                         const float m1 = abs_bits(om.x);
@@ -305,7 +317,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     const float qn = lam - R[e];      // V2C, eq. equ_s4e19
                     float fq;
                     if constexpr (kAlgo == kCBP) {
-                        fq = psiq_clamped(qn, a, lmax);
+                        fq = phi2_clamped(qn, a, lmax);
                         PQ[b] = fq;
                     } else {
                         fq = __builtin_fminf(__builtin_fabsf(qn), lmax);
@@ -394,10 +406,10 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         auto flushed = [&](auto bc) {
             constexpr int b = bc;
             constexpr int el = TT::T.elast[b], rl = TT::T.er[el];
-            const float2 om = sOm[slot][rl * Z + wrap<Z>(opaque_v(l) - opaque_s(A.sht)[el])];
+            const float2 om = sOm[slot][rl * Z + wrap_lo<Z>(opaque_v(l) - opaque_s(A.sht)[el])];
             if constexpr (kAlgo == kCBP) {
                 const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
-                return Q[b] + with_sign(r_psi(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
+                return Q[b] + with_sign(phi2(dd), sign_bit(om.x) ^ (Q[b] < 0.0f));
             } else {
                 const float aq = __builtin_fminf(__builtin_fabsf(Q[b]), lmax);
                 const float m1 = abs_bits(om.x);
@@ -414,11 +426,12 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         }
         if (kDbg && t == A.d.sweep && f < A.d.frames) {
             const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
+            const float un = kLog2 ? kLn2 : 1.0f;  // dumps in natural units
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
                 if constexpr (kBelief) {
-                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b];
-                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(bc);
+                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b] * un;
+                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(bc) * un;
                 } else {
                     if (A.d.lam) A.d.lam[f * N + b * Z + l] = Q[b];
                 }
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     constexpr int e = ec;
                     constexpr int r = TT::T.er[e];
                     const int k = wrap<Z>(l - A.sht[e]);
-                    A.d.r[f * Etot + TT::T.csr_off[r] + k * TT::T.dc[r] + TT::T.ejpos[e]] = R[e];
+                    A.d.r[f * Etot + TT::T.csr_off[r] + k * TT::T.dc[r] + TT::T.ejpos[e]] = R[e] * un;
                 });
             if constexpr (kBelief) {
                 if (A.d.om)
@@ -436,7 +449,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                         constexpr int r = rc;
                         const float2 om = sOm[slot][r * Z + l];
                         A.d.om[f * M + r * Z + l] =
-                            kAlgo == kCBP ? with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x))
+                            kAlgo == kCBP ? with_sign(phi2(abs_bits(om.x) + om.y) * un, sign_bit(om.x))
                                           : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
                     });
             }
