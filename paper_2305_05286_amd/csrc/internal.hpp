@@ -9,6 +9,15 @@ namespace cbp {
 // CBP_RULE_MIN_SUM).
 enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2, kCBPNMS = 3 };
 
+// Read of a table that no launch writes, through the constant address space:
+// where the index is wave-uniform the compiler emits a scalar load (through a
+// generic pointer it could not rule out aliasing with the kernel's stores and
+// would issue a vector load, a full memory round trip, instead).
+template <class T>
+__device__ __forceinline__ T ldc(const T *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 struct Params {
     float a;       // phi(lmax): lower clamp of |Q| entering phi
     float lmax;    // upper clamp

@@ -1,23 +1,20 @@
 // FP32 device math of the check rule on gfx950.
 //
-// phi(x) = -ln tanh(x/2) (Sec. II-A, eq. equ_s2e5).  The kernels keep every
-// phi-domain quantity (the terms a check folds and their sums) in log2 units,
-// psi = phi / ln 2, so that the hardware log2/exp2 need no scaling:
+// phi(x) = -ln tanh(x/2) (Sec. II-A, eq. equ_s2e5) is its own inverse.  The
+// log-tanh kernels keep every LLR in log2 units (L / ln 2); there the rule
+// needs g(x) = phi(x ln2) / ln2, which is again its own inverse, so one
+// function maps a V2C magnitude to its phi-domain term and a phi-domain sum
+// back to a C2V magnitude, and the hardware log2/exp2 need no scaling:
 //
-//   psi_q(x)  = phi(x) / ln2 for a V2C magnitude x (natural units)
-//     x <  1:  -log2(x * PA(x^2)),    PA(y) ~ tanh(sqrt(y)/2) / sqrt(y)
-//     x >= 1:  t * UB(t^2), t = 2^(-x log2 e),  UB(s) ~ (2/ln2) atanh(sqrt s)/sqrt s
-//   r_psi(d)  = phi(d ln2), the C2V magnitude of a psi-domain sum d
-//     d <  1/ln2: -ln2 * log2(d * QA(d^2)),  QA(u) ~ tanh(ln2 sqrt(u)/2)/sqrt(u)
-//     d >= 1/ln2: t * UR(t^2), t = 2^-d,      UR(s) ~ 2 atanh(sqrt s)/sqrt s
+//   x <  1/ln2: -log2(x * QA(x^2)),  QA(u) ~ tanh(ln2 sqrt(u)/2) / sqrt(u)
+//   x >= 1/ln2: t * UB(t^2), t = 2^-x,  UB(s) ~ (2/ln2) atanh(sqrt s) / sqrt s
 //
-// (the large-argument forms are phi = ln((1+t)/(1-t)) = 2 atanh t with
-// t = e^-x; the small-argument forms keep 1 - t from cancelling).  Each range
-// needs one hardware transcendental (v_log_f32 / v_exp_f32) and a degree-4
-// polynomial, a weighted least-squares fit for relative error (max 1.1e-8 ..
-// 1.3e-8 on its interval); the two functions stay within 1e-6 (psi_q,
-// x <= 20) and 2e-7 (r_psi) relative of phi.  Large sums underflow to
-// denormals / 0.
+// (the large-argument form is phi = 2 atanh(e^-x); the small-argument form
+// keeps 1 - t from cancelling).  Each range takes one hardware
+// transcendental (v_log_f32 / v_exp_f32) and a degree-4 polynomial, a
+// weighted least-squares fit for relative error (max 1.1e-8 .. 1.3e-8 on its
+// interval); g stays within 1.9e-7 relative of phi(x ln2)/ln2 for x up to
+// 60.  Large sums underflow to denormals / 0.
 //
 // Check-belief representation.  The paper keeps Omega in the LLR domain and
 // recovers an excluded C2V message through psi- (eq. equ_s4e13), i.e. a
@@ -29,8 +26,8 @@
 //   else    : the rest is Mx + (S - f)          (f <= Mx, so the error of the
 //                                                 difference is <= eps * Mx)
 // which is the exclusion of eq. (equ_s3e2) / App. A (equ_ae7) without the
-// cancellation; f must be bit-identical to the folded value, so it is cached
-// per variable.
+// cancellation; f must be bit-identical to the folded value (cached, or
+// recomputed from the unchanged V2C value by the same code).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -44,49 +41,6 @@ constexpr float kInvLn2 = 1.4426950408889634f;
 // Both ranges are evaluated and one result selected: the lanes of a wave
 // almost always straddle the split, and branching then costs more than the
 // second polynomial (measured on MI355X: 10% of the CBP kernel).
-__device__ __forceinline__ float psi_q(float x) {
-    const float y = x * x;
-    float p = 3.346680023241788e-05f;
-    p = __builtin_fmaf(p, y, -0.0004139537049923092f);
-    p = __builtin_fmaf(p, y, 0.004163993522524834f);
-    p = __builtin_fmaf(p, y, -0.041666336357593536f);
-    p = __builtin_fmaf(p, y, 0.5f);
-    const float small = -__builtin_amdgcn_logf(x * p);
-    const float t = __builtin_amdgcn_exp2f(-x * kLog2e);
-    const float s = t * t;
-    float u = 0.42938604950904846f;
-    u = __builtin_fmaf(u, s, 0.39844658970832825f);
-    u = __builtin_fmaf(u, s, 0.5777652859687805f);
-    u = __builtin_fmaf(u, s, 0.961784839630127f);
-    u = __builtin_fmaf(u, s, 2.885390043258667f);
-    return x < 1.0f ? small : t * u;
-}
-
-__device__ __forceinline__ float r_psi(float d) {
-    const float uu = d * d;
-    float p = 1.2360707160041784e-06f;
-    p = __builtin_fmaf(p, uu, -3.182218279107474e-05f);
-    p = __builtin_fmaf(p, uu, 0.0006662501837126911f);
-    p = __builtin_fmaf(p, uu, -0.01387591753154993f);
-    p = __builtin_fmaf(p, uu, 0.3465735912322998f);
-    const float small = -kLn2 * __builtin_amdgcn_logf(d * p);
-    const float t = __builtin_amdgcn_exp2f(-d);
-    const float s = t * t;
-    float w = 0.2976277470588684f;
-    w = __builtin_fmaf(w, s, 0.2761821448802948f);
-    w = __builtin_fmaf(w, s, 0.4004763960838318f);
-    w = __builtin_fmaf(w, s, 0.6666584610939026f);
-    w = __builtin_fmaf(w, s, 2.0f);
-    return d < kInvLn2 ? small : t * w;
-}
-
-// phi in log2 units: g(x) = phi(x ln2) / ln2.  Because phi is its own inverse,
-// so is g: with every LLR kept in log2 units (L / ln2) the check rule needs
-// this one function for both directions (g = psi_q on a V2C magnitude, and
-// g = r_psi on a phi-domain sum), and neither range needs a unit conversion:
-//   x <  1/ln2: -log2(x * QA(x^2))
-//   x >= 1/ln2: t * UB(t^2), t = 2^-x
-// (the coefficient sets above; max relative error 1.9e-7 against phi).
 __device__ __forceinline__ float phi2(float x) {
     const float uu = x * x;
     float p = 1.2360707160041784e-06f;
@@ -105,15 +59,10 @@ __device__ __forceinline__ float phi2(float x) {
     return x < kInvLn2 ? small : t * u;
 }
 
-// g of a V2C magnitude (log2 units) clamped to [a2, lmax2], a2 = g(lmax2).
+// g of a V2C magnitude (log2 units) clamped to [a2, lmax2], a2 = g(lmax2)
+// (saturation of the messages entering a check).
 __device__ __forceinline__ float phi2_clamped(float q, float a2, float lmax2) {
     return phi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2));
-}
-
-// psi of a V2C magnitude clamped to [a, lmax], a = phi(lmax) (saturation of
-// the messages entering a check).
-__device__ __forceinline__ float psiq_clamped(float q, float a, float lmax) {
-    return psi_q(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a), lmax));
 }
 
 // Float carrying magnitude m >= 0 with its sign bit set iff neg.
@@ -136,12 +85,12 @@ __device__ __forceinline__ float or_sign(float mag, uint32_t sign_src) {
     return __uint_as_float(__float_as_uint(mag) | (sign_src & 0x80000000u));
 }
 
-// psi-domain magnitude of a row belief (Mx = max term, S = rest) excluding f.
+// phi-domain magnitude of a row belief (Mx = max term, S = rest) excluding f.
 __device__ __forceinline__ float excl_sum(float Mx, float S, float f) {
     return (f == Mx) ? S : Mx + (S - f);
 }
 
-// Fold one psi term into a (max, rest) accumulator.
+// Fold one phi-domain term into a (max, rest) accumulator.
 __device__ __forceinline__ void fold(float &Mx, float &S, float f) {
     S += __builtin_fminf(Mx, f);
     Mx = __builtin_fmaxf(Mx, f);

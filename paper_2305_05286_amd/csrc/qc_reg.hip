@@ -2,16 +2,17 @@
 // compiled in (qc_graphs.inc); circulant shifts are runtime arguments.
 //
 // Layout.  A frame occupies Z lanes ("a slot"); lane l owns variable l of
-// every block-column b (v = b*Z + l): its latest V2C message Q[b], the psi
-// (phi / ln2) of that message as folded into its latest check PQ[b], the C2V message of each
-// of its edges R[e] and its hard decisions (bit b of xb) all live in VGPRs.
+// every block-column b (v = b*Z + l): its latest V2C message Q[b], the phi2
+// term of that message as folded into its latest check PQ[b], the C2V message
+// of each of its edges R[e] and its hard decisions (bit b of xb) all live in
+// VGPRs (log-tanh CBP in log2 units, see phi.hpp).
 // Block-row r is one layer of the sweep: its Z rows share no variable, so the
 // Z lanes update them at once with exactly the result of the paper's
 // row-by-row order.  Row k of block-row r meets variable (k + s) mod Z of
 // block-column b, i.e. lane l talks to row (l - s) mod Z: the only cross-lane
 // traffic is through LDS, one rotated (bank-conflict-free) access per edge:
 //   phase 1 (lane = variable): B2V from the latest check's belief (LDS read),
-//            V2C, hard decision, psi of the new V2C -> exchange slot of its row;
+//            V2C, hard decision, phi2 of the new V2C -> exchange slot of its row;
 //   phase 2 (lane = row k):    fold the row's exchange entries into the
 //            check-belief (max term, rest-of-sum, sign parity) -> LDS.
 // Two barriers per layer.  Workgroups hold lcm(Z, 64)/Z slots (Z = 96: two

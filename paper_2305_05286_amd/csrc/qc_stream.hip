@@ -21,10 +21,11 @@
 //   Q  [NB][Z]  CBP: latest V2C; NMS: posterior Lambda
 //   PQ [NB][Z]  FBP only: accumulator of the new C2V messages
 //   R  [E][Z]   C2V message of every edge
-//   OM [MB][Z]  CBP: check-beliefs (max psi term | parity, rest of the sum)
+//   OM [MB][Z]  CBP: check-beliefs (max phi2 term | parity, rest of the sum)
 //   XB [NB][Z]  hard decisions (bytes)
-// CBP needs no cached psi(|Q_v|): Q_v is still the V2C value the latest check
-// folded, and psi of it is recomputed bit-identically.
+// CBP keeps LLRs in log2 units and needs no cached phi2(|Q_v|): Q_v is still
+// the V2C value the latest check folded, and phi2 of it is recomputed
+// bit-identically.
 #include "internal.hpp"
 #include "phi.hpp"
 
@@ -48,13 +49,6 @@ struct StreamArgs {
     char *ws;           // slot workspaces, ws_stride bytes apart
     int64_t ws_stride;
 };
-
-// Read of a table that no launch writes, as constant memory (scalar loads
-// where the index is wave-uniform).
-template <class T>
-__device__ __forceinline__ T ldc(const T *p, int64_t i) {
-    return ((const __attribute__((address_space(4))) T *)p)[i];
-}
 
 struct Edge {
     int b, sh, ep, epsh, epr;
@@ -98,11 +92,15 @@ void qc_stream_kernel(StreamArgs A) {
     float2 *OM = reinterpret_cast<float2 *>(base + ((4 * ((kAlgo == kFBPNMS ? 2 : 1) * N + (int64_t)E * Z) + 7) & ~(int64_t)7));
     uint8_t *XB = reinterpret_cast<uint8_t *>(OM + (kBelief ? (int64_t)MB * Z : 0));  // slot end = qc_stream_slot_bytes
 
-    const float a = A.p.a, lmax = A.p.lmax, alpha = A.p.alpha;
+    // The log-tanh rule keeps every LLR in log2 units (L / ln2), where one
+    // function (phi2) serves both directions of the check rule.
+    constexpr bool kLog2 = kAlgo == kCBP;
+    const float us = kLog2 ? kLog2e : 1.0f;
+    const float a = A.p.a * us, lmax = A.p.lmax * us, alpha = A.p.alpha;
 
     auto load = [&](int64_t fr) {
         for (int b = 0; b < NB; ++b) {
-            const float v = A.llr[fr * N + (int64_t)b * Z + l];
+            const float v = A.llr[fr * N + (int64_t)b * Z + l] * us;
             Q[b * Z + l] = v;
             if constexpr (kAlgo == kFBPNMS) PQ[b * Z + l] = 0.0f;
             XB[b * Z + l] = v < 0.0f;
@@ -184,9 +182,9 @@ void qc_stream_kernel(StreamArgs A) {
                         kp += (kp < 0) ? Z : 0;
                         const float2 om = OM[ed.epr * Z + kp];
                         if constexpr (kAlgo == kCBP) {
-                            // Q_v is still the V2C value whose psi c_j folded
-                            const float dd = excl_sum(abs_bits(om.x), om.y, psiq_clamped(q, a, lmax));
-                            rn = with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+                            // Q_v is still the V2C value whose phi2 c_j folded
+                            const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
+                            rn = with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
                         } else {
                             const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
                             const float m1 = abs_bits(om.x);
@@ -198,7 +196,7 @@ void qc_stream_kernel(StreamArgs A) {
                     const float lam = q + rn;
                     if (ed.last) XB[iv] = lam < 0.0f;  // v's last visit of the sweep decides
                     const float qn = lam - (own ? rn : R[(int64_t)e * Z + l]);
-                    const float fq = kAlgo == kCBP ? psiq_clamped(qn, a, lmax)
+                    const float fq = kAlgo == kCBP ? phi2_clamped(qn, a, lmax)
                                                    : __builtin_fminf(__builtin_fabsf(qn), lmax);
                     Q[iv] = qn;
                     sX[(e - e0) * Z + kc] = with_sign(fq, qn < 0.0f);
@@ -274,8 +272,8 @@ void qc_stream_kernel(StreamArgs A) {
             const float2 om = OM[ldc(g.er, el) * Z + k];
             const float q = Q[b * Z + l];
             if constexpr (kAlgo == kCBP) {
-                const float dd = excl_sum(abs_bits(om.x), om.y, psiq_clamped(q, a, lmax));
-                return q + with_sign(r_psi(dd), sign_bit(om.x) ^ (q < 0.0f));
+                const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
+                return q + with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
             } else {
                 const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
                 const float m1 = abs_bits(om.x);
@@ -288,10 +286,11 @@ void qc_stream_kernel(StreamArgs A) {
         }
         if (t == A.d.sweep && f < A.d.frames) {
             const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
+            const float un = kLog2 ? kLn2 : 1.0f;  // dumps in natural units
             for (int b = 0; b < NB; ++b) {
                 if constexpr (kBelief) {
-                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b * Z + l];
-                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(b);
+                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b * Z + l] * un;
+                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(b) * un;
                 } else {
                     if (A.d.lam) A.d.lam[f * N + b * Z + l] = Q[b * Z + l];
                 }
@@ -302,14 +301,14 @@ void qc_stream_kernel(StreamArgs A) {
                     int k = l - ldc(g.esh, e);
                     k += (k < 0) ? Z : 0;
                     const int r0 = ldc(g.rstart, r), dc = ldc(g.rstart, r + 1) - r0;
-                    A.d.r[f * Etot + (int64_t)r0 * Z + (int64_t)k * dc + (e - r0)] = R[(int64_t)e * Z + l];
+                    A.d.r[f * Etot + (int64_t)r0 * Z + (int64_t)k * dc + (e - r0)] = R[(int64_t)e * Z + l] * un;
                 }
             if constexpr (kBelief) {
                 if (A.d.om)
                     for (int r = 0; r < MB; ++r) {
                         const float2 om = OM[r * Z + l];
                         A.d.om[f * M + (int64_t)r * Z + l] =
-                            kAlgo == kCBP ? with_sign(r_psi(abs_bits(om.x) + om.y), sign_bit(om.x))
+                            kAlgo == kCBP ? with_sign(phi2(abs_bits(om.x) + om.y) * un, sign_bit(om.x))
                                           : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
                     }
             }

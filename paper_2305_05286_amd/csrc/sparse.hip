@@ -2,7 +2,8 @@
 //
 // Every lane of a wave runs the whole sweep of its own frame in the paper's
 // row order; since all lanes share the code, the row/edge loops and the table
-// reads are wave-uniform (scalar loads) and the per-frame state is stored
+// reads are wave-uniform (scalar loads through the constant address space)
+// and the per-frame state is stored
 // frame-interleaved (index-major, frame-minor) so that each access of a wave
 // is one contiguous 256-byte line.  Frames that have stopped are masked off;
 // the wave leaves its loop once every lane has stopped.
@@ -18,7 +19,7 @@ __device__ bool lane_syndrome_ok(const SparseDev &g, const uint8_t *xb, int64_t 
     uint32_t bad = 0;
     for (int i = 0; i < g.M; ++i) {
         uint32_t p = 0;
-        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) p ^= xb[(int64_t)g.col_idx[e] * S + lf];
+        for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) p ^= xb[(int64_t)ldc(g.col_idx, e) * S + lf];
         bad |= p;
     }
     return bad == 0;
@@ -31,16 +32,18 @@ __device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int6
 }
 
 // --------------------------------------------------------------------------
-// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (psi = phi/ln2 of the clamped
-// Q folded into the latest check), a2 = R[E], a3 = OmM[M] (max psi term, sign
-// bit = parity), a4 = OmS[M] (rest of the psi sum), xb = hard decisions [N].
+// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (phi2 of the clamped Q folded
+// into the latest check), a2 = R[E], a3 = OmM[M] (max phi2 term, sign bit =
+// parity), a4 = OmS[M] (rest of the phi2 sum), xb = hard decisions [N].  The
+// log-tanh rule keeps LLRs in log2 units (L / ln2), where phi2 serves both
+// directions of the check rule; Params a and lmax arrive already scaled.
 // --------------------------------------------------------------------------
 // C2V of a check recovered from its belief (om = max term or min1 with the
 // parity in its sign bit, os = rest of the sum or min2), excluding q.
 template <bool kMin>
 __device__ float b2v(float om, float os, float pq, float q, const Params &p) {
     if constexpr (!kMin) {
-        return with_sign(r_psi(excl_sum(abs_bits(om), os, pq)), sign_bit(om) ^ (q < 0.0f));
+        return with_sign(phi2(excl_sum(abs_bits(om), os, pq)), sign_bit(om) ^ (q < 0.0f));
     } else {
         const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
         const float m1 = abs_bits(om);
@@ -51,8 +54,8 @@ __device__ float b2v(float om, float os, float pq, float q, const Params &p) {
 template <bool kMin>
 __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v, const Params &p) {
     const int64_t S = w.stride;
-    const int e = g.last_edge[v];
-    const int j = g.edge_row[e];
+    const int e = ldc(g.last_edge, v);
+    const int j = ldc(g.edge_row, e);
     const float q = w.a0[(int64_t)v * S + lf];
     return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
 }
@@ -68,12 +71,16 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     const int64_t f = f0 + lf;
     const int64_t S = w.stride;
     float *Q = w.a0, *PQ = w.a1, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
+    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
+    const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
+    p.a *= us;
+    p.lmax *= us;
     uint8_t *xb = w.xb;
     bool active = valid;
     // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
     if (valid) {
         for (int v = 0; v < g.N; ++v) {
-            const float l = llr[f * g.N + v];
+            const float l = llr[f * g.N + v] * us;
             Q[(int64_t)v * S + lf] = l;
             xb[(int64_t)v * S + lf] = l < 0.0f;
         }
@@ -90,24 +97,24 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             for (int i = 0; i < g.M; ++i) {
                 float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
                 bool par = false;
-                for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
-                    const int v = g.col_idx[e];
+                for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) {
+                    const int v = ldc(g.col_idx, e);
                     const int64_t iv = (int64_t)v * S + lf;
                     const float q = Q[iv];
                     float rn = 0.0f;
-                    if (!(t == 1 && g.first[e])) {
+                    if (!(t == 1 && ldc(g.first, e))) {
                         // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
                         // from its belief, then committed to R(c_j -> v) first.
-                        const int64_t ij = (int64_t)g.pred_row[e] * S + lf;
+                        const int64_t ij = (int64_t)ldc(g.pred_row, e) * S + lf;
                         rn = b2v<kMin>(OmM[ij], OmS[ij], PQ[iv], q, p);
-                        R[(int64_t)g.pred_edge[e] * S + lf] = rn;
+                        R[(int64_t)ldc(g.pred_edge, e) * S + lf] = rn;
                     }
                     const float lam = q + rn;                 // eq. equ_s4e20
                     xb[iv] = lam < 0.0f;                      // eq. equ_s2e7
                     const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
                     Q[iv] = qn;
                     if constexpr (!kMin) {
-                        const float fq = psiq_clamped(qn, p.a, p.lmax);
+                        const float fq = phi2_clamped(qn, p.a, p.lmax);
                         PQ[iv] = fq;
                         fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
                     } else {                                  // eq. equ_s4e21xx
@@ -124,17 +131,17 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                 for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed<kMin>(g, w, lf, v, p) < 0.0f;
             if (t == d.sweep && f < d.frames) {
                 for (int v = 0; v < g.N; ++v) {
-                    if (d.q) d.q[f * g.N + v] = Q[(int64_t)v * S + lf];
-                    if (d.lam) d.lam[f * g.N + v] = cbp_flushed<kMin>(g, w, lf, v, p);
+                    if (d.q) d.q[f * g.N + v] = Q[(int64_t)v * S + lf] * un;
+                    if (d.lam) d.lam[f * g.N + v] = cbp_flushed<kMin>(g, w, lf, v, p) * un;
                 }
                 if (d.r)
-                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf];
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf] * un;
                 if (d.om)
                     for (int i = 0; i < g.M; ++i) {
                         const float om = OmM[(int64_t)i * S + lf];
                         d.om[f * g.M + i] =
                             kMin ? with_sign(p.alpha * abs_bits(om), sign_bit(om))
-                                 : with_sign(r_psi(abs_bits(om) + OmS[(int64_t)i * S + lf]), sign_bit(om));
+                                 : with_sign(phi2(abs_bits(om) + OmS[(int64_t)i * S + lf]) * un, sign_bit(om));
                     }
             }
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
@@ -181,18 +188,18 @@ __global__ __launch_bounds__(kWave) void nms_sparse_kernel(
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) Acc[(int64_t)v * S + lf] = 0.0f;
             for (int i = 0; i < g.M; ++i) {
-                const int e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+                const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
                 float m1 = __builtin_inff(), m2 = __builtin_inff();
                 bool par = false;
                 for (int e = e0; e < e1; ++e) {
-                    const float q = Lam[(int64_t)g.col_idx[e] * S + lf] - R[(int64_t)e * S + lf];
+                    const float q = Lam[(int64_t)ldc(g.col_idx, e) * S + lf] - R[(int64_t)e * S + lf];
                     const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
                     m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
                     m1 = __builtin_fminf(m1, aq);
                     par ^= (q < 0.0f);
                 }
                 for (int e = e0; e < e1; ++e) {
-                    const int64_t iv = (int64_t)g.col_idx[e] * S + lf;
+                    const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
                     const int64_t ie = (int64_t)e * S + lf;
                     const float q = Lam[iv] - R[ie];
                     const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
@@ -231,7 +238,7 @@ __global__ __launch_bounds__(256) void syndrome_kernel(SparseDev g, const uint8_
     uint32_t bad = 0;
     for (int i = 0; i < g.M; ++i) {
         uint32_t par = 0;
-        for (int e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) par ^= bits[f * g.N + g.col_idx[e]] & 1u;
+        for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) par ^= bits[f * g.N + ldc(g.col_idx, e)] & 1u;
         bad |= par;
     }
     ok[f] = bad == 0;
