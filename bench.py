@@ -225,18 +225,23 @@ def main() -> int:
                 "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(dur * 1e3, 4),
                 "frame_sweeps_per_s": float(r["iters"].sum()) / dur}
         # The state of this kernel lives in VGPRs and LDS; its binding limit is
-        # VALU issue: SQ_INSTS_VALU per launch (committed counter pass) over the
-        # live launch duration, against 256 CU x 4 SIMD x 2.4 GHz / 4 cycles
-        # per wave64 instruction = 614.4 G wave-instructions/s.
+        # VALU issue.  Main-pipe VALU wave-instructions per launch (committed
+        # counter pass: SQ_INSTS_VALU minus the transcendentals, which gfx950
+        # runs in a separate unit) over the live launch duration, against
+        # 256 CU x 4 SIMD x 2.4 GHz / 4 cycles per wave64 instruction =
+        # 614.4 G wave-instructions/s.
         vf = ROOT / "profiles" / "valu_qc2304_cbp.json"
         if vf.exists():
             v = json.loads(vf.read_text())
-            if v.get("kernel_hash") == kernel_hash() and abs(v.get("ebn0_db", -1) - op) < 1e-9:
+            if (v.get("kernel_hash") == kernel_hash() and abs(v.get("ebn0_db", -1) - op) < 1e-9
+                    and "main_valu_wave_instructions_per_launch" in v):
                 peak = 256 * 4 * 2.4e9 / 4 / 1e9
-                a_ = v["valu_wave_instructions_per_launch"] / dur / 1e9
+                main = v["main_valu_wave_instructions_per_launch"]
+                a_ = main / dur / 1e9
                 roof_alu = {"bound": "alu", "achieved": round(a_, 2), "peak": peak,
                             "unit": "G VALU wave-instr/s", "frac": round(a_ / peak, 4),
-                            "valu_wave_instructions_per_launch": v["valu_wave_instructions_per_launch"]}
+                            "main_valu_wave_instructions_per_launch": main,
+                            "trans_wave_instructions_per_launch": v["trans_wave_instructions_per_launch"]}
 
     # ---------------- 4. the n=26112 code (streamed kernel) ----------------
     large = None

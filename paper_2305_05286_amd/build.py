@@ -26,6 +26,10 @@ FLAGS = [
     # keep the backend from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    # device code: IEEE mode off, so that fminf/fmaxf need no NaN
+    # canonicalisation of their operands (the decoders never produce NaN from
+    # finite LLRs); host code keeps full NaN semantics for option checks
+    "-Xarch_device", "-mno-amdgpu-ieee", "-Xarch_device", "-fno-honor-nans",
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
 ]
 

@@ -21,13 +21,14 @@
 // difference of phi sums.  In FP32 that difference cancels catastrophically
 // when the excluded input dominates the sum, so the kernels keep a row's
 // belief in the phi domain as (max term Mx with the sign parity in its sign
-// bit, S = sum of the other terms).  Excluding a term f that was folded in:
-//   f == Mx : the rest is S                     (no subtraction at all)
-//   else    : the rest is Mx + (S - f)          (f <= Mx, so the error of the
-//                                                 difference is <= eps * Mx)
-// which is the exclusion of eq. (equ_s3e2) / App. A (equ_ae7) without the
-// cancellation; f must be bit-identical to the folded value (cached, or
-// recomputed from the unchanged V2C value by the same code).
+// bit, S = sum of the other terms).  Excluding a term f that was folded in,
+// the rest is S + (Mx - f): 0 <= f <= Mx, so Mx - f is exact whenever f is
+// within a factor 2 of Mx (Sterbenz) and exactly 0 when f is the maximum, and
+// the result carries one rounding relative to itself, however small the rest
+// is next to the excluded term.  This is the exclusion of eq. (equ_s3e2) /
+// App. A (equ_ae7) without the cancellation; f must be bit-identical to the
+// folded value (cached, or recomputed from the unchanged V2C value by the
+// same code).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -87,7 +88,7 @@ __device__ __forceinline__ float or_sign(float mag, uint32_t sign_src) {
 
 // phi-domain magnitude of a row belief (Mx = max term, S = rest) excluding f.
 __device__ __forceinline__ float excl_sum(float Mx, float S, float f) {
-    return (f == Mx) ? S : Mx + (S - f);
+    return S + (Mx - f);
 }
 
 // Fold one phi-domain term into a (max, rest) accumulator.

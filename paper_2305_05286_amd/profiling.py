@@ -21,7 +21,8 @@ import statistics
 from pathlib import Path
 
 ROOT = Path(__file__).resolve().parents[1]
-KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp"]
+KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp",
+                  "paper_2305_05286_amd/build.py"]  # source and compile flags
 COPY_BYTES = 1 << 30
 
 
@@ -94,14 +95,27 @@ def traffic(a) -> dict:
 
 
 def valu(a) -> dict:
-    """VALU / LDS instruction counts of the CBP kernel (one counter pass)."""
-    ins = _counter(a.dir, is_cbp, "SQ_INSTS_VALU")
-    lds = _counter(a.dir, is_cbp, "SQ_INSTS_LDS")
-    waves = _counter(a.dir, is_cbp, "SQ_WAVES")
+    """VALU / LDS instruction counts of the CBP kernel (one counter pass).
+
+    gfx950 executes transcendentals (v_exp_f32, v_log_f32) in their own unit,
+    overlapped with the main VALU pipeline, so the issue bound of the main
+    pipe counts SQ_INSTS_VALU - SQ_INSTS_VALU_TRANS_F32.  VALU busy follows
+    the profiler's own derived metric: SQ_ACTIVE_INST_VALU (quad-cycles, summed
+    over all SIMDs) per CU over the GPU-active cycles of one XCD.
+    """
+    def mean(c):
+        return statistics.mean(_counter(a.dir, is_cbp, c))
+    ins, trans = mean("SQ_INSTS_VALU"), mean("SQ_INSTS_VALU_TRANS_F32")
+    active, grbm = mean("SQ_ACTIVE_INST_VALU"), mean("GRBM_GUI_ACTIVE")
+    cus, xcds = 256, 8
     return {"kernel": "qc_reg_kernel<QcGraph0, CBP>", "kernel_hash": kernel_hash(),
-            "ebn0_db": a.ebn0, "valu_wave_instructions_per_launch": statistics.mean(ins),
-            "lds_wave_instructions_per_launch": statistics.mean(lds),
-            "waves_per_launch": statistics.mean(waves)}
+            "ebn0_db": a.ebn0, "valu_wave_instructions_per_launch": ins,
+            "trans_wave_instructions_per_launch": trans,
+            "main_valu_wave_instructions_per_launch": ins - trans,
+            "lds_wave_instructions_per_launch": mean("SQ_INSTS_LDS"),
+            "waves_per_launch": mean("SQ_WAVES"),
+            "active_inst_valu_quad_cycles": active, "grbm_gui_active_all_xcds": grbm,
+            "valu_busy": active / cus / (grbm / xcds)}
 
 
 def main():
