@@ -166,6 +166,92 @@ int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch,
 int cbp_syndrome(const cbp_code_t *code, const uint8_t *bits, uint8_t *ok_out, int64_t batch,
                  void *stream);
 
+/* ---- mixed-code batches ------------------------------------------------- */
+/*
+ * One persistent launch decodes frames of several QC codes (different rates,
+ * lengths and lifting sizes Z) with per-frame early termination.  Frames wait
+ * in one queue per code; every workgroup has the same number of lanes, a
+ * multiple of each code's Z, and decodes lanes / Z frames of one code at a
+ * time, refilling a slot from the queue as soon as its frame stops; when a
+ * code's queue is empty the workgroup moves on to the next code.  Every code
+ * must offer the streamed layout (CBP_KERNEL_QC_STREAM in cbp_code_info).
+ */
+typedef struct cbp_mix cbp_mix_t;
+
+/* A plan over ncodes (1..256) QC code handles.  The handles are referenced,
+ * not copied: they must outlive the plan.  CBP_EUNSUPPORTED if a code lacks
+ * the streamed layout or the least common multiple of the Z values exceeds
+ * 1024. */
+int cbp_mix_create(const cbp_code_t *const *codes, int32_t ncodes, cbp_mix_t **out);
+void cbp_mix_free(cbp_mix_t *mix);
+
+/* Schedule of the persistent launch: lanes per workgroup (a multiple of every
+ * Z of the plan, at most 1024; it sets the frames per workgroup, lanes / Z)
+ * and workgroups per CU (0 = as many as fit).  The default is the smallest
+ * multiple of the Z values that fills whole 64-lane waves, and 0. */
+typedef struct {
+    int32_t lanes;
+    int32_t groups_per_cu;
+} cbp_mix_schedule_t;
+int cbp_mix_get_schedule(const cbp_mix_t *mix, cbp_mix_schedule_t *sched);
+int cbp_mix_set_schedule(cbp_mix_t *mix, const cbp_mix_schedule_t *sched);
+
+/* Device workspace (bytes) of cbp_mix_decode for `batch` frames on the
+ * current device under the plan's schedule; decoder as for
+ * cbp_workspace_size (0 = cbp_decode with opts->check_rule, 1 = layered
+ * NMS, 2 = flooding NMS). */
+int cbp_mix_workspace_size(const cbp_mix_t *mix, int32_t decoder, int64_t batch,
+                           const cbp_opts_t *opts, size_t *bytes);
+
+/*
+ * Decode a mixed batch with one decoder (same rules and options as the
+ * single-code entry points; state dumps are not supported here).
+ *   llr_in       device float32 [llr_elems]: the frames' channel LLRs, packed.
+ *   frame_code   device int32 [batch]: index in the plan of frame f's code.
+ *   frame_offset device int64 [batch]: element offset of frame f in llr_in and
+ *                bits_out; the frame occupies N of its code elements.
+ *   bits_out     device uint8 [llr_elems]: hard decisions at the same offsets.
+ *   iters_out    device int32 [batch]: sweeps executed; -1 for a frame whose
+ *                code index is outside the plan or whose LLRs leave
+ *                [0, llr_elems) (its decisions are not written).
+ *   workspace    device buffer of at least cbp_mix_workspace_size bytes.
+ * The call only launches kernels on `stream`: no allocation, no host
+ * synchronisation, no memset node, so it may be captured in a HIP graph once
+ * the plan has been used on the device (the first call uploads the code
+ * tables) — see cbp_mix_graph_create.
+ */
+int cbp_mix_decode(const cbp_mix_t *mix, int32_t decoder, const float *llr_in, int64_t llr_elems,
+                   const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,
+                   int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Autotuner: decodes the given batch (arguments as for cbp_mix_decode, minus
+ * the workspace) once per candidate schedule — lanes in {L, 2L, 4L} up to 1024
+ * (L = the default lanes) times workgroups per CU from 1 to what fits — timing
+ * each launch with HIP events on `stream` (the call synchronises it and
+ * allocates its own workspace), and sets the fastest as the plan's schedule.
+ * best and best_ms may be NULL.  The outputs hold the last candidate's
+ * (identical) decode.
+ */
+int cbp_mix_tune(cbp_mix_t *mix, int32_t decoder, const float *llr_in, int64_t llr_elems,
+                 const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,
+                 int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                 void *stream, cbp_mix_schedule_t *best, float *best_ms);
+
+/* A HIP graph of one cbp_mix_decode call with these arguments (captured on a
+ * private stream; every replay reads and writes the same buffers, so refill
+ * llr_in / frame_code / frame_offset in place between replays).
+ * cbp_graph_launch replays it on `stream`. */
+typedef struct cbp_graph cbp_graph_t;
+int cbp_mix_graph_create(const cbp_mix_t *mix, int32_t decoder, const float *llr_in,
+                         int64_t llr_elems, const int32_t *frame_code,
+                         const int64_t *frame_offset, uint8_t *bits_out, int32_t *iters_out,
+                         int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *workspace,
+                         size_t workspace_bytes, cbp_graph_t **out);
+int cbp_graph_launch(cbp_graph_t *graph, void *stream);
+void cbp_graph_free(cbp_graph_t *graph);
+
 /* ---- diagnostics --------------------------------------------------------- */
 const char *cbp_strerror(int status);
 const char *cbp_last_error(void);

@@ -27,13 +27,20 @@ DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2}
 EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info",
            "cbp_opts_default", "cbp_decode", "lbp_nms_decode", "fbp_nms_decode",
            "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
-           "cbp_version")
+           "cbp_version", "cbp_mix_create", "cbp_mix_free", "cbp_mix_get_schedule",
+           "cbp_mix_set_schedule", "cbp_mix_workspace_size", "cbp_mix_decode", "cbp_mix_tune",
+           "cbp_mix_graph_create", "cbp_graph_launch", "cbp_graph_free")
 
 
 class CbpError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
         self.status = status
+
+
+class MixSchedule(ctypes.Structure):
+    """Mirror of cbp_mix_schedule_t."""
+    _fields_ = [("lanes", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -87,6 +94,22 @@ def lib():
         L.cbp_last_error.restype = ctypes.c_char_p
         L.cbp_version.argtypes = []
         L.cbp_version.restype = i32
+        if not hasattr(L, "cbp_mix_create"):  # a library built before the mixed-batch entry points
+            _lib = L
+            return _lib
+        L.cbp_mix_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+        L.cbp_mix_free.argtypes = [vp]
+        L.cbp_mix_free.restype = None
+        L.cbp_mix_get_schedule.argtypes = [vp, ctypes.POINTER(MixSchedule)]
+        L.cbp_mix_set_schedule.argtypes = [vp, ctypes.POINTER(MixSchedule)]
+        L.cbp_mix_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(Opts), ctypes.POINTER(sz)]
+        mix_args = [vp, i32, vp, i64, vp, vp, vp, vp, i32, i64, ctypes.POINTER(Opts)]
+        L.cbp_mix_decode.argtypes = mix_args + [vp, sz, vp]
+        L.cbp_mix_tune.argtypes = mix_args + [vp, ctypes.POINTER(MixSchedule), ctypes.POINTER(ctypes.c_float)]
+        L.cbp_mix_graph_create.argtypes = mix_args + [vp, sz, ctypes.POINTER(vp)]
+        L.cbp_graph_launch.argtypes = [vp, vp]
+        L.cbp_graph_free.argtypes = [vp]
+        L.cbp_graph_free.restype = None
         _lib = L
     return _lib
 
@@ -248,3 +271,126 @@ def workspace_size(code: Code, decoder: str, batch: int, **kw) -> int:
 
 def version() -> int:
     return int(lib().cbp_version())
+
+
+# ---- mixed-code batches (cbp_mix_*) -----------------------------------------
+
+_MIX_ALGOS = {"cbp": (0, "log_tanh"), "cbp_nms": (0, "min_sum"), "lbp_nms": (1, "log_tanh"),
+              "fbp_nms": (2, "log_tanh")}
+
+
+class Graph:
+    """A captured cbp_mix_decode (cbp_graph_t); launch() replays it."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep  # buffers the graph reads and writes
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(lib().cbp_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cbp_graph_free(h)
+            self._h = None
+
+
+class Mix:
+    """A plan over several QC codes decoded together in one persistent launch (cbp_mix_t).
+
+    Frames are packed: frame f has code index frame_code[f] and its N LLRs start at
+    frame_offset[f] of a flat float32 tensor; decisions go to the same offsets of a flat
+    uint8 tensor."""
+
+    def __init__(self, codes):
+        self.codes = list(codes)  # the handles must outlive the plan
+        arr = (ctypes.c_void_p * len(self.codes))(*[c.handle for c in self.codes])
+        h = ctypes.c_void_p()
+        check(lib().cbp_mix_create(arr, len(self.codes), ctypes.byref(h)))
+        self._h = h
+        self.N = [c.N for c in self.codes]
+
+    @property
+    def schedule(self):
+        sc = MixSchedule()
+        check(lib().cbp_mix_get_schedule(self._h, ctypes.byref(sc)))
+        return (sc.lanes, sc.groups_per_cu)
+
+    @schedule.setter
+    def schedule(self, value):
+        sc = MixSchedule(int(value[0]), int(value[1]))
+        check(lib().cbp_mix_set_schedule(self._h, ctypes.byref(sc)))
+
+    def workspace_size(self, batch, algo="cbp", **kw):
+        dec, rule = _MIX_ALGOS[algo]
+        o = _opts(check_rule=rule, **kw)
+        n = ctypes.c_size_t()
+        check(lib().cbp_mix_workspace_size(self._h, dec, int(batch), ctypes.byref(o), ctypes.byref(n)))
+        return n.value
+
+    def _args(self, algo, llr, frame_code, frame_offset, max_iter, out, kw):
+        import torch
+        if not (llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 1 and llr.is_contiguous()):
+            raise TypeError("llr must be a contiguous 1-D float32 CUDA tensor")
+        if not (frame_code.is_cuda and frame_code.dtype == torch.int32 and frame_code.is_contiguous()):
+            raise TypeError("frame_code must be a contiguous int32 CUDA tensor")
+        if not (frame_offset.is_cuda and frame_offset.dtype == torch.int64 and frame_offset.is_contiguous()):
+            raise TypeError("frame_offset must be a contiguous int64 CUDA tensor")
+        B = frame_code.numel()
+        if frame_offset.numel() != B:
+            raise ValueError("frame_code and frame_offset differ in length")
+        if out is None:
+            bits = torch.zeros(llr.numel(), dtype=torch.uint8, device=llr.device)
+            iters = torch.empty(B, dtype=torch.int32, device=llr.device)
+        else:
+            bits, iters = out
+        dec, rule = _MIX_ALGOS[algo]
+        o = _opts(check_rule=rule, **kw)
+        args = [self._h, dec, llr.data_ptr(), llr.numel(), frame_code.data_ptr(), frame_offset.data_ptr(),
+                bits.data_ptr(), iters.data_ptr(), int(max_iter), B, ctypes.byref(o)]
+        return args, bits, iters, B
+
+    def decode(self, llr, frame_code, frame_offset, max_iter, algo="cbp", workspace=None, out=None,
+               stream=None, **kw):
+        """Returns (bits uint8 [len(llr)], iters int32 [batch]); allocates the workspace with
+        torch when none is given."""
+        import torch
+        args, bits, iters, B = self._args(algo, llr, frame_code, frame_offset, max_iter, out, kw)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_size(B, algo), dtype=torch.uint8, device=llr.device)
+        s = stream if stream is not None else torch.cuda.current_stream(llr.device)
+        with torch.cuda.device(llr.device):
+            check(lib().cbp_mix_decode(*args, workspace.data_ptr(), workspace.numel(),
+                                       ctypes.c_void_p(s.cuda_stream)))
+        return bits, iters
+
+    def tune(self, llr, frame_code, frame_offset, max_iter, algo="cbp", out=None, stream=None, **kw):
+        """Times every candidate schedule on this batch and keeps the fastest.
+        Returns ((lanes, groups_per_cu), ms)."""
+        import torch
+        args, bits, iters, B = self._args(algo, llr, frame_code, frame_offset, max_iter, out, kw)
+        s = stream if stream is not None else torch.cuda.current_stream(llr.device)
+        best, ms = MixSchedule(), ctypes.c_float()
+        with torch.cuda.device(llr.device):
+            check(lib().cbp_mix_tune(*args, ctypes.c_void_p(s.cuda_stream), ctypes.byref(best), ctypes.byref(ms)))
+        return (best.lanes, best.groups_per_cu), ms.value
+
+    def graph(self, llr, frame_code, frame_offset, max_iter, algo="cbp", workspace=None, out=None, **kw):
+        """Captures one decode of these buffers into a HIP graph.  Returns (graph, bits, iters)."""
+        import torch
+        args, bits, iters, B = self._args(algo, llr, frame_code, frame_offset, max_iter, out, kw)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_size(B, algo), dtype=torch.uint8, device=llr.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(llr.device):
+            check(lib().cbp_mix_graph_create(*args, workspace.data_ptr(), workspace.numel(), ctypes.byref(h)))
+        return Graph(h, (llr, frame_code, frame_offset, bits, iters, workspace)), bits, iters
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cbp_mix_free(h)
+            self._h = None

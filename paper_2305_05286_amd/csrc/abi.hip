@@ -43,8 +43,8 @@ struct DevTables {
     void *buf = nullptr;
     SparseDev g{};
     const int *qc_sht = nullptr;  // shift table of the register-resident kernel
-    QcStreamDev qs{};             // base structure of the streamed kernel
-    bool qs_ready = false;
+    StreamCode sc{};              // streamed kernel: base structure (device pointers)
+    const StreamCode *sc_dev = nullptr;  // the same descriptor in device memory
 };
 
 }  // namespace
@@ -61,6 +61,18 @@ struct cbp_code {
     int qE = 0, qdcmax = 0;  // base edges and max block-row degree (QC codes)
     std::mutex mu;
     DevTables dev[kMaxDevices];
+};
+
+struct cbp_mix {
+    std::vector<const cbp_code *> codes;
+    int lcm = 1, zmin = 0, zmax = 0, dcmax = 0, default_lanes = 0;
+    cbp_mix_schedule_t sched{};
+    std::mutex mu;
+    StreamCode *dev_codes[kMaxDevices] = {};  // the codes' descriptors per device
+};
+
+struct cbp_graph {
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -116,7 +128,7 @@ int check_csr(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_i
 double phi64(double x) { return std::log1p(2.0 / std::expm1(x)); }
 
 int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
-                  const int **qc_sht = nullptr, const QcStreamDev **qs = nullptr) {
+                  const int **qc_sht = nullptr, const DevTables **tab = nullptr) {
     cbp_code *c = const_cast<cbp_code *>(cc);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -136,6 +148,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         // streamed-kernel edge table (QC codes)
         std::vector<int> qt;
         int qE = 0, dcmax = 0;
+        size_t q_rstart = 0, q_er = 0, q_esh = 0, q_elast = 0, q_erec = 0, q_sc = 0;
         if (c->qc) {
             const int mb = c->mb, nb = c->nb;
             std::vector<int> rstart(mb + 1), eb, esh, er, ep, epr, epsh, efirst, elast(nb, -1);
@@ -172,11 +185,16 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
                 epr[e] = er[ep[e]];
                 epsh[e] = esh[ep[e]];
             }
-            for (auto *v : {&rstart, &eb, &esh, &er, &ep, &epr, &epsh, &efirst, &elast})
-                qt.insert(qt.end(), v->begin(), v->end());
-            // the records start 16-byte aligned in the device buffer
+            // layout (offsets in ints from the start of qt): rstart, er, esh,
+            // elast, then 16-byte aligned the edge records and the descriptor
+            q_rstart = 0;
+            for (auto *v : {&rstart, &er, &esh, &elast}) qt.insert(qt.end(), v->begin(), v->end());
+            q_er = mb + 1;
+            q_esh = q_er + qE;
+            q_elast = q_esh + qE;
             const size_t off0 = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size();
             while ((off0 + qt.size()) % 4) qt.push_back(0);
+            q_erec = qt.size();
             for (int e = 0; e < qE; ++e) {
                 const int last = elast[eb[e]] == e;
                 qt.push_back(eb[e] | last << 29 | efirst[e] << 30);
@@ -184,6 +202,8 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
                 qt.push_back(ep[e]);
                 qt.push_back(epsh[e] | epr[e] << 16);
             }
+            q_sc = qt.size();
+            qt.resize(q_sc + (sizeof(StreamCode) + 3) / 4, 0);  // filled once the device address is known
         }
         const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size() + qt.size();
         const size_t bytes = ints * 4 + (size_t)E + 64;
@@ -206,6 +226,24 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         p += N;
         if (!sht.empty()) std::memcpy(p, sht.data(), 4 * sht.size());
         p += sht.size();
+        if (c->qc) {
+            int *dq = (int *)buf + (p - host.data());  // device address of qt
+            StreamCode &sc = t.sc;
+            sc = StreamCode{};
+            sc.Z = c->Z;
+            sc.mb = c->mb;
+            sc.nb = c->nb;
+            sc.E = qE;
+            sc.dcmax = dcmax;
+            sc.N = (int64_t)c->nb * c->Z;
+            sc.rstart = dq + q_rstart;
+            sc.erec = reinterpret_cast<const int4 *>(dq + q_erec);
+            sc.elast = dq + q_elast;
+            sc.er = dq + q_er;
+            sc.esh = dq + q_esh;
+            std::memcpy(qt.data() + q_sc, &sc, sizeof sc);
+            t.sc_dev = reinterpret_cast<const StreamCode *>(dq + q_sc);
+        }
         if (!qt.empty()) std::memcpy(p, qt.data(), 4 * qt.size());
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -232,43 +270,13 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         d += N;
         t.qc_sht = sht.empty() ? nullptr : d;
         d += sht.size();
-        if (c->qc) {
-            QcStreamDev &q = t.qs;
-            q.Z = c->Z;
-            q.mb = c->mb;
-            q.nb = c->nb;
-            q.E = qE;
-            q.dcmax = dcmax;
-            q.rstart = d;
-            d += c->mb + 1;
-            q.eb = d;
-            d += qE;
-            q.esh = d;
-            d += qE;
-            q.er = d;
-            d += qE;
-            q.ep = d;
-            d += qE;
-            q.epr = d;
-            d += qE;
-            q.epsh = d;
-            d += qE;
-            q.efirst = d;
-            d += qE;
-            q.elast = d;
-            d += c->nb;
-            d = reinterpret_cast<int *>(((uintptr_t)d + 15) & ~(uintptr_t)15);
-            q.erec = reinterpret_cast<const int4 *>(d);
-            d += 4 * (size_t)qE;
-            t.qs_ready = true;
-        }
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;
     }
     *g = &t.g;
     if (qc_sht) *qc_sht = t.qc_sht;
-    if (qs) *qs = t.qs_ready ? &t.qs : nullptr;
+    if (tab) *tab = &t;
     return CBP_OK;
 }
 
@@ -338,33 +346,43 @@ int64_t sparse_chunk_frames(int algo, const SparseDev &g, int64_t batch) {
 // which bounds its workspace (e.g. 2048 x 0.68 MB for the n = 26112 code).
 constexpr int64_t kStreamMaxSlots = 2048;
 
-QcStreamDev stream_shape_of(const cbp_code_t *c) {
-    QcStreamDev q{};
-    q.Z = c->Z;
-    q.mb = c->mb;
-    q.nb = c->nb;
-    q.E = c->qE;
-    q.dcmax = c->qdcmax;
-    return q;
+// Frames per workgroup of a one-code streamed launch: whole waves where Z
+// allows it (Z = 96: two frames in three waves).
+int stream_slots(int Z) {
+    if (Z >= 64) return (Z % 64 == 0) ? 1 : (Z % 32 == 0 ? 2 : 1);
+    int s = 1;
+    while ((s * Z) % 64 != 0 && s * Z < 1024) ++s;
+    return s;
 }
 
-int64_t stream_groups_cap(const QcStreamDev &q, int64_t batch) {
-    int slots, threads;
-    size_t lds;
-    qc_stream_shape(q, &slots, &threads, &lds);
-    const int64_t need = (batch + slots - 1) / slots;
-    const int64_t cap = std::max<int64_t>(1, kStreamMaxSlots / slots);
-    return std::min(need, cap);
+// Geometry of a one-code streamed launch (groups capped by the batch and by
+// kStreamMaxSlots frames in flight; device occupancy is applied at launch).
+StreamLaunch single_stream(int algo, const cbp_code_t *c, int64_t batch) {
+    StreamLaunch L{};
+    const int SL = stream_slots(c->Z);
+    L.ncodes = 1;
+    L.lanes = SL * c->Z;
+    L.dcmax = c->qdcmax;
+    L.max_slots = SL;
+    const int64_t need = (batch + SL - 1) / SL;
+    const int64_t cap = std::max<int64_t>(1, kStreamMaxSlots / SL);
+    L.groups = (int)std::min(need, cap);
+    L.group_bytes = SL * stream_slot_bytes(algo, (int64_t)c->nb * c->Z, c->qE, c->mb, c->Z);
+    return L;
+}
+
+int device_cus(int dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 1;
+    return cus;
 }
 
 size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch) {
     if (kernel == CBP_KERNEL_QC_REG) return 256;
     if (kernel == CBP_KERNEL_QC_STREAM) {
-        const QcStreamDev q = stream_shape_of(code);
-        int slots, threads;
-        size_t lds;
-        qc_stream_shape(q, &slots, &threads, &lds);
-        return 256 + (size_t)stream_groups_cap(q, batch) * slots * qc_stream_slot_bytes(algo, q);
+        const StreamLaunch L = single_stream(algo, code, batch);
+        return 256 + (size_t)L.groups * L.group_bytes;
     }
     return sparse_ws_bytes(algo, g, sparse_chunk_frames(algo, g, batch));
 }
@@ -383,8 +401,8 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     int dev = 0;
     const SparseDev *g = nullptr;
     const int *qc_sht = nullptr;
-    const QcStreamDev *qs = nullptr;
-    rc = ensure_device(code, &dev, &g, &qc_sht, &qs);
+    const DevTables *tab = nullptr;
+    rc = ensure_device(code, &dev, &g, &qc_sht, &tab);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const size_t need = needed_ws(algo, code, *g, r.kernel, batch);
@@ -400,10 +418,23 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
         e = launch_qc_reg(code->qc_reg_id, algo, qc_sht, llr, bits, iters, batch,
                           max_iter, r.p, r.d, (int *)ws, dev, s);
     } else if (r.kernel == CBP_KERNEL_QC_STREAM) {
-        const int64_t cap = stream_groups_cap(*qs, batch);
-        const int64_t groups = std::min<int64_t>(cap, qc_stream_groups(algo, *qs, dev));
-        e = launch_qc_stream(algo, *qs, llr, bits, iters, batch, max_iter, r.p, r.d, (int)groups,
-                             (char *)ws + 256, (int *)ws, s);
+        StreamLaunch L = single_stream(algo, code, batch);
+        L.codes = tab->sc_dev;
+        if (L.group_bytes >= ((int64_t)1 << 31)) {
+            if (own) (void)hipFreeAsync(ws, s);
+            return fail(CBP_EUNSUPPORTED, "frame state above 2 GiB per workgroup");
+        }
+        const int per_cu = stream_groups_per_cu(algo, L.lanes, stream_lds_bytes(algo, L.lanes, L.dcmax, L.max_slots));
+        if (per_cu <= 0) {
+            if (own) (void)hipFreeAsync(ws, s);
+            return fail(CBP_EUNSUPPORTED, "the streamed kernel's LDS for this code (Z=%d, row degree %d) exceeds a CU",
+                        code->Z, code->qdcmax);
+        }
+        L.groups = (int)std::min<int64_t>(L.groups, (int64_t)per_cu * device_cus(dev));
+        e = launch_fill_i32((int *)ws, 1, 0, s);
+        if (e == hipSuccess)
+            e = launch_qc_stream(algo, L, llr, bits, iters, batch, nullptr, nullptr, nullptr,
+                                 (unsigned int *)ws, max_iter, r.p, r.d, (char *)ws + 256, s);
     } else {
         const int64_t chunk = sparse_chunk_frames(algo, *g, batch);
         SparseWs w = sparse_ws_carve(algo, *g, chunk, ws);
@@ -420,9 +451,339 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     return CBP_OK;
 }
 
+// ---- mixed-code batches ---------------------------------------------------
+
+int mix_ensure_device(cbp_mix *m, int *dev_out, const StreamCode **codes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CBP_EUNSUPPORTED, "device %d", dev);
+    *dev_out = dev;
+    std::lock_guard<std::mutex> lock(m->mu);
+    if (!m->dev_codes[dev]) {
+        std::vector<StreamCode> host;
+        for (const cbp_code *c : m->codes) {
+            int d2 = 0;
+            const SparseDev *g = nullptr;
+            const DevTables *tab = nullptr;
+            int rc = ensure_device(c, &d2, &g, nullptr, &tab);
+            if (rc) return rc;
+            host.push_back(tab->sc);
+        }
+        void *buf = nullptr;
+        e = hipMalloc(&buf, sizeof(StreamCode) * host.size());
+        if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+        e = hipMemcpy(buf, host.data(), sizeof(StreamCode) * host.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(buf);
+            return hip_fail(e, "hipMemcpy of the plan's code descriptors");
+        }
+        m->dev_codes[dev] = (StreamCode *)buf;
+    }
+    *codes = m->dev_codes[dev];
+    return CBP_OK;
+}
+
+int mix_algo(int32_t decoder, const cbp_opts_t *opts, int *algo) {
+    if (decoder < 0 || decoder > 2) return fail(CBP_EINVAL, "decoder must be 0, 1 or 2");
+    *algo = decoder == 0 ? ((opts && opts->check_rule == CBP_RULE_MIN_SUM) ? kCBPNMS : kCBP) : decoder;
+    return CBP_OK;
+}
+
+constexpr size_t kMixHeader = 4096;  // counter[256] (1 KB) + qstart[257] (int64)
+
+int mix_geometry(const cbp_mix *m, int algo, const cbp_mix_schedule_t &sc, int dev, int64_t batch,
+                 StreamLaunch *L) {
+    *L = StreamLaunch{};
+    L->ncodes = (int)m->codes.size();
+    L->lanes = sc.lanes;
+    L->dcmax = m->dcmax;
+    L->max_slots = sc.lanes / m->zmin;
+    const size_t lds = stream_lds_bytes(algo, L->lanes, L->dcmax, L->max_slots);
+    int per_cu = stream_groups_per_cu(algo, L->lanes, lds);
+    if (per_cu <= 0)
+        return fail(CBP_EUNSUPPORTED, "%d lanes with row degree %d need %zu B of LDS: no workgroup fits a CU",
+                    L->lanes, L->dcmax, lds);
+    if (sc.groups_per_cu > 0) per_cu = std::min(per_cu, sc.groups_per_cu);
+    int64_t groups = (int64_t)per_cu * device_cus(dev);
+    groups = std::min<int64_t>(groups, std::max<int64_t>(1, batch));
+    L->groups = (int)groups;
+    int64_t gb = 0;
+    for (const cbp_code *c : m->codes)
+        gb = std::max(gb, (int64_t)(sc.lanes / c->Z) *
+                              stream_slot_bytes(algo, (int64_t)c->nb * c->Z, c->qE, c->mb, c->Z));
+    L->group_bytes = gb;
+    if (gb >= ((int64_t)1 << 31)) return fail(CBP_EUNSUPPORTED, "workgroup workspace above 2 GiB");
+    return CBP_OK;
+}
+
+size_t mix_ws_bytes(const StreamLaunch &L, int64_t batch) {
+    const size_t perm = ((size_t)4 * batch + 255) & ~(size_t)255;
+    return kMixHeader + perm + (size_t)L.groups * L.group_bytes;
+}
+
+int mix_decode_impl(const cbp_mix *mc, int32_t decoder, const float *llr, int64_t llr_elems,
+                    const int32_t *fcode, const int64_t *foff, uint8_t *bits, int32_t *iters,
+                    int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *ws,
+                    size_t ws_bytes, void *stream, const cbp_mix_schedule_t &sched) {
+    cbp_mix *m = const_cast<cbp_mix *>(mc);
+    if (!m) return fail(CBP_EINVAL, "mix is NULL");
+    if (batch < 0 || max_iter < 0 || llr_elems < 0) return fail(CBP_EINVAL, "negative batch/max_iter/llr_elems");
+    if (batch > INT32_MAX) return fail(CBP_EINVAL, "batch above 2^31 - 1 frames");
+    int algo = 0;
+    int rc = mix_algo(decoder, opts, &algo);
+    if (rc) return rc;
+    if (batch == 0) return CBP_OK;
+    if (!llr || !fcode || !foff || !bits || !iters) return fail(CBP_EINVAL, "NULL buffer");
+    cbp_opts_t o;
+    if (opts) o = *opts;
+    else cbp_opts_default(&o);
+    o.kernel = CBP_KERNEL_QC_STREAM;  // every code of a plan has it
+    Resolved r;
+    rc = resolve_opts(m->codes[0], algo, batch, &o, &r);
+    if (rc) return rc;
+    if (r.d.sweep > 0 && r.d.frames > 0) return fail(CBP_EUNSUPPORTED, "state dumps are not available for mixed batches");
+    int dev = 0;
+    const StreamCode *dc = nullptr;
+    rc = mix_ensure_device(m, &dev, &dc);
+    if (rc) return rc;
+    StreamLaunch L;
+    rc = mix_geometry(m, algo, sched, dev, batch, &L);
+    if (rc) return rc;
+    L.codes = dc;
+    const size_t need = mix_ws_bytes(L, batch);
+    if (!ws || ws_bytes < need) return fail(CBP_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    char *w = (char *)ws;
+    unsigned int *counter = (unsigned int *)w;
+    int64_t *qstart = (int64_t *)(w + 1024);
+    int32_t *perm = (int32_t *)(w + kMixHeader);
+    char *groups = w + kMixHeader + (((size_t)4 * batch + 255) & ~(size_t)255);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_mix_prepare(fcode, foff, batch, llr_elems, dc, L.ncodes, qstart, perm, counter, iters, s);
+    if (e == hipSuccess)
+        e = launch_qc_stream(algo, L, llr, bits, iters, batch, qstart, perm, foff, counter, max_iter, r.p,
+                             r.d, groups, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return CBP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int cbp_mix_create(const cbp_code_t *const *codes, int32_t ncodes, cbp_mix_t **out) {
+    if (!out) return fail(CBP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!codes || ncodes <= 0 || ncodes > kMaxMixCodes) return fail(CBP_EINVAL, "need 1..%d codes", kMaxMixCodes);
+    cbp_mix *m = new (std::nothrow) cbp_mix;
+    if (!m) return fail(CBP_ENOMEM, "out of host memory");
+    int64_t lcm = 1;
+    for (int i = 0; i < ncodes; ++i) {
+        const cbp_code *c = codes[i];
+        if (!c) {
+            delete m;
+            return fail(CBP_EINVAL, "code %d is NULL", i);
+        }
+        if (!(c->qc && c->Z <= 1024 && c->mb < 32768 && c->nb < 65536)) {
+            delete m;
+            return fail(CBP_EUNSUPPORTED, "code %d has no streamed layout", i);
+        }
+        int64_t a = lcm, b = c->Z;
+        while (b) {
+            const int64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        lcm = lcm / a * c->Z;
+        if (lcm > 1024) {
+            delete m;
+            return fail(CBP_EUNSUPPORTED, "the Z values need workgroups of %lld lanes (> 1024)", (long long)lcm);
+        }
+        m->codes.push_back(c);
+        m->zmin = m->zmin ? std::min(m->zmin, c->Z) : c->Z;
+        m->zmax = std::max(m->zmax, c->Z);
+        m->dcmax = std::max(m->dcmax, c->qdcmax);
+    }
+    m->lcm = (int)lcm;
+    int lanes = m->lcm;
+    while (lanes % 64 != 0 && lanes * 2 <= 1024) lanes *= 2;
+    m->default_lanes = lanes;
+    m->sched.lanes = lanes;
+    m->sched.groups_per_cu = 0;
+    *out = m;
+    return CBP_OK;
+}
+
+void cbp_mix_free(cbp_mix_t *m) {
+    if (!m) return;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (int d = 0; d < kMaxDevices; ++d)
+        if (m->dev_codes[d] && hipSetDevice(d) == hipSuccess) (void)hipFree(m->dev_codes[d]);
+    if (have_cur) (void)hipSetDevice(cur);
+    delete m;
+}
+
+int cbp_mix_get_schedule(const cbp_mix_t *m, cbp_mix_schedule_t *sched) {
+    if (!m || !sched) return fail(CBP_EINVAL, "mix/sched is NULL");
+    *sched = m->sched;
+    return CBP_OK;
+}
+
+int cbp_mix_set_schedule(cbp_mix_t *m, const cbp_mix_schedule_t *sched) {
+    if (!m || !sched) return fail(CBP_EINVAL, "mix/sched is NULL");
+    if (sched->lanes <= 0 || sched->lanes > 1024 || sched->lanes % m->lcm != 0)
+        return fail(CBP_EINVAL, "lanes must be a multiple of %d in (0, 1024]", m->lcm);
+    if (sched->groups_per_cu < 0) return fail(CBP_EINVAL, "groups_per_cu < 0");
+    m->sched = *sched;
+    return CBP_OK;
+}
+
+int cbp_mix_workspace_size(const cbp_mix_t *m, int32_t decoder, int64_t batch, const cbp_opts_t *opts,
+                           size_t *bytes) {
+    if (!m || !bytes) return fail(CBP_EINVAL, "mix/bytes is NULL");
+    if (batch < 0) return fail(CBP_EINVAL, "batch < 0");
+    int algo = 0;
+    int rc = mix_algo(decoder, opts, &algo);
+    if (rc) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    StreamLaunch L;
+    rc = mix_geometry(m, algo, m->sched, dev, batch, &L);
+    if (rc) return rc;
+    *bytes = mix_ws_bytes(L, batch);
+    return CBP_OK;
+}
+
+int cbp_mix_decode(const cbp_mix_t *m, int32_t decoder, const float *llr_in, int64_t llr_elems,
+                   const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,
+                   int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                   void *workspace, size_t workspace_bytes, void *stream) {
+    if (!m) return fail(CBP_EINVAL, "mix is NULL");
+    return mix_decode_impl(m, decoder, llr_in, llr_elems, frame_code, frame_offset, bits_out, iters_out,
+                           max_iter, batch, opts, workspace, workspace_bytes, stream, m->sched);
+}
+
+int cbp_mix_tune(cbp_mix_t *m, int32_t decoder, const float *llr_in, int64_t llr_elems,
+                 const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,
+                 int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                 void *stream, cbp_mix_schedule_t *best, float *best_ms) {
+    if (!m) return fail(CBP_EINVAL, "mix is NULL");
+    if (batch <= 0) return fail(CBP_EINVAL, "tuning needs frames");
+    int algo = 0;
+    int rc = mix_algo(decoder, opts, &algo);
+    if (rc) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::vector<cbp_mix_schedule_t> cand;
+    size_t need = 0;
+    for (int lanes = m->default_lanes; lanes <= 1024 && lanes <= 4 * m->default_lanes; lanes *= 2) {
+        cbp_mix_schedule_t sc{lanes, 0};
+        StreamLaunch L;
+        if (mix_geometry(m, algo, sc, dev, batch, &L) != CBP_OK) continue;
+        const int per_cu = stream_groups_per_cu(algo, lanes, stream_lds_bytes(algo, lanes, L.dcmax, L.max_slots));
+        for (int g = 1; g <= per_cu; ++g) {
+            sc.groups_per_cu = g;
+            StreamLaunch Lg;
+            if (mix_geometry(m, algo, sc, dev, batch, &Lg) != CBP_OK) continue;
+            cand.push_back(sc);
+            need = std::max(need, mix_ws_bytes(Lg, batch));
+        }
+    }
+    if (cand.empty()) return fail(CBP_EUNSUPPORTED, "no schedule fits the device");
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = nullptr;
+    e = hipMalloc(&ws, need);
+    if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    float best_t = -1.0f;
+    cbp_mix_schedule_t best_s = m->sched;
+    for (size_t i = 0; i < cand.size() && rc == CBP_OK; ++i) {
+        // one untimed launch for the first candidate (code upload, caches)
+        for (int rep = (i == 0 ? 0 : 1); rep < 2 && rc == CBP_OK; ++rep) {
+            if (rep == 1 && (e = hipEventRecord(t0, s)) != hipSuccess) break;
+            rc = mix_decode_impl(m, decoder, llr_in, llr_elems, frame_code, frame_offset, bits_out, iters_out,
+                                 max_iter, batch, opts, ws, need, stream, cand[i]);
+            if (rep == 1 && rc == CBP_OK) e = hipEventRecord(t1, s);
+        }
+        if (rc != CBP_OK || e != hipSuccess) break;
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            best_s = cand[i];
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipFree(ws);
+    if (rc != CBP_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "timing");
+    m->sched = best_s;
+    if (best) *best = best_s;
+    if (best_ms) *best_ms = best_t;
+    return CBP_OK;
+}
+
+int cbp_mix_graph_create(const cbp_mix_t *mc, int32_t decoder, const float *llr_in, int64_t llr_elems,
+                         const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,
+                         int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                         void *workspace, size_t workspace_bytes, cbp_graph_t **out) {
+    if (!out) return fail(CBP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mc) return fail(CBP_EINVAL, "mix is NULL");
+    cbp_mix *m = const_cast<cbp_mix *>(mc);
+    // device tables first: their upload is not capturable
+    int dev = 0;
+    const StreamCode *dc = nullptr;
+    int rc = mix_ensure_device(m, &dev, &dc);
+    if (rc) return rc;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = mix_decode_impl(m, decoder, llr_in, llr_elems, frame_code, frame_offset, bits_out, iters_out, max_iter,
+                         batch, opts, workspace, workspace_bytes, cs, m->sched);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (rc == CBP_OK && e2 == hipSuccess) e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != CBP_OK) return rc;
+    if (e2 != hipSuccess) return hip_fail(e2, "graph capture");
+    cbp_graph *g = new (std::nothrow) cbp_graph;
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(CBP_ENOMEM, "out of host memory");
+    }
+    g->exec = exec;
+    *out = g;
+    return CBP_OK;
+}
+
+int cbp_graph_launch(cbp_graph_t *g, void *stream) {
+    if (!g || !g->exec) return fail(CBP_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return CBP_OK;
+}
+
+void cbp_graph_free(cbp_graph_t *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    delete g;
+}
 
 void cbp_opts_default(cbp_opts_t *o) {
     if (!o) return;

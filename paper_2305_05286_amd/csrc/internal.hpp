@@ -9,6 +9,13 @@ namespace cbp {
 // CBP_RULE_MIN_SUM).
 enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2, kCBPNMS = 3 };
 
+// Work-item and workgroup ids straight from the hardware registers.  (The
+// device code is built with relaxed NaN handling, which keeps the compiler
+// from inlining the device library's id functions: threadIdx / blockIdx would
+// become calls, with a stack frame and clobbered registers.)
+__device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int gid_x() { return (int)__builtin_amdgcn_workgroup_id_x(); }
+
 // Read of a table that no launch writes, through the constant address space:
 // where the index is wave-uniform the compiler emits a scalar load (through a
 // generic pointer it could not rule out aliasing with the kernel's stores and
@@ -61,31 +68,64 @@ hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 
-// ---- QC streamed kernels (any base matrix) ---------------------------------
-// Base structure in sweep order (block-row major, block-column ascending).
-struct QcStreamDev {
-    int Z, mb, nb, E, dcmax, slots;
-    const int *rstart;  // [mb+1] first edge of each block-row
-    const int *eb;      // [E] block-column of the edge
-    const int *esh;     // [E] circulant shift of the edge
-    const int *er;      // [E] block-row of the edge
-    const int *ep;      // [E] latest-check edge (cyclically previous block-row of the column)
-    const int *epr;     // [E] block-row of ep
-    const int *epsh;    // [E] shift of ep
-    const int *efirst;  // [E] 1 if the edge's block-row is the first of its column
-    const int *elast;   // [nb] last edge of each block-column
-    // [E] the fields the sweep reads, one 16-byte record per edge:
-    //   x = eb | last << 29 | first << 30  (last: the edge is its column's
-    //       last visit of the sweep; first: efirst), y = esh, z = ep,
-    //   w = epsh | epr << 16
+// ---- QC streamed kernels (any base matrix, any mix of codes) --------------
+// Base structure of one QC code in sweep order (block-row major, block-column
+// ascending), device pointers.  A device array of these describes the codes
+// of one launch; the kernels read it with scalar loads.
+struct StreamCode {
+    int Z, mb, nb, E, dcmax, pad0;
+    int64_t N;            // nb * Z
+    const int *rstart;    // [mb+1] first edge of each block-row
+    // [E] one 16-byte record per edge: x = block-column | last << 29 |
+    // first << 30 (last: the column's last visit of the sweep; first: the
+    // column's first block-row), y = shift, z = latest-check edge (the
+    // cyclically previous block-row of the column), w = its shift | its
+    // block-row << 16
     const int4 *erec;
+    const int *elast;     // [nb] last edge of each block-column
+    const int *er;        // [E] block-row of the edge
+    const int *esh;       // [E] shift of the edge
 };
-int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g);
-void qc_stream_shape(const QcStreamDev &g, int *slots, int *threads, size_t *lds);
-int qc_stream_groups(int algo, const QcStreamDev &g, int device);
-hipError_t launch_qc_stream(int algo, const QcStreamDev &g, const float *llr, uint8_t *bits,
-                            int32_t *iters, int64_t batch, int max_iter, const Params &p,
-                            const Dump &d, int groups, void *ws, int *counter, hipStream_t s);
+
+// Device workspace of one frame in flight (bytes, 256-aligned).
+__host__ __device__ inline int64_t stream_slot_bytes(int algo, int64_t N, int E, int mb, int Z) {
+    const bool belief = algo == kCBP || algo == kCBPNMS;
+    int64_t b = 4 * ((algo == kFBPNMS ? 2 : 1) * N + (int64_t)E * Z);
+    b = (b + 7) & ~(int64_t)7;
+    if (belief) b += 8LL * mb * Z;
+    b += N;
+    return (b + 255) & ~(int64_t)255;
+}
+
+// Geometry of one streamed launch.  Every workgroup has `lanes` threads, a
+// multiple of each code's Z, and holds lanes / Z frames of one code at a time.
+struct StreamLaunch {
+    const StreamCode *codes;  // device [ncodes]
+    int ncodes;
+    int lanes;
+    int dcmax;                // largest block-row degree over the codes
+    int max_slots;            // lanes / smallest Z
+    int groups;
+    int64_t group_bytes;      // workspace per workgroup
+};
+size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots);
+// Workgroups of the streamed kernel that fit on one CU (0 if none).
+int stream_groups_per_cu(int algo, int lanes, size_t lds);
+// Frames: queue q of code c holds perm[qstart[c] + q] (perm == NULL: frame
+// qstart[c] + q; qstart == NULL: one code, frames [0, batch)); frame f's LLRs
+// and decisions start at offset[f] (NULL: f * N).  counter[ncodes] must be 0.
+hipError_t launch_qc_stream(int algo, const StreamLaunch &L, const float *llr, uint8_t *bits,
+                            int32_t *iters, int64_t batch, const int64_t *qstart,
+                            const int32_t *perm, const int64_t *offset, unsigned int *counter,
+                            int max_iter, const Params &p, const Dump &d, void *ws, hipStream_t s);
+// Groups the frames of a mixed batch by code: writes qstart[ncodes+1],
+// perm[batch], zeroes counter[ncodes]; frames with a code index outside
+// [0, ncodes) or LLRs outside [0, llr_elems) get iters = -1 and no queue slot.
+constexpr int kMaxMixCodes = 256;
+hipError_t launch_mix_prepare(const int32_t *frame_code, const int64_t *offset, int64_t batch,
+                              int64_t llr_elems, const StreamCode *codes, int ncodes,
+                              int64_t *qstart, int32_t *perm, unsigned int *counter,
+                              int32_t *iters, hipStream_t s);
 
 // ---- QC register-resident kernels (compiled base patterns) ----------------
 // Number of compiled base patterns and the pattern table for matching.

@@ -193,8 +193,8 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     __shared__ int sBad[2][SL];
     __shared__ int sAct[SL], sFresh[SL];
 
-    const int slot = threadIdx.x / Z;
-    const int l = threadIdx.x - slot * Z;
+    const int slot = tid_x() / Z;
+    const int l = tid_x() - slot * Z;
     // The log-tanh rule keeps every LLR in log2 units (L / ln2), where one
     // function (phi2) serves both directions of the check rule; the min-sum
     // rules are linear and keep natural units.

@@ -1,6 +1,7 @@
-// Quasi-cyclic decoders for any base matrix, with the per-frame state in a
-// device workspace instead of registers (frames too large for the register
-// file, or base patterns that are not compiled in).
+// Quasi-cyclic decoders for any base matrix and any mix of codes, with the
+// per-frame state in a device workspace instead of registers (frames too
+// large for the register file, base patterns that are not compiled in, and
+// batches that mix codes, lengths and rates in one launch).
 //
 // Same mapping as the register-resident kernels: a frame occupies Z lanes,
 // lane l owns variable l of every block-column, block-rows are the layers of
@@ -10,6 +11,14 @@
 // major, block-column ascending), read through the constant address space so
 // that its wave-uniform reads are scalar loads: a vector load there would put
 // a full memory round trip in front of every state access of the edge.
+//
+// Scheduling.  The launch is persistent: every workgroup has the same number
+// of lanes, a multiple of each code's Z, and decodes lanes / Z frames of one
+// code at a time ("slots").  Frames wait in one queue per code; a slot whose
+// frame stops (at a sweep boundary, per-frame early termination) writes its
+// outputs and claims the next frame of the queue, and when a code's queue is
+// empty and its last frames are done the workgroup moves on to the next
+// code.  A single-code launch is the case of one queue.
 //
 // The kernel is bound by memory latency (a layer's accesses depend on the
 // edge table and end in a barrier), so what matters is the number of frames
@@ -40,352 +49,462 @@ struct StreamArgs {
     const float *llr;
     uint8_t *bits;
     int32_t *iters;
-    unsigned int *counter;
+    const StreamCode *codes;
+    int ncodes;
+    int lanes;
+    int xfloats;              // LDS floats of one exchange array (lanes * dcmax, even)
+    int max_slots;
+    const int64_t *qstart;    // [ncodes+1] or NULL (one code, frames [0, batch))
+    const int32_t *perm;      // frame ids grouped by code, or NULL (identity)
+    const int64_t *offset;    // element offset of each frame, or NULL (f * N)
+    unsigned int *counter;    // [ncodes] claims per queue
     int64_t batch;
     int max_iter;
     Params p;
     Dump d;
-    QcStreamDev g;
-    char *ws;           // slot workspaces, ws_stride bytes apart
-    int64_t ws_stride;
+    char *ws;                 // workgroup workspaces, group_bytes apart
+    int64_t group_bytes;
 };
+
+// A workgroup's workspace as a buffer resource (base and size in SGPRs):
+// every state access is a buffer load/store with a 32-bit lane offset, so no
+// 64-bit VGPR address is ever formed (and an offset past the end reads 0 /
+// drops the store instead of faulting).
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned int;
+struct Ws {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ float ld(uint32_t o) const {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)o, 0, 0));
+    }
+    __device__ void st(uint32_t o, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)o, 0, 0);
+    }
+    __device__ float2 ld2(uint32_t o) const {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, 0);
+        return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+    }
+    __device__ void st2(uint32_t o, float2 v) const {
+        const u32x2 u = {__float_as_uint(v.x), __float_as_uint(v.y)};
+        __builtin_amdgcn_raw_buffer_store_b64(u, r, (int)o, 0, 0);
+    }
+    __device__ uint32_t ldb(uint32_t o) const { return __builtin_amdgcn_raw_buffer_load_b8(r, (int)o, 0, 0); }
+    __device__ void stb(uint32_t o, bool v) const {
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)v, r, (int)o, 0, 0);
+    }
+};
+// raw buffer, 32-bit dword format (gfx9 family descriptor word 3)
+constexpr int kBufferWord3 = 0x00020000;
 
 struct Edge {
     int b, sh, ep, epsh, epr;
     bool last, first;
 };
-__device__ __forceinline__ Edge edge(const QcStreamDev &g, int e) {
-    const int *rec = reinterpret_cast<const int *>(g.erec) + 4 * (int64_t)e;
+__device__ __forceinline__ Edge edge(const int4 *erec, int e) {
+    const int *rec = reinterpret_cast<const int *>(erec) + 4 * (int64_t)e;
     const int x = ldc(rec, 0), w = ldc(rec, 3);
     return Edge{x & 0xffff, ldc(rec, 1), ldc(rec, 2), w & 0xffff, w >> 16, ((x >> 29) & 1) != 0,
                 ((x >> 30) & 1) != 0};
 }
 
-template <int kAlgo>
+// kDbg: the instantiation that also serves hd_mode = 1 and the state dumps
+// (cold code still costs registers in a kernel held to 64 VGPRs).
+template <int kAlgo, bool kDbg>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(STREAM_WPE_N)))
 void qc_stream_kernel(StreamArgs A) {
     extern __shared__ float smem[];
-    const QcStreamDev &g = A.g;
-    const int Z = g.Z, NB = g.nb, MB = g.mb, E = g.E;
-    const int64_t N = (int64_t)NB * Z;
-    const int SL = g.slots;
-    const int slot = threadIdx.x / Z;
-    const int l = threadIdx.x - slot * Z;
-    // LDS: exchange [SL][dcmax][Z] floats, NMS V2C stash [SL][dcmax][Z] floats,
-    // row state [SL][Z] float2, flags
-    const size_t xfloats = ((size_t)2 * SL * g.dcmax * Z + 1) & ~(size_t)1;  // keep sRow 8-byte aligned
-    float *sX = smem + (size_t)slot * g.dcmax * Z;
-    float *sQ = smem + (size_t)(SL + slot) * g.dcmax * Z;
-    float2 *sRow = reinterpret_cast<float2 *>(smem + xfloats) + (size_t)slot * Z;
-    int *sFlags = reinterpret_cast<int *>(smem + xfloats + 2 * (size_t)SL * Z);
-    unsigned int *sF = reinterpret_cast<unsigned int *>(sFlags);  // [SL]
-    int *sBad = sFlags + SL;                                        // [2][SL]
-    int *sAct = sFlags + 3 * SL;                                    // [SL]
-    int *sFresh = sFlags + 4 * SL;                                  // [SL]
-
+    using CS = const __attribute__((address_space(4))) StreamCode;
+    CS *codes = (CS *)A.codes;
     constexpr bool kBelief = kAlgo == kCBP || kAlgo == kCBPNMS;
-    const int64_t gslot = (int64_t)blockIdx.x * SL + slot;
-    char *base = A.ws + gslot * A.ws_stride;
-    float *Q = reinterpret_cast<float *>(base);
-    float *PQ = Q + N;                                     // FBP only
-    float *R = Q + (kAlgo == kFBPNMS ? 2 * N : N);
-    float2 *OM = reinterpret_cast<float2 *>(base + ((4 * ((kAlgo == kFBPNMS ? 2 : 1) * N + (int64_t)E * Z) + 7) & ~(int64_t)7));
-    uint8_t *XB = reinterpret_cast<uint8_t *>(OM + (kBelief ? (int64_t)MB * Z : 0));  // slot end = qc_stream_slot_bytes
-
     // The log-tanh rule keeps every LLR in log2 units (L / ln2), where one
     // function (phi2) serves both directions of the check rule.
     constexpr bool kLog2 = kAlgo == kCBP;
     const float us = kLog2 ? kLog2e : 1.0f;
     const float a = A.p.a * us, lmax = A.p.lmax * us, alpha = A.p.alpha;
 
-    auto load = [&](int64_t fr) {
-        for (int b = 0; b < NB; ++b) {
-            const float v = A.llr[fr * N + (int64_t)b * Z + l] * us;
-            Q[b * Z + l] = v;
-            if constexpr (kAlgo == kFBPNMS) PQ[b * Z + l] = 0.0f;
-            XB[b * Z + l] = v < 0.0f;
-        }
-        for (int e = 0; e < E; ++e) R[(int64_t)e * Z + l] = 0.0f;
-    };
+    // LDS, sized for the largest code of the launch: exchange [lanes*dcmax],
+    // NMS V2C stash [lanes*dcmax], row state [lanes] float2, 5 flag arrays
+    float *sXall = smem;
+    float *sQall = smem + A.xfloats;
+    float2 *sRowAll = reinterpret_cast<float2 *>(smem + (kBelief ? 1 : 2) * (size_t)A.xfloats);
+    int *sFlags = reinterpret_cast<int *>(sRowAll + A.lanes);
+    const int MS = A.max_slots;
+    int64_t *sF = reinterpret_cast<int64_t *>(sFlags);  // [MS] claimed queue position
+    int *sBad = sFlags + 2 * MS;                         // [2][MS]
+    int *sAct = sFlags + 4 * MS;                         // [MS]
+    int *sFresh = sFlags + 5 * MS;                       // [MS]
 
-    if (l == 0) sF[slot] = atomicAdd(A.counter, 1u);
-    __syncthreads();
-    int64_t f = sF[slot];
-    int t = 0, it = 0;
-    if (f < A.batch) load(f);
+    for (int visit = 0; visit < A.ncodes; ++visit) {
+        const int c = (int)(((unsigned)gid_x() + (unsigned)visit) % (unsigned)A.ncodes);
+        const int Z = codes[c].Z, NB = codes[c].nb, MB = codes[c].mb, E = codes[c].E;
+        const int dcm = codes[c].dcmax;
+        const int64_t N = codes[c].N;
+        const int *rstart = codes[c].rstart;
+        const int4 *erec = codes[c].erec;
+        const int64_t q0 = A.qstart ? ldc(A.qstart, c) : 0;
+        const int64_t qn = (A.qstart ? ldc(A.qstart, c + 1) : A.batch) - q0;
+        const int SL = A.lanes / Z;
+        const int slot = tid_x() / Z;
+        const int l = tid_x() - slot * Z;
+        float *sX = sXall + (size_t)slot * dcm * Z;
+        float *sQ = sQall + (size_t)slot * dcm * Z;
+        float2 *sRow = sRowAll + (size_t)slot * Z;
 
-    for (;;) {
-        // ---------------- syndrome of the current decisions --------------
-        const int pb = it & 1;
-        ++it;
-        if (l == 0) sBad[pb * SL + slot] = 0;
-        __syncthreads();  // decisions of all lanes written
-        uint32_t bad = 0;
-        for (int r = 0; r < MB; ++r) {
-            uint32_t par = 0;
-            for (int e = ldc(g.rstart, r); e < ldc(g.rstart, r + 1); ++e) {
-                const Edge ed = edge(g, e);
-                int idx = l + ed.sh;
-                idx -= (idx >= Z) ? Z : 0;
-                par ^= XB[ed.b * Z + idx];
+        // State: byte offsets of this slot's arrays in the workgroup's buffer.
+        const Ws W{__builtin_amdgcn_make_buffer_rsrc(A.ws + (int64_t)gid_x() * A.group_bytes, 0,
+                                                     (int)A.group_bytes, kBufferWord3)};
+        const uint32_t oQ = (uint32_t)(slot * stream_slot_bytes(kAlgo, N, E, MB, Z));
+        const uint32_t oPQ = oQ + 4u * (uint32_t)N;
+        const uint32_t oR = oQ + 4u * (uint32_t)((kAlgo == kFBPNMS ? 2 : 1) * N);
+        const uint32_t oOM = (oR + 4u * (uint32_t)(E * Z) + 7u) & ~7u;
+        const uint32_t oXB = oOM + (kBelief ? 8u * (uint32_t)(MB * Z) : 0u);
+
+        // frame id and element offset of queue position k
+        auto frame_of = [&](int64_t k) -> int { return A.perm ? A.perm[q0 + k] : (int)(q0 + k); };
+        auto offset_of = [&](int fr) -> int64_t { return A.offset ? A.offset[fr] : (int64_t)fr * N; };
+
+        auto load = [&](int64_t fo) {
+            for (int b = 0; b < NB; ++b) {
+                const float v = A.llr[fo + (int64_t)b * Z + l] * us;
+                W.st(oQ + 4u * (b * Z + l), v);
+                if constexpr (kAlgo == kFBPNMS) W.st(oPQ + 4u * (b * Z + l), 0.0f);
+                W.stb(oXB + b * Z + l, v < 0.0f);
             }
-            bad |= par;
-        }
-        if (bad) sBad[pb * SL + slot] = 1;
+            for (int e = 0; e < E; ++e) W.st(oR + 4u * (e * Z + l), 0.0f);
+        };
+
+        if (l == 0) sF[slot] = (int64_t)atomicAdd(A.counter + c, 1u);
         __syncthreads();
-        const bool ok = sBad[pb * SL + slot] == 0;
-        const bool have = f < A.batch;
-        const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok);
-        const bool claim = done && have;
-        if (claim) {
-            for (int b = 0; b < NB; ++b) A.bits[f * N + (int64_t)b * Z + l] = XB[b * Z + l];
+        int64_t k = sF[slot];
+        bool have = k < qn;
+        int f = have ? frame_of(k) : 0;
+        int64_t fo = have ? offset_of(f) : 0;
+        int t = 0, it = 0;
+        if (have) load(fo);
+
+        for (;;) {
+            // ---------------- syndrome of the current decisions ----------
+            const int pb = it & 1;
+            ++it;
+            if (l == 0) sBad[pb * MS + slot] = 0;
+            __syncthreads();  // decisions of all lanes written
+            uint32_t bad = 0;
+            for (int r = 0; r < MB; ++r) {
+                uint32_t par = 0;
+                for (int e = ldc(rstart, r); e < ldc(rstart, r + 1); ++e) {
+                    const Edge ed = edge(erec, e);
+                    int idx = l + ed.sh;
+                    idx -= (idx >= Z) ? Z : 0;
+                    par ^= W.ldb(oXB + ed.b * Z + idx);
+                }
+                bad |= par;
+            }
+            if (bad) sBad[pb * MS + slot] = 1;
+            __syncthreads();
+            const bool ok = sBad[pb * MS + slot] == 0;
+            const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok);
+            const bool claim = done && have;
+            if (claim) {
+                for (int b = 0; b < NB; ++b) A.bits[fo + (int64_t)b * Z + l] = (uint8_t)W.ldb(oXB + b * Z + l);
+                if (l == 0) {
+                    A.iters[f] = t;
+                    sF[slot] = (int64_t)atomicAdd(A.counter + c, 1u);
+                }
+            }
+            __syncthreads();
+            if (claim) {
+                k = sF[slot];
+                have = k < qn;
+                t = 0;
+                if (have) {
+                    f = frame_of(k);
+                    fo = offset_of(f);
+                    load(fo);
+                }
+            }
             if (l == 0) {
-                A.iters[f] = t;
-                sF[slot] = atomicAdd(A.counter, 1u);
+                sAct[slot] = have;
+                sFresh[slot] = claim && have;
             }
-        }
-        __syncthreads();
-        if (claim) {
-            f = sF[slot];
-            t = 0;
-            if (f < A.batch) load(f);
-        }
-        if (l == 0) {
-            sAct[slot] = f < A.batch;
-            sFresh[slot] = claim && f < A.batch;
-        }
-        __syncthreads();
-        bool anyAct = false, anyFresh = false;
-        for (int s = 0; s < SL; ++s) {
-            anyAct |= sAct[s] != 0;
-            anyFresh |= sFresh[s] != 0;
-        }
-        if (!anyAct) break;
-        if (anyFresh) continue;
+            __syncthreads();
+            bool anyAct = false, anyFresh = false;
+            for (int s2 = 0; s2 < SL; ++s2) {
+                anyAct |= sAct[s2] != 0;
+                anyFresh |= sFresh[s2] != 0;
+            }
+            if (!anyAct) break;
+            if (anyFresh) continue;
 
-        // ---------------- one sweep ---------------------------------------
-        const bool first = (t == 0);
-        for (int r = 0; r < MB; ++r) {
-            const int e0 = ldc(g.rstart, r), e1 = ldc(g.rstart, r + 1);
-            // phase 1: lane = variable
-            for (int e = e0; e < e1; ++e) {
-                const Edge ed = edge(g, e);
-                const int iv = ed.b * Z + l;
-                int kc = l - ed.sh;
-                kc += (kc < 0) ? Z : 0;
-                if constexpr (kBelief) {
-                    const float q = Q[iv];
-                    float rn = 0.0f;
-                    bool own = false;  // R(c_j -> v) is R(c_i -> v): a degree-1 column
-                    if (!(first && ed.first)) {
-                        int kp = l - ed.epsh;
-                        kp += (kp < 0) ? Z : 0;
-                        const float2 om = OM[ed.epr * Z + kp];
-                        if constexpr (kAlgo == kCBP) {
-                            // Q_v is still the V2C value whose phi2 c_j folded
-                            const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
-                            rn = with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
-                        } else {
-                            const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
-                            const float m1 = abs_bits(om.x);
-                            rn = with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
-                        }
-                        R[(int64_t)ed.ep * Z + l] = rn;  // commit R(c_j -> v) first
-                        own = ed.ep == e;
-                    }
-                    const float lam = q + rn;
-                    if (ed.last) XB[iv] = lam < 0.0f;  // v's last visit of the sweep decides
-                    const float qn = lam - (own ? rn : R[(int64_t)e * Z + l]);
-                    const float fq = kAlgo == kCBP ? phi2_clamped(qn, a, lmax)
-                                                   : __builtin_fminf(__builtin_fabsf(qn), lmax);
-                    Q[iv] = qn;
-                    sX[(e - e0) * Z + kc] = with_sign(fq, qn < 0.0f);
-                } else {
-                    const float q = Q[iv] - R[(int64_t)e * Z + l];
-                    sQ[(e - e0) * Z + l] = q;  // kept for phase 3
-                    sX[(e - e0) * Z + kc] = with_sign(__builtin_fminf(__builtin_fabsf(q), lmax), q < 0.0f);
-                }
-            }
-            __syncthreads();
-            // phase 2: lane = row l of layer r
-            {
-                bool par = false;
-                if constexpr (kAlgo == kCBP) {
-                    float Mx = 0.0f, Sr = 0.0f;
-                    for (int j = 0; j < e1 - e0; ++j) {
-                        const float x = sX[j * Z + l];
-                        par ^= sign_bit(x);
-                        fold(Mx, Sr, abs_bits(x));
-                    }
-                    OM[r * Z + l] = make_float2(with_sign(Mx, par), Sr);
-                } else {
-                    float m1 = __builtin_inff(), m2 = __builtin_inff();
-                    for (int j = 0; j < e1 - e0; ++j) {
-                        const float x = sX[j * Z + l];
-                        par ^= sign_bit(x);
-                        const float ax = abs_bits(x);
-                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
-                        m1 = __builtin_fminf(m1, ax);
-                    }
-                    if constexpr (kBelief) OM[r * Z + l] = make_float2(with_sign(m1, par), m2);
-                    else sRow[l] = make_float2(with_sign(m1, par), m2);
-                }
-            }
-            __syncthreads();
-            if constexpr (!kBelief) {
-                // phase 3: lane = variable
+            // ---------------- one sweep -----------------------------------
+            const bool first = (t == 0);
+            for (int r = 0; r < MB; ++r) {
+                const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
+                // phase 1: lane = variable
                 for (int e = e0; e < e1; ++e) {
-                    const Edge ed = edge(g, e);
+                    const Edge ed = edge(erec, e);
                     const int iv = ed.b * Z + l;
                     int kc = l - ed.sh;
                     kc += (kc < 0) ? Z : 0;
-                    const float2 rw = sRow[kc];
-                    const float q = sQ[(e - e0) * Z + l];
-                    const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
-                    const float m1 = abs_bits(rw.x);
-                    const float rn = with_sign(alpha * ((aq == m1) ? rw.y : m1), sign_bit(rw.x) ^ (q < 0.0f));
-                    R[(int64_t)e * Z + l] = rn;
-                    if constexpr (kAlgo == kLBPNMS) Q[iv] = q + rn;
-                    else PQ[iv] += rn;
-                }
-            }
-        }
-        ++t;
-
-        // ---------------- end of sweep ------------------------------------
-        if constexpr (!kBelief) {
-            for (int b = 0; b < NB; ++b) {
-                const int iv = b * Z + l;
-                float lam = Q[iv];
-                if constexpr (kAlgo == kFBPNMS) {
-                    if (f < A.batch) lam = A.llr[f * N + iv] + PQ[iv];
-                    Q[iv] = lam;
-                    PQ[iv] = 0.0f;
-                }
-                XB[iv] = lam < 0.0f;
-            }
-        }
-        auto flushed = [&](int b) {
-            const int el = ldc(g.elast, b);
-            int k = l - ldc(g.esh, el);
-            k += (k < 0) ? Z : 0;
-            const float2 om = OM[ldc(g.er, el) * Z + k];
-            const float q = Q[b * Z + l];
-            if constexpr (kAlgo == kCBP) {
-                const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
-                return q + with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
-            } else {
-                const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
-                const float m1 = abs_bits(om.x);
-                return q + with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
-            }
-        };
-        if constexpr (kBelief) {
-            if (A.p.hd_mode == 1)
-                for (int b = 0; b < NB; ++b) XB[b * Z + l] = flushed(b) < 0.0f;
-        }
-        if (t == A.d.sweep && f < A.d.frames) {
-            const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
-            const float un = kLog2 ? kLn2 : 1.0f;  // dumps in natural units
-            for (int b = 0; b < NB; ++b) {
-                if constexpr (kBelief) {
-                    if (A.d.q) A.d.q[f * N + b * Z + l] = Q[b * Z + l] * un;
-                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(b) * un;
-                } else {
-                    if (A.d.lam) A.d.lam[f * N + b * Z + l] = Q[b * Z + l];
-                }
-            }
-            if (A.d.r)
-                for (int e = 0; e < E; ++e) {
-                    const int r = ldc(g.er, e);
-                    int k = l - ldc(g.esh, e);
-                    k += (k < 0) ? Z : 0;
-                    const int r0 = ldc(g.rstart, r), dc = ldc(g.rstart, r + 1) - r0;
-                    A.d.r[f * Etot + (int64_t)r0 * Z + (int64_t)k * dc + (e - r0)] = R[(int64_t)e * Z + l] * un;
-                }
-            if constexpr (kBelief) {
-                if (A.d.om)
-                    for (int r = 0; r < MB; ++r) {
-                        const float2 om = OM[r * Z + l];
-                        A.d.om[f * M + (int64_t)r * Z + l] =
-                            kAlgo == kCBP ? with_sign(phi2(abs_bits(om.x) + om.y) * un, sign_bit(om.x))
-                                          : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
+                    if constexpr (kBelief) {
+                        const float q = W.ld(oQ + 4u * iv);
+                        float rn = 0.0f;
+                        bool own = false;  // R(c_j -> v) is R(c_i -> v): a degree-1 column
+                        if (!(first && ed.first)) {
+                            int kp = l - ed.epsh;
+                            kp += (kp < 0) ? Z : 0;
+                            const float2 om = W.ld2(oOM + 8u * (ed.epr * Z + kp));
+                            if constexpr (kAlgo == kCBP) {
+                                // Q_v is still the V2C value whose phi2 c_j folded
+                                const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
+                                rn = with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
+                            } else {
+                                const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
+                                const float m1 = abs_bits(om.x);
+                                rn = with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
+                            }
+                            W.st(oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v) first
+                            own = ed.ep == e;
+                        }
+                        const float lam = q + rn;
+                        if (ed.last) W.stb(oXB + iv, lam < 0.0f);  // v's last visit of the sweep decides
+                        const float qn2 = lam - (own ? rn : W.ld(oR + 4u * (e * Z + l)));
+                        const float fq = kAlgo == kCBP ? phi2_clamped(qn2, a, lmax)
+                                                       : __builtin_fminf(__builtin_fabsf(qn2), lmax);
+                        W.st(oQ + 4u * iv, qn2);
+                        sX[(e - e0) * Z + kc] = with_sign(fq, qn2 < 0.0f);
+                    } else {
+                        const float q = W.ld(oQ + 4u * iv) - W.ld(oR + 4u * (e * Z + l));
+                        sQ[(e - e0) * Z + l] = q;  // kept for phase 3
+                        sX[(e - e0) * Z + kc] = with_sign(__builtin_fminf(__builtin_fabsf(q), lmax), q < 0.0f);
                     }
+                }
+                __syncthreads();
+                // phase 2: lane = row l of layer r
+                {
+                    bool par = false;
+                    if constexpr (kAlgo == kCBP) {
+                        float Mx = 0.0f, Sr = 0.0f;
+                        for (int j = 0; j < e1 - e0; ++j) {
+                            const float x = sX[j * Z + l];
+                            par ^= sign_bit(x);
+                            fold(Mx, Sr, abs_bits(x));
+                        }
+                        W.st2(oOM + 8u * (r * Z + l), make_float2(with_sign(Mx, par), Sr));
+                    } else {
+                        float m1 = __builtin_inff(), m2 = __builtin_inff();
+                        for (int j = 0; j < e1 - e0; ++j) {
+                            const float x = sX[j * Z + l];
+                            par ^= sign_bit(x);
+                            const float ax = abs_bits(x);
+                            m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
+                            m1 = __builtin_fminf(m1, ax);
+                        }
+                        if constexpr (kBelief) W.st2(oOM + 8u * (r * Z + l), make_float2(with_sign(m1, par), m2));
+                        else sRow[l] = make_float2(with_sign(m1, par), m2);
+                    }
+                }
+                __syncthreads();
+                if constexpr (!kBelief) {
+                    // phase 3: lane = variable
+                    for (int e = e0; e < e1; ++e) {
+                        const Edge ed = edge(erec, e);
+                        const int iv = ed.b * Z + l;
+                        int kc = l - ed.sh;
+                        kc += (kc < 0) ? Z : 0;
+                        const float2 rw = sRow[kc];
+                        const float q = sQ[(e - e0) * Z + l];
+                        const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
+                        const float m1 = abs_bits(rw.x);
+                        const float rn = with_sign(alpha * ((aq == m1) ? rw.y : m1), sign_bit(rw.x) ^ (q < 0.0f));
+                        W.st(oR + 4u * (e * Z + l), rn);
+                        if constexpr (kAlgo == kLBPNMS) W.st(oQ + 4u * iv, q + rn);
+                        else W.st(oPQ + 4u * iv, W.ld(oPQ + 4u * iv) + rn);
+                    }
+                }
+            }
+            ++t;
+
+            // ---------------- end of sweep --------------------------------
+            if constexpr (!kBelief) {
+                for (int b = 0; b < NB; ++b) {
+                    const int iv = b * Z + l;
+                    float lam = W.ld(oQ + 4u * iv);
+                    if constexpr (kAlgo == kFBPNMS) {
+                        if (have) lam = A.llr[fo + iv] + W.ld(oPQ + 4u * iv);
+                        W.st(oQ + 4u * iv, lam);
+                        W.st(oPQ + 4u * iv, 0.0f);
+                    }
+                    W.stb(oXB + iv, lam < 0.0f);
+                }
+            }
+            auto flushed = [&](int b) {
+                const int el = ldc(codes[c].elast, b);
+                int kk = l - ldc(codes[c].esh, el);
+                kk += (kk < 0) ? Z : 0;
+                const float2 om = W.ld2(oOM + 8u * (ldc(codes[c].er, el) * Z + kk));
+                const float q = W.ld(oQ + 4u * (b * Z + l));
+                if constexpr (kAlgo == kCBP) {
+                    const float dd = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a, lmax));
+                    return q + with_sign(phi2(dd), sign_bit(om.x) ^ (q < 0.0f));
+                } else {
+                    const float aq = __builtin_fminf(__builtin_fabsf(q), lmax);
+                    const float m1 = abs_bits(om.x);
+                    return q + with_sign(alpha * ((aq == m1) ? om.y : m1), sign_bit(om.x) ^ (q < 0.0f));
+                }
+            };
+            if constexpr (kBelief && kDbg) {
+                if (A.p.hd_mode == 1)
+                    for (int b = 0; b < NB; ++b) W.stb(oXB + b * Z + l, flushed(b) < 0.0f);
+            }
+            if (kDbg && have && t == A.d.sweep && f < A.d.frames) {  // one-code launches only
+                const int64_t Etot = (int64_t)E * Z, M = (int64_t)MB * Z;
+                const float un = kLog2 ? kLn2 : 1.0f;  // dumps in natural units
+                for (int b = 0; b < NB; ++b) {
+                    if constexpr (kBelief) {
+                        if (A.d.q) A.d.q[f * N + b * Z + l] = W.ld(oQ + 4u * (b * Z + l)) * un;
+                        if (A.d.lam) A.d.lam[f * N + b * Z + l] = flushed(b) * un;
+                    } else {
+                        if (A.d.lam) A.d.lam[f * N + b * Z + l] = W.ld(oQ + 4u * (b * Z + l));
+                    }
+                }
+                if (A.d.r)
+                    for (int e = 0; e < E; ++e) {
+                        const int r = ldc(codes[c].er, e);
+                        int kk = l - ldc(codes[c].esh, e);
+                        kk += (kk < 0) ? Z : 0;
+                        const int r0 = ldc(rstart, r), dc = ldc(rstart, r + 1) - r0;
+                        A.d.r[f * Etot + (int64_t)r0 * Z + (int64_t)kk * dc + (e - r0)] = W.ld(oR + 4u * (e * Z + l)) * un;
+                    }
+                if constexpr (kBelief) {
+                    if (A.d.om)
+                        for (int r = 0; r < MB; ++r) {
+                            const float2 om = W.ld2(oOM + 8u * (r * Z + l));
+                            A.d.om[f * M + (int64_t)r * Z + l] =
+                                kAlgo == kCBP ? with_sign(phi2(abs_bits(om.x) + om.y) * un, sign_bit(om.x))
+                                              : with_sign(alpha * abs_bits(om.x), sign_bit(om.x));
+                        }
+                }
             }
         }
+        __syncthreads();  // the flags are reused by the next code
     }
 }
 
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+// Groups a mixed batch by code (one workgroup): per-code histogram in LDS,
+// exclusive scan, scatter of the frame ids.  The order of the frames within
+// a code's queue is whatever the atomics give; it does not affect results.
+__global__ __launch_bounds__(1024) void mix_prepare_kernel(const int32_t *frame_code,
+                                                           const int64_t *offset, int64_t batch,
+                                                           int64_t llr_elems, const StreamCode *codes,
+                                                           int ncodes, int64_t *qstart, int32_t *perm,
+                                                           unsigned int *counter, int32_t *iters) {
+    __shared__ unsigned int hist[kMaxMixCodes];
+    __shared__ int64_t cur[kMaxMixCodes];
+    using CS = const __attribute__((address_space(4))) StreamCode;
+    CS *cs = (CS *)codes;
+    for (int i = tid_x(); i < ncodes; i += 1024) {
+        hist[i] = 0;
+        counter[i] = 0;
+    }
+    __syncthreads();
+    auto valid = [&](int64_t f, int cc) {
+        if (cc < 0 || cc >= ncodes) return false;
+        const int64_t o = offset[f];
+        return o >= 0 && o <= llr_elems - cs[cc].N;
+    };
+    for (int64_t f = tid_x(); f < batch; f += 1024) {
+        const int cc = frame_code[f];
+        if (valid(f, cc)) atomicAdd(&hist[cc], 1u);
+        else iters[f] = -1;
+    }
+    __syncthreads();
+    if (tid_x() == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < ncodes; ++i) {
+            qstart[i] = acc;
+            cur[i] = acc;
+            acc += hist[i];
+        }
+        qstart[ncodes] = acc;
+    }
+    __syncthreads();
+    for (int64_t f = tid_x(); f < batch; f += 1024) {
+        const int cc = frame_code[f];
+        if (valid(f, cc)) perm[atomicAdd((unsigned long long *)&cur[cc], 1ull)] = (int32_t)f;
+    }
+}
 
-int slots_per_group(int Z) {
-    if (Z >= 64) return (Z % 64 == 0) ? 1 : (Z % 32 == 0 ? 2 : 1);
-    int s = 1;
-    while ((s * Z) % 64 != 0 && s * Z < 1024) ++s;
-    return s;
+template <bool kDbg>
+const void *stream_kernel(int algo) {
+    return algo == kCBP      ? reinterpret_cast<const void *>(qc_stream_kernel<kCBP, kDbg>)
+           : algo == kLBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kLBPNMS, kDbg>)
+           : algo == kFBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kFBPNMS, kDbg>)
+                             : reinterpret_cast<const void *>(qc_stream_kernel<kCBPNMS, kDbg>);
+}
+
+template <bool kDbg>
+void launch_algo(int algo, dim3 grid, dim3 block, size_t lds, hipStream_t s, const StreamArgs &A) {
+    if (algo == kCBP)
+        hipLaunchKernelGGL((qc_stream_kernel<kCBP, kDbg>), grid, block, lds, s, A);
+    else if (algo == kLBPNMS)
+        hipLaunchKernelGGL((qc_stream_kernel<kLBPNMS, kDbg>), grid, block, lds, s, A);
+    else if (algo == kFBPNMS)
+        hipLaunchKernelGGL((qc_stream_kernel<kFBPNMS, kDbg>), grid, block, lds, s, A);
+    else
+        hipLaunchKernelGGL((qc_stream_kernel<kCBPNMS, kDbg>), grid, block, lds, s, A);
 }
 
 }  // namespace
 
-int64_t qc_stream_slot_bytes(int algo, const QcStreamDev &g) {
-    const int64_t N = (int64_t)g.nb * g.Z;
-    int64_t b = round_up(4 * ((algo == kFBPNMS ? 2 : 1) * N + (int64_t)g.E * g.Z), 8);
-    if (algo == kCBP || algo == kCBPNMS) b += 8LL * g.mb * g.Z;
-    b += N;
-    return round_up(b, 256);
+size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots) {
+    const bool belief = algo == kCBP || algo == kCBPNMS;
+    const size_t xfloats = ((size_t)lanes * dcmax + 1) & ~(size_t)1;
+    return 4 * xfloats * (belief ? 1 : 2) + 8 * (size_t)lanes + 4 * 6 * (size_t)max_slots;
 }
 
-void qc_stream_shape(const QcStreamDev &g, int *slots, int *threads, size_t *lds) {
-    const int SL = slots_per_group(g.Z);
-    *slots = SL;
-    *threads = SL * g.Z;
-    const size_t xfloats = ((size_t)2 * SL * g.dcmax * g.Z + 1) & ~(size_t)1;
-    *lds = xfloats * 4 + (size_t)SL * g.Z * 8 + 8 * 4 * (size_t)SL;
+int stream_groups_per_cu(int algo, int lanes, size_t lds) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stream_kernel<false>(algo), lanes, lds) != hipSuccess)
+        return 0;
+    return per_cu;
 }
 
-int qc_stream_groups(int algo, const QcStreamDev &g, int device) {
-    int slots, threads;
-    size_t lds;
-    qc_stream_shape(g, &slots, &threads, &lds);
-    int per_cu = 0, cus = 0;
-    const void *fn = algo == kCBP      ? reinterpret_cast<const void *>(qc_stream_kernel<kCBP>)
-                     : algo == kLBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kLBPNMS>)
-                     : algo == kFBPNMS ? reinterpret_cast<const void *>(qc_stream_kernel<kFBPNMS>)
-                                       : reinterpret_cast<const void *>(qc_stream_kernel<kCBPNMS>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 1;
-    return (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-}
-
-hipError_t launch_qc_stream(int algo, const QcStreamDev &g, const float *llr, uint8_t *bits,
-                            int32_t *iters, int64_t batch, int max_iter, const Params &p,
-                            const Dump &d, int groups, void *ws, int *counter, hipStream_t s) {
-    int slots, threads;
-    size_t lds;
-    qc_stream_shape(g, &slots, &threads, &lds);
+hipError_t launch_qc_stream(int algo, const StreamLaunch &L, const float *llr, uint8_t *bits,
+                            int32_t *iters, int64_t batch, const int64_t *qstart,
+                            const int32_t *perm, const int64_t *offset, unsigned int *counter,
+                            int max_iter, const Params &p, const Dump &d, void *ws, hipStream_t s) {
     StreamArgs A{};
     A.llr = llr;
     A.bits = bits;
     A.iters = iters;
-    A.counter = (unsigned int *)counter;
+    A.codes = L.codes;
+    A.ncodes = L.ncodes;
+    A.lanes = L.lanes;
+    A.xfloats = (int)(((size_t)L.lanes * L.dcmax + 1) & ~(size_t)1);
+    A.max_slots = L.max_slots;
+    A.qstart = qstart;
+    A.perm = perm;
+    A.offset = offset;
+    A.counter = counter;
     A.batch = batch;
     A.max_iter = max_iter;
     A.p = p;
     A.d = d;
-    A.g = g;
-    A.g.slots = slots;
     A.ws = (char *)ws;
-    A.ws_stride = qc_stream_slot_bytes(algo, g);
-    hipError_t err = launch_fill_i32(counter, 1, 0, s);
-    if (err != hipSuccess) return err;
-    if (algo == kCBP)
-        hipLaunchKernelGGL(qc_stream_kernel<kCBP>, dim3(groups), dim3(threads), lds, s, A);
-    else if (algo == kLBPNMS)
-        hipLaunchKernelGGL(qc_stream_kernel<kLBPNMS>, dim3(groups), dim3(threads), lds, s, A);
-    else if (algo == kFBPNMS)
-        hipLaunchKernelGGL(qc_stream_kernel<kFBPNMS>, dim3(groups), dim3(threads), lds, s, A);
-    else
-        hipLaunchKernelGGL(qc_stream_kernel<kCBPNMS>, dim3(groups), dim3(threads), lds, s, A);
+    A.group_bytes = L.group_bytes;
+    const size_t lds = stream_lds_bytes(algo, L.lanes, L.dcmax, L.max_slots);
+    const dim3 grid(L.groups), block(L.lanes);
+    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1;
+    if (dbg) launch_algo<true>(algo, grid, block, lds, s, A);
+    else launch_algo<false>(algo, grid, block, lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_mix_prepare(const int32_t *frame_code, const int64_t *offset, int64_t batch,
+                              int64_t llr_elems, const StreamCode *codes, int ncodes,
+                              int64_t *qstart, int32_t *perm, unsigned int *counter,
+                              int32_t *iters, hipStream_t s) {
+    hipLaunchKernelGGL(mix_prepare_kernel, dim3(1), dim3(1024), 0, s, frame_code, offset, batch,
+                       llr_elems, codes, ncodes, qstart, perm, counter, iters);
     return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@ namespace cbp {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kSyndromeBlock = 256;
+constexpr int kFillBlock = 256;
 
 __device__ bool lane_syndrome_ok(const SparseDev &g, const uint8_t *xb, int64_t S, int64_t lf) {
     uint32_t bad = 0;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
     Dump d) {
-    const int64_t lf = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    const int64_t lf = (int64_t)gid_x() * kWave + tid_x();
     const bool valid = lf < nf;
     const int64_t f = f0 + lf;
     const int64_t S = w.stride;
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(kWave) void nms_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
     Dump d) {
-    const int64_t lf = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    const int64_t lf = (int64_t)gid_x() * kWave + tid_x();
     const bool valid = lf < nf;
     const int64_t f = f0 + lf;
     const int64_t S = w.stride;
@@ -231,9 +233,9 @@ __global__ __launch_bounds__(kWave) void nms_sparse_kernel(
     if (active) write_out(g, xb, S, lf, bits, iters, f, max_iter);
 }
 
-__global__ __launch_bounds__(256) void syndrome_kernel(SparseDev g, const uint8_t *__restrict__ bits,
+__global__ __launch_bounds__(kSyndromeBlock) void syndrome_kernel(SparseDev g, const uint8_t *__restrict__ bits,
                                                        uint8_t *__restrict__ ok, int64_t batch) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = (int64_t)gid_x() * kSyndromeBlock + tid_x();
     if (f >= batch) return;
     uint32_t bad = 0;
     for (int i = 0; i < g.M; ++i) {
@@ -244,8 +246,8 @@ __global__ __launch_bounds__(256) void syndrome_kernel(SparseDev g, const uint8_
     ok[f] = bad == 0;
 }
 
-__global__ void fill_i32_kernel(int *p, int n, int value) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kFillBlock) void fill_i32_kernel(int *p, int n, int value) {
+    const int i = gid_x() * kFillBlock + tid_x();
     if (i < n) p[i] = value;
 }
 
@@ -307,13 +309,14 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
 
 hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
                            hipStream_t s) {
-    const dim3 grid((unsigned)((batch + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((batch + kSyndromeBlock - 1) / kSyndromeBlock)), block(kSyndromeBlock);
     hipLaunchKernelGGL(syndrome_kernel, grid, block, 0, s, g, bits, ok, batch);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int *ptr, int n, int value, hipStream_t s) {
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ptr, n, value);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + kFillBlock - 1) / kFillBlock), dim3(kFillBlock), 0, s, ptr,
+                       n, value);
     return hipGetLastError();
 }
 

@@ -74,3 +74,36 @@ def test_frames_prefix_and_statistics():
     assert abs(z.mean() / (2 / s2) - 1) < 0.01
     assert abs(z.var() / (4 / s2) - 1) < 0.02
     assert l2.dtype == np.float32
+
+
+# ---- mixed-code workload ---------------------------------------------------
+
+def test_mixed_family_shapes_and_codewords():
+    from paper_2305_05286_amd.workload import RATES, Z_VALUES, make_mixed_batch, mixed_family
+    fam = mixed_family()
+    assert len(fam) == len(RATES) * len(Z_VALUES)
+    rates = sorted({round(c.K / c.N, 4) for c in fam})
+    assert rates == sorted(round(k, 4) for k in (1 / 3, 1 / 2, 2 / 3, 5 / 6, 8 / 9))
+    assert sorted({c.Z for c in fam}) == list(Z_VALUES)
+    for c in fam:
+        assert c.M == c.N - c.K                       # staircase parity part: full rank
+        mb, nb = c.shifts.shape
+        kb = nb - mb
+        par = (c.shifts[:, kb:] >= 0).astype(int)     # strict lower dual-diagonal
+        assert (par == np.eye(mb, dtype=int) + np.eye(mb, k=-1, dtype=int)).all()
+    b = make_mixed_batch(fam, 600, key=(9,))
+    assert b["llr"].dtype == np.float32 and b["offset"].dtype == np.int64
+    lens = np.array([fam[i].N for i in b["code"]])
+    assert (np.diff(b["offset"]) == lens[:-1]).all() and b["offset"][0] == 0
+    assert b["llr"].size == lens.sum()
+    assert (b["ebn0"] >= 0).all() and (b["ebn0"] <= 4).all()
+    assert len(set(b["code"].tolist())) == len(fam)    # 600 frames reach every code
+    for c in range(len(fam)):
+        fr = np.nonzero(b["code"] == c)[0][:3]
+        words = np.stack([b["codeword"][b["offset"][f]:b["offset"][f] + fam[c].N] for f in fr])
+        assert (syndrome(fam[c], words) == 0).all()
+        # LLR sign follows the codeword at high SNR on average
+        llr = np.concatenate([b["llr"][b["offset"][f]:b["offset"][f] + fam[c].N] for f in fr])
+        assert ((llr < 0) == np.concatenate(list(words)).astype(bool)).mean() > 0.8
+    again = make_mixed_batch(fam, 600, key=(9,))
+    assert (again["llr"] == b["llr"]).all() and (again["code"] == b["code"]).all()
