@@ -85,6 +85,8 @@ def main() -> int:
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n=26112 code (streamed kernel) section")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-code batch (25 QC codes in one persistent launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -276,7 +278,67 @@ def main() -> int:
             log(f"[bench] n=26112 {algo}: {t * 1e3:.2f} ms, FER {fer:.2e}, iters {its:.2f}")
         del bl_t, bc_t, bbits, bit, bws
 
-    # ---------------- 5. CPU baseline: the FP64 oracle ----------------------
+    # ---------------- 5. mixed-code batch (one persistent launch) ----------
+    mixed = None
+    if not args.no_mixed:
+        from paper_2305_05286_amd.workload import RATES, make_mixed_batch, mixed_family
+        fam = list(mixed_family())
+        MB_, MMI = 65536, 25
+        t0 = time.perf_counter()
+        mw = make_mixed_batch(fam, MB_, key=(2026, 7))
+        log(f"[bench] mixed batch: {MB_} frames of {len(fam)} codes, {mw['llr'].size} LLRs "
+            f"({time.perf_counter() - t0:.1f}s)")
+        mix = cbp.Mix([cbp.Code.from_workload(c) for c in fam])
+        ml = torch.from_numpy(mw["llr"]).to(dev)
+        mc = torch.from_numpy(mw["code"]).to(dev)
+        mo = torch.from_numpy(mw["offset"]).to(dev)
+        mbits = torch.zeros(ml.numel(), dtype=torch.uint8, device=dev)
+        mit = torch.empty(MB_, dtype=torch.int32, device=dev)
+        k_info = np.array([fam[c].K for c in mw["code"]], dtype=np.int64)
+        sched0 = mix.schedule
+        best, tune_ms = mix.tune(ml, mc, mo, MMI, "cbp", out=(mbits, mit))
+        log(f"[bench] mixed autotuner: default schedule {sched0}, tuned {best} ({tune_ms:.2f} ms)")
+        mws = torch.empty(mix.workspace_size(MB_, "cbp"), dtype=torch.uint8, device=dev)
+
+        def mtime(fn, reps):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for s_, e_ in ev:
+                s_.record(stream)
+                fn()
+                e_.record(stream)
+            torch.cuda.synchronize()
+            return [s_.elapsed_time(e_) / 1e3 for s_, e_ in ev]
+
+        eager = mtime(lambda: mix.decode(ml, mc, mo, MMI, "cbp", workspace=mws, out=(mbits, mit)), 5)
+        graph, _, _ = mix.graph(ml, mc, mo, MMI, "cbp", workspace=mws, out=(mbits, mit))
+        graph.launch(stream)
+        gt = mtime(lambda: graph.launch(stream), args.steps)
+        bits_h, it_h = mbits.cpu().numpy(), mit.cpu().numpy()
+        ferr = np.array([(bits_h[o:o + k] != mw["codeword"][o:o + k]).any()
+                         for o, k in zip(mw["offset"], k_info)])
+        rate_of = np.array([i // (len(fam) // len(RATES)) for i in mw["code"]])
+        gsec = float(np.median(gt))
+        mixed = {"frames": MB_, "codes": len(fam), "rates": [r[0] for r in RATES],
+                 "z": sorted({c.Z for c in fam}), "ebn0_db": "U[0,4] per frame", "max_iter": MMI,
+                 "decoder": "cbp", "schedule_default": list(sched0), "schedule_tuned": list(best),
+                 "eager_ms": round(float(np.median(eager)) * 1e3, 3),
+                 "graph_ms": round(gsec * 1e3, 3),
+                 "gbps": round(float(k_info.sum()) / gsec / 1e9, 3),
+                 "frames_per_s": round(MB_ / gsec, 1), "mean_iters": round(float(it_h.mean()), 3),
+                 "fer": round(float(ferr.mean()), 5),
+                 "fer_by_rate": {RATES[r][0]: round(float(ferr[rate_of == r].mean()), 5)
+                                 for r in range(len(RATES))}}
+        for algo in ("lbp_nms",):
+            lws = torch.empty(mix.workspace_size(MB_, algo), dtype=torch.uint8, device=dev)
+            mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit))
+            lt = mtime(lambda: mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit)), 3)
+            mixed[f"{algo}_eager_ms"] = round(float(np.median(lt)) * 1e3, 3)
+            mixed[f"{algo}_mean_iters"] = round(float(mit.double().mean().item()), 3)
+        log(f"[bench] mixed cbp: eager {mixed['eager_ms']:.2f} ms, graph {mixed['graph_ms']:.2f} ms, "
+            f"{mixed['gbps']:.2f} Gbit/s, iters {mixed['mean_iters']:.2f}, FER {mixed['fer']:.3f}")
+        del ml, mc, mo, mbits, mit, mws, lws, graph
+
+    # ---------------- 6. CPU baseline: the FP64 oracle ----------------------
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -319,6 +381,7 @@ def main() -> int:
                             for a, v in results.items()},
         "matched_fer": matched or None,
         "large_code": large,
+        "mixed_batch": mixed,
         "sweep": {a: [{k: (round(x, 6) if isinstance(x, float) else x) for k, x in p.items()} for p in v]
                   for a, v in sweep.items()} if not args.no_sweep else None,
     }
