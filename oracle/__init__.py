@@ -18,6 +18,9 @@ Every function follows the paper (Guan & Liang, arXiv 2305.05286):
   min-sum check rule (alpha * sign * min of the other clamped |Q|).
 * ``algo="cbp_nms"``: CBP with the min-sum B2V/C2B of Sec. IV-D
   (parity unpinned beyond the tree and symmetry checks in the tests).
+* ``unrolled``: a fixed number of CBP sweeps whose B2V outputs are scaled and
+  offset by per-sweep, per-column weights (the differentiable decoder), with
+  the flushed soft output.
 """
 from __future__ import annotations
 
@@ -68,6 +71,8 @@ def _load():
         lib.orc_decode.restype = i
         lib.orc_decode.argtypes = [i, i, i, p, p, p, ll, i, d, d, i, i, p, p,
                                    i, ll, p, p, p, p, p, i]
+        lib.orc_unrolled.restype = i
+        lib.orc_unrolled.argtypes = [i, i, p, p, p, i, i, p, p, p, ll, d, p, i]
         _lib = lib
     return _lib
 
@@ -132,4 +137,30 @@ def decode(code, llr, max_iter: int, algo: str = "cbp", *, lmax: float = LMAX,
                         _ptr(dlam), _ptr(ops), int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_decode failed ({rc})")
+    return out
+
+
+def unrolled(code, llr, w, beta, *, grp=None, lmax: float = LMAX, nthreads: int = 0):
+    """T = len(w) sweeps of CBP with weighted B2V outputs; returns the soft output
+    float64 [B, N].  w, beta: [T, G]; grp: int [N] weight group of each variable
+    (default: the base block-column v // Z of a QC code)."""
+    lib = _load()
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    if llr.ndim != 2 or llr.shape[1] != code.N:
+        raise ValueError("llr must be [B, N]")
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    if w.ndim != 2 or beta.shape != w.shape:
+        raise ValueError("w and beta must be [T, G]")
+    T, G = w.shape
+    if grp is None:
+        grp = np.arange(code.N) // code.Z
+    grp = np.ascontiguousarray(grp, dtype=np.int32)
+    row_ptr = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    out = np.zeros(llr.shape, dtype=np.float64)
+    rc = lib.orc_unrolled(code.M, code.N, _ptr(row_ptr), _ptr(col_idx), _ptr(grp), G, T, _ptr(w),
+                          _ptr(beta), _ptr(llr), llr.shape[0], float(lmax), _ptr(out), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_unrolled failed ({rc})")
     return out

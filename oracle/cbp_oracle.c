@@ -401,6 +401,99 @@ int orc_decode(int algo, int M, int N, const int *row_ptr, const int *col_idx,
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Unrolled CBP with learnable B2V weights                             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * T sweeps of CBP (Sec. IV-C, rows in order, no stopping test) in which the
+ * B2V output R_new(c_j -> v) of eq. (equ_s4e18) is replaced, in sweep t, by
+ *     sgn(R_new) * max(w[t][grp[v]] * |R_new| - beta[t][grp[v]], 0)
+ * before it is committed (equ_s4e22) and added to Q_v (equ_s4e20); grp[v] is
+ * the variable's weight group (the base block-column of a QC code).  w = 1,
+ * beta = 0 is plain CBP.  Output: o_v = Q_v plus the same weighted B2V from
+ * v's latest check with the weights of the last sweep, the soft value whose
+ * sign is the flushed hard decision (hd_mode = 1).
+ */
+static void cbp_unrolled_frame(const graph_t *g, const float *L, int T, const int *grp, int G,
+                               const double *w, const double *beta, double lmax, double *out,
+                               double *Q, double *R, double *Om, int *last) {
+    const int M = g->M, N = g->N, E = g->E;
+    for (int v = 0; v < N; ++v) { Q[v] = (double)L[v]; last[v] = -1; }
+    for (int e = 0; e < E; ++e) R[e] = 0.0;
+    for (int i = 0; i < M; ++i) Om[i] = INFINITY;
+    for (int t = 0; t < T; ++t) {
+        for (int i = 0; i < M; ++i) {
+            double om = INFINITY;
+            for (int e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                int v = g->col_idx[e];
+                int ej = last[v];
+                double Rn = 0.0;
+                if (ej >= 0) {
+                    double r = orc_psi_minus(Om[g->row_of[ej]], Q[v], lmax);
+                    int k = t * G + grp[v];
+                    double mag = w[k] * fabs(r) - beta[k];
+                    Rn = sgn(r) * (mag > 0.0 ? mag : 0.0);
+                    R[ej] = Rn;
+                }
+                double Qn = Q[v] + Rn - R[e];
+                om = orc_psi_plus(om, Qn, lmax);
+                Q[v] = Qn;
+                last[v] = e;
+            }
+            Om[i] = om;
+        }
+    }
+    for (int v = 0; v < N; ++v) {
+        double Rn = 0.0;
+        if (last[v] >= 0) {
+            double r = orc_psi_minus(Om[g->row_of[last[v]]], Q[v], lmax);
+            int k = (T - 1) * G + grp[v];
+            double mag = w[k] * fabs(r) - beta[k];
+            Rn = sgn(r) * (mag > 0.0 ? mag : 0.0);
+        }
+        out[v] = Q[v] + Rn;
+    }
+}
+
+/*
+ * Unrolled weighted CBP on B frames.  grp: int32 [N] in [0, G); w, beta:
+ * float64 [T][G]; llr float32 [B][N]; out float64 [B][N].  Returns 0, or -1
+ * on bad arguments.
+ */
+int orc_unrolled(int M, int N, const int *row_ptr, const int *col_idx, const int *grp, int G,
+                 int T, const double *w, const double *beta, const float *llr, long long B,
+                 double lmax, double *out, int nthreads) {
+    if (M <= 0 || N <= 0 || !row_ptr || !col_idx || !grp || G <= 0 || T <= 0 || !w || !beta || B < 0)
+        return -1;
+    if (B == 0) return 0;
+    if (!llr || !out) return -1;
+    for (int v = 0; v < N; ++v)
+        if (grp[v] < 0 || grp[v] >= G) return -1;
+    graph_t g;
+    g.M = M; g.N = N; g.E = row_ptr[M]; g.row_ptr = row_ptr; g.col_idx = col_idx;
+    g.row_of = (int *)malloc(sizeof(int) * (size_t)(g.E > 0 ? g.E : 1));
+    for (int i = 0; i < M; ++i)
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) g.row_of[e] = i;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        double *Q = (double *)malloc(sizeof(double) * (size_t)N);
+        double *R = (double *)malloc(sizeof(double) * (size_t)(g.E > 0 ? g.E : 1));
+        double *Om = (double *)malloc(sizeof(double) * (size_t)M);
+        int *last = (int *)malloc(sizeof(int) * (size_t)N);
+#pragma omp for schedule(dynamic, 4)
+        for (long long f = 0; f < B; ++f)
+            cbp_unrolled_frame(&g, llr + f * (long long)N, T, grp, G, w, beta, lmax,
+                               out + f * (long long)N, Q, R, Om, last);
+        free(Q); free(R); free(Om); free(last);
+    }
+    free(g.row_of);
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
 int orc_max_threads(void) {
 #ifdef _OPENMP

@@ -341,3 +341,43 @@ def test_paper_stop_rule_agrees_at_high_snr():
     a = oracle.decode(code, llr, 30, "cbp", stop_rule=1)
     assert ((a["bits"] != cw).any(axis=1)).mean() < 0.02
     assert (a["iters"] >= 1).all()
+
+
+# ---- unrolled CBP with weighted B2V outputs (the differentiable decoder) ------
+
+def test_unrolled_unit_weights_is_cbp_flushed_posterior():
+    """w = 1, beta = 0: the soft output after T sweeps is plain CBP's flushed posterior."""
+    for name in ("qc_t64s", "reg36_n96"):
+        code = get_code(name)
+        llr, _ = make_frames(code, 2.0, 16, key=(41,))
+        T = 5
+        G = code.N // code.Z if code.Z else 1
+        grp = np.arange(code.N) // code.Z if code.Z else np.zeros(code.N, dtype=int)
+        o = oracle.unrolled(code, llr, np.ones((T, G)), np.zeros((T, G)), grp=grp)
+        d = oracle.decode(code, llr, T, "cbp", stop_rule=2, hd_mode=1, dump_sweep=T, ndump=16)
+        assert np.array_equal(o, d["Lam"]), name
+
+
+def test_unrolled_silenced_checks_return_channel_llrs():
+    code = get_code("qc_t16")
+    llr, _ = make_frames(code, 1.0, 8, key=(42,))
+    G = code.N // code.Z
+    for w, beta in ((np.zeros((3, G)), np.zeros((3, G))), (np.ones((3, G)), np.full((3, G), 1e9))):
+        assert np.array_equal(oracle.unrolled(code, llr, w, beta), llr.astype(np.float64))
+
+
+def test_unrolled_single_check_closed_form():
+    """One check of degree 3: every column has degree 1, so Q stays L and the output is
+    L_v plus the weighted tanh-rule extrinsic of the other two LLRs (eq. equ_s2e4)."""
+    code = code_from_dense(np.array([[1, 1, 1]], dtype=np.uint8))
+    rng = np.random.default_rng(43)
+    llr = rng.normal(0, 3, size=(20, 3)).astype(np.float32)
+    w = np.array([[1.3], [0.8]])
+    beta = np.array([[0.2], [0.3]])
+    o = oracle.unrolled(code, llr, w, beta, grp=np.zeros(3, dtype=int))
+    L = llr.astype(np.float64)
+    for v in range(3):
+        others = [u for u in range(3) if u != v]
+        r = 2 * np.arctanh(np.prod(np.tanh(L[:, others] / 2), axis=1))
+        expect = L[:, v] + np.sign(r) * np.maximum(w[1, 0] * np.abs(r) - beta[1, 0], 0)
+        assert np.allclose(o[:, v], expect, rtol=1e-12, atol=1e-12)
