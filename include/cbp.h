@@ -252,6 +252,47 @@ int cbp_mix_graph_create(const cbp_mix_t *mix, int32_t decoder, const float *llr
 int cbp_graph_launch(cbp_graph_t *graph, void *stream);
 void cbp_graph_free(cbp_graph_t *graph);
 
+/* ---- unrolled differentiable CBP ---------------------------------------- */
+/*
+ * A fixed number of CBP sweeps (Sec. IV-C, no stopping test) whose B2V outputs
+ * carry learnable weights: in sweep t, the B2V output R_new(c_j -> v) of eq.
+ * equ_s4e18 is replaced by
+ *     sgn(R_new) * max(w[t][b] * |R_new| - beta[t][b], 0)
+ * (b = the base block-column of v) before it is committed and added to Q_v.
+ * w = 1, beta = 0 is plain CBP.  The output is the soft value
+ * o_v = Q_v + (the same weighted B2V from v's latest check with the weights of
+ * the last sweep), in LLR units (o_v > 0 favours bit 0).  QC codes with the
+ * streamed layout only.
+ *
+ * Memory: the forward pass keeps a checkpoint of the frame state (Q, R,
+ * check-beliefs) after every sweep in the workspace; the backward pass
+ * recomputes one sweep at a time from its checkpoint and runs the adjoint
+ * backwards through it, so the workspace grows with sweeps x frame state, not
+ * with the per-edge history of all sweeps.
+ *
+ *   w, beta      device float32 [sweeps][nb] (nb = base block-columns).
+ *   llr_in       device float32 [batch][N].
+ *   soft_out     device float32 [batch][N].
+ *   grad_out     device float32 [batch][N]: dLoss/d soft_out.
+ *   grad_llr     device float32 [batch][N]: dLoss/d llr_in, or NULL.
+ *   grad_w, grad_beta  device float32 [sweeps][nb]: dLoss/dw, dLoss/dbeta
+ *                (summed over the batch; written, not accumulated).
+ *   workspace    device buffer of at least cbp_unrolled_workspace_size bytes;
+ *                cbp_unrolled_backward must get the workspace of the
+ *                cbp_unrolled_forward call with the same code, llr_in, batch,
+ *                sweeps, w and beta, unmodified in between.
+ *   opts         NULL or options (lmax is used).
+ * Deterministic: repeated calls give identical results.
+ */
+int cbp_unrolled_workspace_size(const cbp_code_t *code, int32_t sweeps, int64_t batch, size_t *bytes);
+int cbp_unrolled_forward(const cbp_code_t *code, const float *llr_in, int64_t batch, int32_t sweeps,
+                         const float *w, const float *beta, float *soft_out, const cbp_opts_t *opts,
+                         void *workspace, size_t workspace_bytes, void *stream);
+int cbp_unrolled_backward(const cbp_code_t *code, const float *llr_in, int64_t batch, int32_t sweeps,
+                          const float *w, const float *beta, const float *grad_out, float *grad_llr,
+                          float *grad_w, float *grad_beta, const cbp_opts_t *opts, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /* ---- diagnostics --------------------------------------------------------- */
 const char *cbp_strerror(int status);
 const char *cbp_last_error(void);

@@ -29,7 +29,8 @@ EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_i
            "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
            "cbp_version", "cbp_mix_create", "cbp_mix_free", "cbp_mix_get_schedule",
            "cbp_mix_set_schedule", "cbp_mix_workspace_size", "cbp_mix_decode", "cbp_mix_tune",
-           "cbp_mix_graph_create", "cbp_graph_launch", "cbp_graph_free")
+           "cbp_mix_graph_create", "cbp_graph_launch", "cbp_graph_free",
+           "cbp_unrolled_workspace_size", "cbp_unrolled_forward", "cbp_unrolled_backward")
 
 
 class CbpError(RuntimeError):
@@ -110,6 +111,10 @@ def lib():
         L.cbp_graph_launch.argtypes = [vp, vp]
         L.cbp_graph_free.argtypes = [vp]
         L.cbp_graph_free.restype = None
+        L.cbp_unrolled_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(sz)]
+        L.cbp_unrolled_forward.argtypes = [vp, vp, i64, i32, vp, vp, vp, ctypes.POINTER(Opts), vp, sz, vp]
+        L.cbp_unrolled_backward.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts),
+                                            vp, sz, vp]
         _lib = L
     return _lib
 
@@ -394,3 +399,86 @@ class Mix:
         if h is not None and _lib is not None:
             _lib.cbp_mix_free(h)
             self._h = None
+
+
+# ---- unrolled differentiable CBP (cbp_unrolled_*) ------------------------------
+
+def unrolled_workspace_size(code: Code, sweeps: int, batch: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().cbp_unrolled_workspace_size(code.handle, int(sweeps), int(batch), ctypes.byref(n)))
+    return n.value
+
+
+def _unrolled_fn():
+    import torch
+
+    class UnrolledCBPFunction(torch.autograd.Function):
+        """Soft output of `sweeps` weighted CBP sweeps; backward is the library's adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, llr, w, beta, code, sweeps, lmax):
+            if not (llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 2 and llr.shape[1] == code.N):
+                raise TypeError(f"llr must be a float32 CUDA tensor [batch, {code.N}]")
+            llr, w, beta = llr.contiguous(), w.detach().contiguous(), beta.detach().contiguous()
+            B = llr.shape[0]
+            ws = torch.empty(unrolled_workspace_size(code, sweeps, B), dtype=torch.uint8, device=llr.device)
+            out = torch.empty_like(llr)
+            o = _opts(lmax=lmax)
+            s = torch.cuda.current_stream(llr.device)
+            with torch.cuda.device(llr.device):
+                check(lib().cbp_unrolled_forward(code.handle, llr.data_ptr(), B, int(sweeps), w.data_ptr(),
+                                                 beta.data_ptr(), out.data_ptr(), ctypes.byref(o),
+                                                 ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+            ctx.save_for_backward(llr, w, beta)
+            ctx.ws, ctx.code, ctx.sweeps, ctx.lmax = ws, code, sweeps, lmax
+            return out
+
+        @staticmethod
+        def backward(ctx, gout):
+            llr, w, beta = ctx.saved_tensors
+            gout = gout.contiguous()
+            B = llr.shape[0]
+            gllr = torch.empty_like(llr) if ctx.needs_input_grad[0] else None
+            gw, gb = torch.empty_like(w), torch.empty_like(beta)
+            o = _opts(lmax=ctx.lmax)
+            s = torch.cuda.current_stream(llr.device)
+            with torch.cuda.device(llr.device):
+                check(lib().cbp_unrolled_backward(ctx.code.handle, llr.data_ptr(), B, int(ctx.sweeps),
+                                                  w.data_ptr(), beta.data_ptr(), gout.data_ptr(),
+                                                  gllr.data_ptr() if gllr is not None else None,
+                                                  gw.data_ptr(), gb.data_ptr(), ctypes.byref(o), ctx.ws.data_ptr(),
+                                                  ctx.ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+            ctx.ws = None
+            return gllr, gw, gb, None, None, None
+
+    return UnrolledCBPFunction
+
+
+_UNROLLED = None
+
+
+def unrolled_cbp(code: Code, llr, w, beta, sweeps: int, lmax: float = 20.0):
+    """Differentiable soft output [batch, N] of `sweeps` weighted CBP sweeps (autograd-aware)."""
+    global _UNROLLED
+    if _UNROLLED is None:
+        _UNROLLED = _unrolled_fn()
+    return _UNROLLED.apply(llr, w, beta, code, int(sweeps), float(lmax))
+
+
+def unrolled_module(code: Code, sweeps: int, lmax: float = 20.0):
+    """A torch.nn.Module with learnable w (init 1) and beta (init 0), [sweeps, nb]."""
+    import torch
+
+    nb = code.N // code.Z
+
+    class UnrolledCBP(torch.nn.Module):
+        def __init__(self):
+            super().__init__()
+            self.code, self.sweeps, self.lmax = code, sweeps, lmax
+            self.w = torch.nn.Parameter(torch.ones(sweeps, nb))
+            self.beta = torch.nn.Parameter(torch.zeros(sweeps, nb))
+
+        def forward(self, llr):
+            return unrolled_cbp(self.code, llr, self.w, self.beta, self.sweeps, self.lmax)
+
+    return UnrolledCBP()

@@ -571,6 +571,104 @@ int mix_decode_impl(const cbp_mix *mc, int32_t decoder, const float *llr, int64_
 
 extern "C" {
 
+// ---- unrolled differentiable CBP ------------------------------------------
+
+namespace {
+
+struct UnrolledGeom {
+    int lanes, groups;
+    int64_t gpart_bytes, group_bytes;
+};
+
+int unrolled_geom(const cbp_code_t *code, int32_t sweeps, int64_t batch, UnrolledGeom *g) {
+    if (!code) return fail(CBP_EINVAL, "code is NULL");
+    if (!(code->qc && code->Z <= 1024 && code->mb < 32768 && code->nb < 65536))
+        return fail(CBP_EUNSUPPORTED, "the unrolled decoder needs a QC code with the streamed layout");
+    if (sweeps < 1 || sweeps > 64) return fail(CBP_EINVAL, "sweeps must be in [1, 64]");
+    if (batch < 0 || batch > INT32_MAX) return fail(CBP_EINVAL, "batch out of range");
+    StreamCode sc{};
+    sc.Z = code->Z;
+    sc.mb = code->mb;
+    sc.nb = code->nb;
+    sc.E = code->qE;
+    sc.dcmax = code->qdcmax;
+    sc.N = (int64_t)code->nb * code->Z;
+    const int SL = stream_slots(code->Z);
+    g->lanes = SL * code->Z;
+    g->groups = (int)((batch + SL - 1) / SL);
+    g->group_bytes = SL * unrolled_frame_bytes(sc, sweeps);
+    if (g->group_bytes >= ((int64_t)1 << 31)) return fail(CBP_EUNSUPPORTED, "frame state above 2 GiB per workgroup");
+    g->gpart_bytes = ((int64_t)g->groups * sweeps * code->nb * 8 + 255) & ~(int64_t)255;
+    return CBP_OK;
+}
+
+int unrolled_run(bool backward, const cbp_code_t *code, const float *llr, int64_t batch, int32_t sweeps,
+                 const float *w, const float *beta, float *out, const float *gout, float *gllr, float *gw,
+                 float *gb, const cbp_opts_t *opts, void *ws, size_t ws_bytes, void *stream) {
+    UnrolledGeom G;
+    int rc = unrolled_geom(code, sweeps, batch, &G);
+    if (rc) return rc;
+    cbp_opts_t o;
+    if (opts) o = *opts;
+    else cbp_opts_default(&o);
+    o.kernel = CBP_KERNEL_QC_STREAM;
+    Resolved r;
+    rc = resolve_opts(code, kCBP, batch, &o, &r);
+    if (rc) return rc;
+    if (!w || !beta) return fail(CBP_EINVAL, "w/beta is NULL");
+    if (batch == 0) {
+        if (backward && gw && gb) {  // no frames: zero gradients
+            hipStream_t s = (hipStream_t)stream;
+            hipError_t e = launch_fill_i32((int *)gw, sweeps * code->nb, 0, s);
+            if (e == hipSuccess) e = launch_fill_i32((int *)gb, sweeps * code->nb, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+        return CBP_OK;
+    }
+    if (!llr || (!backward && !out) || (backward && (!gout || !gw || !gb)))
+        return fail(CBP_EINVAL, "NULL buffer");
+    const size_t need = (size_t)G.gpart_bytes + (size_t)G.groups * G.group_bytes;
+    if (!ws || ws_bytes < need) return fail(CBP_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    int dev = 0;
+    const SparseDev *sg = nullptr;
+    const DevTables *tab = nullptr;
+    rc = ensure_device(code, &dev, &sg, nullptr, &tab);
+    if (rc) return rc;
+    if (!unrolled_fits(tab->sc, G.lanes))
+        return fail(CBP_EUNSUPPORTED, "the unrolled decoder's LDS for this code exceeds a CU");
+    hipError_t e = launch_unrolled(backward, tab->sc, tab->sc_dev, G.lanes, G.groups, llr, batch, sweeps, w, beta,
+                                   out, gout, gllr, (float *)ws, gw, gb, r.p, (char *)ws + G.gpart_bytes,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return CBP_OK;
+}
+
+}  // namespace
+
+int cbp_unrolled_workspace_size(const cbp_code_t *code, int32_t sweeps, int64_t batch, size_t *bytes) {
+    if (!bytes) return fail(CBP_EINVAL, "bytes is NULL");
+    UnrolledGeom G;
+    int rc = unrolled_geom(code, sweeps, batch, &G);
+    if (rc) return rc;
+    *bytes = batch == 0 ? 0 : (size_t)G.gpart_bytes + (size_t)G.groups * G.group_bytes;
+    return CBP_OK;
+}
+
+int cbp_unrolled_forward(const cbp_code_t *code, const float *llr_in, int64_t batch, int32_t sweeps,
+                         const float *w, const float *beta, float *soft_out, const cbp_opts_t *opts,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+    return unrolled_run(false, code, llr_in, batch, sweeps, w, beta, soft_out, nullptr, nullptr, nullptr,
+                        nullptr, opts, workspace, workspace_bytes, stream);
+}
+
+int cbp_unrolled_backward(const cbp_code_t *code, const float *llr_in, int64_t batch, int32_t sweeps,
+                          const float *w, const float *beta, const float *grad_out, float *grad_llr,
+                          float *grad_w, float *grad_beta, const cbp_opts_t *opts, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+    return unrolled_run(true, code, llr_in, batch, sweeps, w, beta, nullptr, grad_out, grad_llr, grad_w,
+                        grad_beta, opts, workspace, workspace_bytes, stream);
+}
+
 int cbp_mix_create(const cbp_code_t *const *codes, int32_t ncodes, cbp_mix_t **out) {
     if (!out) return fail(CBP_EINVAL, "out is NULL");
     *out = nullptr;

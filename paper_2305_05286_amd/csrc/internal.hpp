@@ -127,6 +127,19 @@ hipError_t launch_mix_prepare(const int32_t *frame_code, const int64_t *offset, 
                               int64_t *qstart, int32_t *perm, unsigned int *counter,
                               int32_t *iters, hipStream_t s);
 
+// ---- unrolled differentiable CBP (one QC code, fixed sweeps) --------------
+// Device workspace of one frame (state, T checkpoints, adjoints, tape).
+int64_t unrolled_frame_bytes(const StreamCode &c, int T);
+size_t unrolled_lds_bytes(const StreamCode &c, int lanes, bool backward);
+// True if both kernels can run a workgroup of `lanes` threads on a CU.
+bool unrolled_fits(const StreamCode &c, int lanes);
+// Forward (soft output, checkpoints in ws) or backward (gradients; reads the
+// checkpoints the forward pass left in the same ws).  gpart: [groups][T][NB][2].
+hipError_t launch_unrolled(bool backward, const StreamCode &host_code, const StreamCode *dev_code, int lanes,
+                           int groups, const float *llr, int64_t batch, int T, const float *w,
+                           const float *beta, float *out, const float *gout, float *gllr, float *gpart,
+                           float *gw, float *gb, const Params &p, void *ws, hipStream_t s);
+
 // ---- QC register-resident kernels (compiled base patterns) ----------------
 // Number of compiled base patterns and the pattern table for matching.
 int qc_reg_count();

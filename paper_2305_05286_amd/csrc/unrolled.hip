@@ -1,0 +1,439 @@
+// Unrolled, differentiable CBP: a fixed number of sweeps of CBP (Sec. IV-C)
+// whose B2V outputs carry learnable weights, and its hand-written adjoint.
+//
+// In sweep t the B2V output R_new(c_j -> v) of eq. (equ_s4e18) becomes
+//     sgn(R_new) * max(w[t][b] * |R_new| - beta[t][b], 0),   b = block-column of v,
+// before it is committed (equ_s4e22) and added to Q_v (equ_s4e20); w = 1,
+// beta = 0 is plain CBP.  The output is the soft value o_v = Q_v + (the same
+// weighted B2V from v's latest check with the last sweep's weights).
+//
+// Layout and arithmetic follow the streamed QC decoder: a frame occupies Z
+// lanes, lane l owns variable l of every block-column, block-rows are layers,
+// the check-belief is kept as (max phi2 term | parity, rest of the sum), LLRs in
+// log2 units (phi2 is its own inverse there).  With w = 1, beta = 0 the forward
+// pass performs exactly the streamed kernel's operations.
+//
+// Memory: the forward pass stores the state (Q, R, Omega) at the start of every
+// sweep after the first and after the last one (checkpoints).  The backward pass
+// walks the sweeps in reverse; for each it restores the checkpoint, recomputes
+// the sweep while writing a per-edge tape (Q_v before the visit, the excluded
+// phi-domain sum, R(c_i -> v) as read, the belief's parity), then applies the
+// adjoint layer by layer in reverse order.  Adjoint state: lambda_Q [N],
+// lambda_R [E], lambda_T [M] (adjoint of each check's phi-domain total).  The
+// adjoint of a check total read by a B2V is scattered to the check's rows
+// through LDS (row k gathers from lane (k + s) mod Z), so no atomics are used and
+// the result is deterministic; weight gradients are summed per workgroup in LDS
+// and over workgroups by a fixed-order reduction kernel.
+//
+// Derivatives: g(x) = phi(x ln2)/ln2 has g'(x) = -1/sinh(x ln2); the clamp of
+// |Q| to [a, lmax] passes sign(Q) inside the interval and 0 outside; the
+// exclusion S + (Mx - f) is the check total minus f; signs carry no gradient.
+#include "internal.hpp"
+#include "phi.hpp"
+#include "stream_util.hpp"
+
+namespace cbp {
+namespace {
+
+struct UnArgs {
+    const float *llr;
+    int64_t batch;
+    int T;
+    const StreamCode *code;
+    const float *w, *beta;   // [T][NB]
+    float *out;              // forward: soft output [B][N] (natural units)
+    const float *gout;       // backward: dL/d out [B][N]
+    float *gllr;             // backward: dL/d llr [B][N] or NULL
+    float *gpart;            // backward: [groups][T][NB][2] per-workgroup weight gradients
+    char *ws;                // workgroup workspaces, group_bytes apart
+    int64_t group_bytes;
+    int64_t frame_bytes;
+    float a, lmax;           // natural units
+    int lanes;
+    int dcmax;
+};
+
+// g'(x) = -1 / sinh(x ln2), both forms evaluated and one selected
+__device__ __forceinline__ float dphi2(float x) {
+    const float y = x * kLn2;
+    const float y2 = y * y;
+    const float sh_small = y * (1.0f + y2 * (0.16666667f + y2 * (0.0083333333f + y2 * 0.00019841270f)));
+    const float t = __builtin_amdgcn_exp2f(-x);
+    const float sh_large = (1.0f - t * t) / (2.0f * t);
+    return -1.0f / (y < 0.35f ? sh_small : sh_large);
+}
+
+// d clamp(|q|) / dq
+__device__ __forceinline__ float dclamp(float q, float a2, float lmax2) {
+    const float m = __builtin_fabsf(q);
+    return (m > a2 && m < lmax2) ? (q < 0.0f ? -1.0f : 1.0f) : 0.0f;
+}
+
+__device__ __forceinline__ int wrapz(int x, int Z) {
+    x += (x < 0) ? Z : 0;
+    return x - ((x >= Z) ? Z : 0);
+}
+
+// Frame geometry inside its workgroup's buffer (byte offsets).
+struct Frame {
+    Ws W;
+    int Z, NB, MB, E, l;
+    uint32_t oQ, oR, oOM;            // working state
+    uint32_t oCk;                    // checkpoint 1 (each is `ck` bytes)
+    uint32_t ck;
+    uint32_t oLQ, oLR, oLT, oTape;   // adjoints and tape (backward)
+};
+
+__device__ __forceinline__ Frame frame_of(const UnArgs &A, int slot, int l, int Z, int NB, int MB, int E) {
+    Frame F;
+    F.W = Ws{__builtin_amdgcn_make_buffer_rsrc(A.ws + (int64_t)gid_x() * A.group_bytes, 0, (int)A.group_bytes,
+                                               kBufferWord3)};
+    F.Z = Z;
+    F.NB = NB;
+    F.MB = MB;
+    F.E = E;
+    F.l = l;
+    const uint32_t N = NB * Z, EZ = E * Z, M = MB * Z;
+    const uint32_t base = (uint32_t)(slot * A.frame_bytes);
+    F.ck = 4u * (N + EZ) + 8u * M;
+    F.oQ = base;
+    F.oR = base + 4u * N;
+    F.oOM = base + 4u * (N + EZ);
+    F.oCk = base + F.ck;
+    const uint32_t after = F.oCk + F.ck * (uint32_t)A.T;  // checkpoints 1 .. T
+    F.oLQ = after;
+    F.oLR = after + 4u * N;
+    F.oLT = after + 4u * (N + EZ);
+    F.oTape = (after + 4u * (N + EZ + M) + 15u) & ~15u;
+    return F;
+}
+
+// One sweep of weighted CBP on the working state; kTape also writes the tape.
+template <bool kTape>
+__device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const int4 *erec, int t,
+                      float *sX, float a2, float lmax2) {
+    const int Z = F.Z, l = F.l, NB = F.NB;
+    for (int r = 0; r < F.MB; ++r) {
+        const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
+        for (int e = e0; e < e1; ++e) {
+            const Edge ed = edge(erec, e);
+            const int iv = ed.b * Z + l;
+            const int kc = wrapz(l - ed.sh, Z);
+            const float q = F.W.ld(F.oQ + 4u * iv);
+            float rn = 0.0f, d = -1.0f, par = 0.0f;
+            bool own = false;
+            if (!(t == 0 && ed.first)) {
+                const float2 om = F.W.ld2(F.oOM + 8u * (ed.epr * Z + wrapz(l - ed.epsh, Z)));
+                d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
+                const int k = t * NB + ed.b;
+                const float mag = __builtin_fmaxf(ldc(A.w, k) * phi2(d) - ldc(A.beta, k) * kLog2e, 0.0f);
+                rn = with_sign(mag, sign_bit(om.x) ^ (q < 0.0f));
+                F.W.st(F.oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v) first
+                own = ed.ep == e;
+                par = sign_bit(om.x) ? 1.0f : 0.0f;
+            }
+            const float rold = own ? rn : F.W.ld(F.oR + 4u * (e * Z + l));
+            const float qn = q + rn - rold;
+            F.W.st(F.oQ + 4u * iv, qn);
+            sX[(e - e0) * Z + kc] = with_sign(phi2_clamped(qn, a2, lmax2), qn < 0.0f);
+            if constexpr (kTape) F.W.st4(F.oTape + 16u * (e * Z + l), make_float4(q, d, rold, par));
+        }
+        __syncthreads();
+        {
+            bool p = false;
+            float Mx = 0.0f, Sr = 0.0f;
+            for (int j = 0; j < e1 - e0; ++j) {
+                const float x = sX[j * Z + l];
+                p ^= sign_bit(x);
+                fold(Mx, Sr, abs_bits(x));
+            }
+            F.W.st2(F.oOM + 8u * (r * Z + l), make_float2(with_sign(Mx, p), Sr));
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void copy_state(const Frame &F, uint32_t from, uint32_t to) {
+    const int N = F.NB * F.Z, EZ = F.E * F.Z, M = F.MB * F.Z, l = F.l;
+    for (int i = l; i < N + EZ; i += F.Z) F.W.st(to + 4u * i, F.W.ld(from + 4u * i));
+    for (int i = l; i < M; i += F.Z) {
+        const uint32_t o = 4u * (N + EZ) + 8u * i;
+        F.W.st2(to + o, F.W.ld2(from + o));
+    }
+}
+
+__global__ __launch_bounds__(1024) void unrolled_fwd_kernel(UnArgs A) {
+    extern __shared__ float smem[];
+    using CS = const __attribute__((address_space(4))) StreamCode;
+    CS *cs = (CS *)A.code;
+    const int Z = cs->Z, NB = cs->nb, MB = cs->mb, E = cs->E;
+    const int64_t N = cs->N;
+    const int *rstart = cs->rstart;
+    const int4 *erec = cs->erec;
+    const int SL = A.lanes / Z;
+    const int slot = tid_x() / Z, l = tid_x() - slot * Z;
+    const int64_t f = (int64_t)gid_x() * SL + slot;
+    const bool have = f < A.batch;
+    const float a2 = A.a * kLog2e, lmax2 = A.lmax * kLog2e;
+    float *sX = smem + (size_t)slot * A.dcmax * Z;
+    const Frame F = frame_of(A, slot, l, Z, NB, MB, E);
+
+    for (int b = 0; b < NB; ++b)
+        F.W.st(F.oQ + 4u * (b * Z + l), have ? A.llr[f * N + b * Z + l] * kLog2e : 0.0f);
+    for (int e = 0; e < E; ++e) F.W.st(F.oR + 4u * (e * Z + l), 0.0f);
+    __syncthreads();
+    for (int t = 0; t < A.T; ++t) {
+        if (t > 0) copy_state(F, F.oQ, F.oCk + F.ck * (uint32_t)(t - 1));
+        sweep<false>(A, F, rstart, erec, t, sX, a2, lmax2);
+    }
+    copy_state(F, F.oQ, F.oCk + F.ck * (uint32_t)(A.T - 1));  // state after the last sweep
+    for (int b = 0; b < NB; ++b) {
+        const int el = ldc(cs->elast, b);
+        const float2 om = F.W.ld2(F.oOM + 8u * (ldc(cs->er, el) * Z + wrapz(l - ldc(cs->esh, el), Z)));
+        const float q = F.W.ld(F.oQ + 4u * (b * Z + l));
+        const float d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
+        const int k = (A.T - 1) * NB + b;
+        const float mag = __builtin_fmaxf(ldc(A.w, k) * phi2(d) - ldc(A.beta, k) * kLog2e, 0.0f);
+        const float o = q + with_sign(mag, sign_bit(om.x) ^ (q < 0.0f));
+        if (have) A.out[f * N + b * Z + l] = o * kLn2;
+    }
+}
+
+__global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
+    extern __shared__ float smem[];
+    using CS = const __attribute__((address_space(4))) StreamCode;
+    CS *cs = (CS *)A.code;
+    const int Z = cs->Z, NB = cs->nb, MB = cs->mb, E = cs->E;
+    const int64_t N = cs->N;
+    const int *rstart = cs->rstart;
+    const int4 *erec = cs->erec;
+    const int SL = A.lanes / Z;
+    const int tid = tid_x();
+    const int slot = tid / Z, l = tid - slot * Z;
+    const int64_t f = (int64_t)gid_x() * SL + slot;
+    const bool have = f < A.batch;
+    const float a2 = A.a * kLog2e, lmax2 = A.lmax * kLog2e;
+    const int DM = A.dcmax > NB ? A.dcmax : NB;
+    // LDS: exchange [SL][dcmax][Z], row adjoints [SL][Z], scatter [SL][DM][Z],
+    // weight-gradient accumulators [NB][lanes] x 2
+    float *sX = smem + (size_t)slot * A.dcmax * Z;
+    float *sLall = smem + (size_t)A.lanes * A.dcmax;
+    float *sL = sLall + (size_t)slot * Z;
+    float *sD = sLall + A.lanes + (size_t)slot * DM * Z;
+    float *sAw = sLall + A.lanes + (size_t)A.lanes * DM;
+    float *sAb = sAw + (size_t)NB * A.lanes;
+    const Frame F = frame_of(A, slot, l, Z, NB, MB, E);
+    const uint32_t oFinal = F.oCk + F.ck * (uint32_t)(A.T - 1);
+
+    for (int b = 0; b < NB; ++b) {
+        sAw[b * A.lanes + tid] = 0.0f;
+        sAb[b * A.lanes + tid] = 0.0f;
+    }
+    for (int e = 0; e < E; ++e) F.W.st(F.oLR + 4u * (e * Z + l), 0.0f);
+    for (int r = 0; r < MB; ++r) F.W.st(F.oLT + 4u * (r * Z + l), 0.0f);
+
+    // ---- adjoint of the soft output o_v = Q_v + weighted B2V (last weights)
+    for (int b = 0; b < NB; ++b) {
+        const int el = ldc(cs->elast, b);
+        const float2 om = F.W.ld2(oFinal + 4u * (uint32_t)(N + E * Z) +
+                                  8u * (ldc(cs->er, el) * Z + wrapz(l - ldc(cs->esh, el), Z)));
+        const float q = F.W.ld(oFinal + 4u * (b * Z + l));
+        const float go = have ? A.gout[f * N + b * Z + l] * kLn2 : 0.0f;
+        const float d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
+        const int k = (A.T - 1) * NB + b;
+        const float wk = ldc(A.w, k), m = phi2(d);
+        const bool act = wk * m - ldc(A.beta, k) * kLog2e > 0.0f;
+        const bool neg = sign_bit(om.x) ^ (q < 0.0f);
+        const float lmag = neg ? -go : go;            // d o / d mag = sgn
+        const float lm = act ? lmag * wk : 0.0f;
+        sAw[b * A.lanes + tid] += act ? lmag * m : 0.0f;
+        sAb[b * A.lanes + tid] += act ? -lmag : 0.0f;
+        const float ld = lm * dphi2(d);
+        const float lq = go - ld * dphi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2)) *
+                                  dclamp(q, a2, lmax2);
+        F.W.st(F.oLQ + 4u * (b * Z + l), lq);
+        sD[b * Z + l] = ld;
+    }
+    __syncthreads();
+    for (int b = 0; b < NB; ++b) {  // lane = row l of each check layer
+        const int el = ldc(cs->elast, b);
+        const uint32_t o = F.oLT + 4u * (ldc(cs->er, el) * Z + l);
+        F.W.st(o, F.W.ld(o) + sD[b * Z + wrapz(l + ldc(cs->esh, el), Z)]);
+    }
+    __syncthreads();
+
+    for (int t = A.T - 1; t >= 0; --t) {
+        // restore the state at the start of sweep t and recompute it with the tape
+        if (t > 0) {
+            copy_state(F, F.oCk + F.ck * (uint32_t)(t - 1), F.oQ);
+        } else {
+            for (int b = 0; b < NB; ++b)
+                F.W.st(F.oQ + 4u * (b * Z + l), have ? A.llr[f * N + b * Z + l] * kLog2e : 0.0f);
+            for (int e = 0; e < E; ++e) F.W.st(F.oR + 4u * (e * Z + l), 0.0f);
+        }
+        __syncthreads();
+        sweep<true>(A, F, rstart, erec, t, sX, a2, lmax2);
+
+        for (int r = MB - 1; r >= 0; --r) {
+            const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
+            {  // lane = row l: adjoint of the new total of check row l of layer r
+                const uint32_t o = F.oLT + 4u * (r * Z + l);
+                sL[l] = F.W.ld(o);
+                F.W.st(o, 0.0f);
+            }
+            __syncthreads();
+            for (int e = e0; e < e1; ++e) {  // lane = variable
+                const Edge ed = edge(erec, e);
+                const int iv = ed.b * Z + l;
+                const float4 tp = F.W.ld4(F.oTape + 16u * (e * Z + l));
+                const float q = tp.x, d = tp.y, rold = tp.z;
+                const bool has = d >= 0.0f;
+                float rn = 0.0f, m = 0.0f, wk = 0.0f;
+                bool act = false, neg = false;
+                const int k = t * NB + ed.b;
+                if (has) {
+                    wk = ldc(A.w, k);
+                    m = phi2(d);
+                    act = wk * m - ldc(A.beta, k) * kLog2e > 0.0f;
+                    neg = (tp.w != 0.0f) ^ (q < 0.0f);
+                    rn = with_sign(__builtin_fmaxf(wk * m - ldc(A.beta, k) * kLog2e, 0.0f), neg);
+                }
+                const bool own = has && ed.ep == e;
+                const float qn = q + rn - rold;
+                const float cn = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(qn), a2), lmax2);
+                const float lf = sL[wrapz(l - ed.sh, Z)];
+                const float lqn = F.W.ld(F.oLQ + 4u * iv) + lf * dphi2(cn) * dclamp(qn, a2, lmax2);
+                float lq = lqn;  // through lam = q + rn
+                float ld = 0.0f;
+                if (has) {
+                    const uint32_t oep = F.oLR + 4u * (ed.ep * Z + l);
+                    const float lrn = lqn + (own ? -lqn : 0.0f) + F.W.ld(oep);
+                    F.W.st(oep, 0.0f);  // R(c_j -> v) before the commit is dead
+                    const float lmag = neg ? -lrn : lrn;
+                    const float lm = act ? lmag * wk : 0.0f;
+                    sAw[ed.b * A.lanes + tid] += act ? lmag * m : 0.0f;
+                    sAb[ed.b * A.lanes + tid] += act ? -lmag : 0.0f;
+                    ld = lm * dphi2(d);
+                    const float cq = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2);
+                    lq -= ld * dphi2(cq) * dclamp(q, a2, lmax2);
+                }
+                if (!own) {  // R(c_i -> v) as read by this visit
+                    const uint32_t oe = F.oLR + 4u * (e * Z + l);
+                    F.W.st(oe, F.W.ld(oe) - lqn);
+                }
+                F.W.st(F.oLQ + 4u * iv, lq);
+                sD[(e - e0) * Z + l] = ld;
+            }
+            __syncthreads();
+            for (int e = e0; e < e1; ++e) {  // lane = row l of the B2V's latest check
+                const Edge ed = edge(erec, e);
+                if (t == 0 && ed.first) continue;
+                const uint32_t o = F.oLT + 4u * (ed.epr * Z + l);
+                F.W.st(o, F.W.ld(o) + sD[(e - e0) * Z + wrapz(l + ed.epsh, Z)]);
+            }
+            __syncthreads();
+        }
+        // this sweep's weight gradients: sum over the workgroup's lanes
+        for (int b = tid; b < NB; b += A.lanes) {
+            float sw = 0.0f, sb = 0.0f;
+            for (int i = 0; i < A.lanes; ++i) {
+                sw += sAw[b * A.lanes + i];
+                sb += sAb[b * A.lanes + i];
+            }
+            float *gp = A.gpart + (((int64_t)gid_x() * A.T + t) * NB + b) * 2;
+            gp[0] = sw;
+            gp[1] = sb;
+        }
+        __syncthreads();
+        for (int b = 0; b < NB; ++b) {
+            sAw[b * A.lanes + tid] = 0.0f;
+            sAb[b * A.lanes + tid] = 0.0f;
+        }
+        __syncthreads();
+    }
+    if (have && A.gllr)
+        for (int b = 0; b < NB; ++b)
+            A.gllr[f * N + b * Z + l] = F.W.ld(F.oLQ + 4u * (b * Z + l)) * kLog2e;
+}
+
+// grad_w[t][b] = sum over workgroups, in workgroup order (deterministic);
+// beta enters in log2 units, hence the log2 e factor.
+__global__ __launch_bounds__(256) void unrolled_reduce_kernel(const float *gpart, int groups, int TNB,
+                                                              float *gw, float *gb) {
+    const int i = gid_x() * 256 + tid_x();
+    if (i >= TNB) return;
+    float sw = 0.0f, sb = 0.0f;
+    for (int g = 0; g < groups; ++g) {
+        sw += gpart[((int64_t)g * TNB + i) * 2];
+        sb += gpart[((int64_t)g * TNB + i) * 2 + 1];
+    }
+    gw[i] = sw;
+    gb[i] = sb * kLog2e;
+}
+
+}  // namespace
+
+int64_t unrolled_frame_bytes(const StreamCode &c, int T) {
+    const int64_t N = c.N, EZ = (int64_t)c.E * c.Z, M = (int64_t)c.mb * c.Z;
+    const int64_t state = 4 * (N + EZ) + 8 * M;
+    int64_t b = state * (1 + T) + 4 * (N + EZ + M);
+    b = (b + 15) & ~(int64_t)15;
+    b += 16 * EZ;  // tape
+    return (b + 255) & ~(int64_t)255;
+}
+
+size_t unrolled_lds_bytes(const StreamCode &c, int lanes, bool backward) {
+    const size_t x = (size_t)lanes * c.dcmax;
+    if (!backward) return 4 * x;
+    const int DM = c.dcmax > c.nb ? c.dcmax : c.nb;
+    return 4 * (x + lanes + (size_t)lanes * DM + 2 * (size_t)c.nb * lanes);
+}
+
+bool unrolled_fits(const StreamCode &c, int lanes) {
+    int fw = 0, bw = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fw, reinterpret_cast<const void *>(unrolled_fwd_kernel), lanes,
+                                                     unrolled_lds_bytes(c, lanes, false)) != hipSuccess)
+        return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bw, reinterpret_cast<const void *>(unrolled_bwd_kernel), lanes,
+                                                     unrolled_lds_bytes(c, lanes, true)) != hipSuccess)
+        return false;
+    return fw > 0 && bw > 0;
+}
+
+hipError_t launch_unrolled(bool backward, const StreamCode &host_code, const StreamCode *dev_code, int lanes,
+                           int groups, const float *llr, int64_t batch, int T, const float *w,
+                           const float *beta, float *out, const float *gout, float *gllr, float *gpart,
+                           float *gw, float *gb, const Params &p, void *ws, hipStream_t s) {
+    UnArgs A{};
+    A.llr = llr;
+    A.batch = batch;
+    A.T = T;
+    A.code = dev_code;
+    A.w = w;
+    A.beta = beta;
+    A.out = out;
+    A.gout = gout;
+    A.gllr = gllr;
+    A.gpart = gpart;
+    A.ws = (char *)ws;
+    A.frame_bytes = unrolled_frame_bytes(host_code, T);
+    A.group_bytes = (int64_t)(lanes / host_code.Z) * A.frame_bytes;
+    A.a = p.a;
+    A.lmax = p.lmax;
+    A.lanes = lanes;
+    A.dcmax = host_code.dcmax;
+    const size_t lds = unrolled_lds_bytes(host_code, lanes, backward);
+    if (!backward) {
+        hipLaunchKernelGGL(unrolled_fwd_kernel, dim3(groups), dim3(lanes), lds, s, A);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(unrolled_bwd_kernel, dim3(groups), dim3(lanes), lds, s, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int TNB = T * host_code.nb;
+    hipLaunchKernelGGL(unrolled_reduce_kernel, dim3((TNB + 255) / 256), dim3(256), 0, s, gpart, groups, TNB,
+                       gw, gb);
+    return hipGetLastError();
+}
+
+}  // namespace cbp
