@@ -87,6 +87,8 @@ def main() -> int:
                     help="skip the n=26112 code (streamed kernel) section")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-code batch (25 QC codes in one persistent launch)")
+    ap.add_argument("--train-steps", type=int, default=2000,
+                    help="Adam steps of the unrolled differentiable CBP (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -338,7 +340,20 @@ def main() -> int:
             f"{mixed['gbps']:.2f} Gbit/s, iters {mixed['mean_iters']:.2f}, FER {mixed['fer']:.3f}")
         del ml, mc, mo, mbits, mit, mws, lws, graph
 
-    # ---------------- 6. CPU baseline: the FP64 oracle ----------------------
+    # ---------------- 6. unrolled differentiable CBP: training steps -----
+    train = None
+    if args.train_steps > 0:
+        from paper_2305_05286_amd.train_unrolled import train as train_unrolled
+        tr = train_unrolled("qc2304", sweeps=10, steps=args.train_steps, batch=8192,
+                            log_every=max(1, args.train_steps // 4), log=log)
+        train = {k: v for k, v in tr.items() if k not in ("w", "beta", "history")}
+        train["val_bce_history"] = [round(v["bce"], 6) for v in tr["history"]["val"]]
+        log(f"[bench] unrolled CBP training: {tr['steps_per_s']:.1f} steps/s "
+            f"({tr['frames_per_s'] / 1e3:.0f} k frames/s forward+backward), validation BCE "
+            f"{tr['untrained']['bce']:.5f} -> {tr['trained']['bce']:.5f}, "
+            f"FER {tr['untrained']['fer']:.4f} -> {tr['trained']['fer']:.4f}")
+
+    # ---------------- 7. CPU baseline: the FP64 oracle ----------------------
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -382,6 +397,7 @@ def main() -> int:
         "matched_fer": matched or None,
         "large_code": large,
         "mixed_batch": mixed,
+        "unrolled_training": train,
         "sweep": {a: [{k: (round(x, 6) if isinstance(x, float) else x) for k, x in p.items()} for p in v]
                   for a, v in sweep.items()} if not args.no_sweep else None,
     }
