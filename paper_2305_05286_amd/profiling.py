@@ -21,15 +21,17 @@ import statistics
 from pathlib import Path
 
 ROOT = Path(__file__).resolve().parents[1]
-KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp",
-                  "paper_2305_05286_amd/build.py"]  # source and compile flags
+KERNEL_SOURCES = ["paper_2305_05286_amd/csrc/qc_reg.hip", "paper_2305_05286_amd/csrc/phi.hpp"]
 COPY_BYTES = 1 << 30
 
 
 def kernel_hash() -> str:
+    """Hash of the CBP kernel's sources and compile flags (counter files carry it)."""
+    from paper_2305_05286_amd import build
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         h.update((ROOT / p).read_bytes())
+    h.update(" ".join(f for f in build.FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 

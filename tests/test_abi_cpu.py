@@ -131,3 +131,49 @@ def test_workspace_sizes(L):
     n = cbp.workspace_size(big, "cbp", 4096)
     assert 2048 * per_slot <= n <= 2048 * (per_slot + 512) + 256
     assert cbp.workspace_size(big, "cbp", 3) <= 3 * (per_slot + 512) + 256
+
+
+def test_mix_plan_validation(L):
+    from paper_2305_05286_amd.workload import mixed_family
+    fam = mixed_family()
+    handles = [cbp.Code.from_workload(c) for c in fam]
+    mix = cbp.Mix(handles)
+    assert mix.schedule == (384, 0)                  # lcm(16, 32, 64, 128, 384) fills whole waves
+    mix.schedule = (768, 2)
+    assert mix.schedule == (768, 2)
+    for bad in [(384 + 16, 0), (0, 0), (1152, 0), (384, -1)]:
+        with pytest.raises(cbp.CbpError):
+            mix.schedule = bad
+    small = cbp.Mix([cbp.Code.from_workload(c) for c in fam if c.Z == 16])
+    assert small.schedule == (64, 0)                 # 16 -> doubled to a whole wave
+    # Z values whose workgroup would need more than 1024 lanes, and a non-QC code
+    q96 = cbp.Code.from_qc(np.array([[0, 1, -1], [2, 0, 1]]), 96)
+    q100 = cbp.Code.from_qc(np.array([[0, 1, -1], [2, 0, 1]]), 100)
+    with pytest.raises(cbp.CbpError) as e:
+        cbp.Mix([q96, q100])
+    assert e.value.status == cbp.CBP_EUNSUPPORTED
+    with pytest.raises(cbp.CbpError) as e:
+        cbp.Mix([cbp.Code.from_workload(get_code("reg36_n96"))])
+    assert e.value.status == cbp.CBP_EUNSUPPORTED
+    arr = (ctypes.c_void_p * 1)(None)
+    h = ctypes.c_void_p()
+    assert L.cbp_mix_create(arr, 1, ctypes.byref(h)) == cbp.CBP_EINVAL
+    assert L.cbp_mix_create(arr, 0, ctypes.byref(h)) == cbp.CBP_EINVAL
+    assert L.cbp_mix_create(arr, 257, ctypes.byref(h)) == cbp.CBP_EINVAL
+
+
+def test_unrolled_workspace_and_validation(L):
+    q = cbp.Code.from_workload(get_code("qc2304"))
+    n = cbp.unrolled_workspace_size(q, 10, 8192)
+    state = 4 * (2304 + 7296) + 8 * 1152                # Q, R, check-beliefs per frame
+    per_frame = state * 11 + 4 * (2304 + 7296 + 1152) + 16 * 7296
+    assert 8192 * per_frame <= n <= 8192 * (per_frame + 512) + 4096 * 10 * 24 * 8 + 256
+    assert cbp.unrolled_workspace_size(q, 10, 0) == 0
+    for sweeps in (0, 65):
+        with pytest.raises(cbp.CbpError):
+            cbp.unrolled_workspace_size(q, sweeps, 10)
+    with pytest.raises(cbp.CbpError):
+        cbp.unrolled_workspace_size(cbp.Code.from_workload(get_code("reg36_n96")), 5, 10)
+    sz = ctypes.c_size_t()
+    assert L.cbp_unrolled_workspace_size(q.handle, 5, -1, ctypes.byref(sz)) == cbp.CBP_EINVAL
+    assert L.cbp_unrolled_forward(None, None, 1, 5, None, None, None, None, None, 0, None) == cbp.CBP_EINVAL
