@@ -115,28 +115,53 @@ __device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const 
     const int Z = F.Z, l = F.l, NB = F.NB;
     for (int r = 0; r < F.MB; ++r) {
         const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
-        for (int e = e0; e < e1; ++e) {
-            const Edge ed = edge(erec, e);
-            const int iv = ed.b * Z + l;
-            const int kc = wrapz(l - ed.sh, Z);
-            const float q = F.W.ld(F.oQ + 4u * iv);
+        // two edges at a time: all loads before any store (distinct block-columns;
+        // R(c_i -> v) is read before R(c_j -> v) is stored, from rn in a degree-1 column)
+        struct In {
+            Edge ed;
+            float q, rci;
+            float2 om;
+            bool has;
+        };
+        auto ld_edge = [&](int e, In &in) {
+            in.ed = edge(erec, e);
+            in.q = F.W.ld(F.oQ + 4u * (in.ed.b * Z + l));
+            in.rci = F.W.ld(F.oR + 4u * (e * Z + l));
+            in.has = !(t == 0 && in.ed.first);
+            in.om = in.has ? F.W.ld2(F.oOM + 8u * (in.ed.epr * Z + wrapz(l - in.ed.epsh, Z))) : make_float2(0.0f, 0.0f);
+        };
+        auto fin_edge = [&](int e, const In &in) {
+            const Edge &ed = in.ed;
+            const float q = in.q;
             float rn = 0.0f, d = -1.0f, par = 0.0f;
             bool own = false;
-            if (!(t == 0 && ed.first)) {
-                const float2 om = F.W.ld2(F.oOM + 8u * (ed.epr * Z + wrapz(l - ed.epsh, Z)));
-                d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
+            if (in.has) {
+                d = excl_sum(abs_bits(in.om.x), in.om.y, phi2_clamped(q, a2, lmax2));
                 const int k = t * NB + ed.b;
                 const float mag = __builtin_fmaxf(ldc(A.w, k) * phi2(d) - ldc(A.beta, k) * kLog2e, 0.0f);
-                rn = with_sign(mag, sign_bit(om.x) ^ (q < 0.0f));
-                F.W.st(F.oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v) first
+                rn = with_sign(mag, sign_bit(in.om.x) ^ (q < 0.0f));
+                F.W.st(F.oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v)
                 own = ed.ep == e;
-                par = sign_bit(om.x) ? 1.0f : 0.0f;
+                par = sign_bit(in.om.x) ? 1.0f : 0.0f;
             }
-            const float rold = own ? rn : F.W.ld(F.oR + 4u * (e * Z + l));
+            const float rold = own ? rn : in.rci;
             const float qn = q + rn - rold;
-            F.W.st(F.oQ + 4u * iv, qn);
-            sX[(e - e0) * Z + kc] = with_sign(phi2_clamped(qn, a2, lmax2), qn < 0.0f);
+            F.W.st(F.oQ + 4u * (ed.b * Z + l), qn);
+            sX[(e - e0) * Z + wrapz(l - ed.sh, Z)] = with_sign(phi2_clamped(qn, a2, lmax2), qn < 0.0f);
             if constexpr (kTape) F.W.st4(F.oTape + 16u * (e * Z + l), make_float4(q, d, rold, par));
+        };
+        int e = e0;
+        for (; e + 1 < e1; e += 2) {
+            In p0, p1;
+            ld_edge(e, p0);
+            ld_edge(e + 1, p1);
+            fin_edge(e, p0);
+            fin_edge(e + 1, p1);
+        }
+        if (e < e1) {
+            In p0;
+            ld_edge(e, p0);
+            fin_edge(e, p0);
         }
         __syncthreads();
         {

@@ -74,21 +74,30 @@ def is_cbp(n: str) -> bool:
     return "qc_reg_kernel" in n and "QcGraph0, 0, false" in n
 
 
+def is_stream_cbp(n: str) -> bool:
+    return "qc_stream_kernel<0, false>" in n or ("qc_stream_kernel" in n and "ILi0ELb0E" in n)
+
+
+MATCHERS = {"qc_reg": (is_cbp, "qc_reg_kernel<QcGraph0, CBP>"),
+            "qc_stream": (is_stream_cbp, "qc_stream_kernel<CBP> (n=26112)")}
+
+
 def is_copy(n: str) -> bool:
     # torch's contiguous device-to-device copy runs the runtime's blit kernel
     return n.startswith("__amd_rocclr_copyBuffer")
 
 
 def traffic(a) -> dict:
-    fetch = _counter(a.fetch, is_cbp, "FETCH_SIZE")
-    write = _counter(a.write, is_cbp, "WRITE_SIZE")
+    match, label = MATCHERS[a.kernel]
+    fetch = _counter(a.fetch, match, "FETCH_SIZE")
+    write = _counter(a.write, match, "WRITE_SIZE")
     cf = max(_counter(a.copy_fetch, is_copy, "FETCH_SIZE"))
     cw = max(_counter(a.copy_write, is_copy, "WRITE_SIZE"))
     kf = COPY_BYTES / (cf * 1024.0)
     kw = COPY_BYTES / (cw * 1024.0)
     fb = statistics.mean(fetch) * 1024.0 * kf
     wb = statistics.mean(write) * 1024.0 * kw
-    return {"kernel": "qc_reg_kernel<QcGraph0, CBP>", "kernel_hash": kernel_hash(),
+    return {"kernel": label, "kernel_hash": kernel_hash() if a.kernel == "qc_reg" else None,
             "ebn0_db": a.ebn0, "fetch_kib_per_dispatch": statistics.mean(fetch),
             "write_kib_per_dispatch": statistics.mean(write),
             "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": kf, "write_scale": kw,
@@ -129,6 +138,7 @@ def main():
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         c.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     c.add_argument("--ebn0", type=float, required=True)
+    c.add_argument("--kernel", choices=sorted(MATCHERS), default="qc_reg")
     c.add_argument("--out", required=True)
     v = sub.add_parser("valu")
     v.add_argument("dir")
