@@ -76,9 +76,12 @@ int cbp_code_info(const cbp_code_t *code, int32_t *M, int32_t *N, int64_t *E, in
 
 typedef struct {
     /* 0: stop when the syndrome H x^T = 0, tested on [L < 0] before the first
-     *    sweep and after every sweep (default).  2: run exactly max_iter sweeps.
-     *    (1, the paper's consecutive-positive-check-belief rule, is not
-     *    implemented on the GPU: CBP_EUNSUPPORTED.) */
+     *    sweep and after every sweep (default).  1: the paper's rule (Sec.
+     *    IV-C Step 2(3)), cbp_decode only: stop as soon as M consecutive check
+     *    updates (rows in index order, across sweeps) each leave Omega > 0 and
+     *    flip no hard decision; the decisions are those after that row, and
+     *    iters_out counts the sweep it falls in.  With hd_mode 1 it needs the
+     *    sparse kernel (else CBP_EUNSUPPORTED).  2: run exactly max_iter sweeps. */
     int32_t stop_rule;
     /* CBP hard decision.  0: x_v = [Lambda_v < 0] from the V2C phase of v's
      * last visit in the sweep (paper Step 3; default).  1: from the flushed

@@ -292,9 +292,9 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     cbp_opts_t def;
     cbp_opts_default(&def);
     if (!o) o = &def;
-    if (o->stop_rule == 1)
-        return fail(CBP_EUNSUPPORTED, "stop_rule 1 (consecutive positive check-beliefs) is not implemented on the GPU");
-    if (o->stop_rule != 0 && o->stop_rule != 2) return fail(CBP_EINVAL, "stop_rule must be 0 or 2");
+    if (o->stop_rule < 0 || o->stop_rule > 2) return fail(CBP_EINVAL, "stop_rule must be 0, 1 or 2");
+    if (o->stop_rule == 1 && algo != kCBP && algo != kCBPNMS)
+        return fail(CBP_EINVAL, "stop_rule 1 (the paper's rule) applies to cbp_decode only");
     if (o->hd_mode != 0 && o->hd_mode != 1) return fail(CBP_EINVAL, "hd_mode must be 0 or 1");
     if (o->hd_mode == 1 && algo != kCBP && algo != kCBPNMS)
         return fail(CBP_EINVAL, "hd_mode 1 applies to cbp_decode only");
@@ -314,6 +314,9 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
         return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024, mb < 32768, nb < 65536");
     if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE)
         return fail(CBP_EINVAL, "unknown kernel %d", o->kernel);
+    if (o->stop_rule == 1 && o->hd_mode == 1 && k != CBP_KERNEL_SPARSE)
+        return fail(CBP_EUNSUPPORTED, "stop_rule 1 with hd_mode 1 needs the sparse kernel (a mid-layer stop would "
+                                      "have to undo the layer's messages)");
     r->kernel = k;
     r->p.lmax = o->lmax;
     r->p.a = (float)phi64((double)o->lmax);

@@ -108,7 +108,7 @@ struct StreamLaunch {
     int groups;
     int64_t group_bytes;      // workspace per workgroup
 };
-size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots);
+size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots, bool dbg = false);
 // Workgroups of the streamed kernel that fit on one CU (0 if none).
 int stream_groups_per_cu(int algo, int lanes, size_t lds);
 // Frames: queue q of code c holds perm[qstart[c] + q] (perm == NULL: frame

@@ -189,6 +189,12 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     __shared__ float2 sRow[kBelief ? 1 : SL][kBelief ? 1 : 2 * Z];
     __shared__ float sX[SL][DCM][2 * Z];
     __shared__ Mask sXB[SL][2 * Z];
+    // paper's stopping rule (kDbg): per-edge decision flips, per-row verdicts
+    constexpr bool kStop = kDbg && kBelief;
+    __shared__ uint8_t sFl[kStop ? SL : 1][kStop ? DCM : 1][kStop ? 2 * Z : 1];
+    __shared__ uint8_t sGood[kStop ? SL : 1][kStop ? Z : 1];
+    __shared__ int sStop[SL];
+    __shared__ long long sRun[SL];
     __shared__ unsigned int sF[SL];
     __shared__ int sBad[2][SL];
     __shared__ int sAct[SL], sFresh[SL];
@@ -208,6 +214,13 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     Mask xb = 0;
     int64_t f;
     int t = 0, it = 0;
+    // paper's stopping rule: rows in a row (across sweeps) with Omega > 0 and no
+    // flipped decision; when the run reaches M mid-layer, the decisions of the
+    // layer's later rows are reverted and frozen in xb_stop
+    const bool paper = kStop && A.p.stop_rule == 1;
+    long long run = 0;
+    bool pstop = false;
+    Mask xb_stop = 0;
 
     auto load = [&](int64_t fr) {
         xb = 0;
@@ -251,12 +264,13 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         __syncthreads();
         const bool ok = sBad[pb][slot] == 0;
         const bool have = f < A.batch;
-        const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok);
+        const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok) || (paper && pstop);
         const bool claim = done && have;
         if (claim) {
+            const Mask xo = (paper && pstop) ? xb_stop : xb;
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
-                A.bits[f * N + b * Z + l] = (uint8_t)((xb >> b) & 1u);
+                A.bits[f * N + b * Z + l] = (uint8_t)((xo >> b) & 1u);
             });
             if (l == 0) {
                 A.iters[f] = t;
@@ -267,6 +281,8 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         if (claim) {
             f = sF[slot];
             t = 0;
+            run = 0;
+            pstop = false;
             if (f < A.batch) load(f);
         }
         if (l == 0) {
@@ -290,6 +306,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             float qk[e1 - e0];
             const int lv = opaque_v(l);
             const auto sh = opaque_s(A.sht);
+            [[maybe_unused]] const Mask xb_prev = xb;  // decisions before this layer
             // phase 1: lane = variable
             static_for<e0, e1>([&](auto ec) {
                 constexpr int e = ec;
@@ -315,6 +332,13 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                     }
                     const float lam = Q[b] + rn;      // eq. equ_s4e20
                     xb = (xb & ~(Mask(1) << b)) | (Mask(fbits(lam) >> 31) << b);  // [lam < 0]
+                    if constexpr (kStop) {
+                        if (paper) {
+                            const uint8_t fl = (uint8_t)(((xb ^ xb_prev) >> b) & 1u);
+                            sFl[slot][j][lv] = fl;
+                            sFl[slot][j][lv + Z] = fl;
+                        }
+                    }
                     const float qn = lam - R[e];      // V2C, eq. equ_s4e19
                     float fq;
                     if constexpr (kAlgo == kCBP) {
@@ -369,8 +393,57 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                         sRow[slot][l + Z] = rs;
                     }
                 }
+                if constexpr (kStop) {
+                    if (paper) {  // Step 2(3): this row's update keeps Omega > 0 and flips nothing
+                        uint8_t fl = 0;
+                        static_for<0, e1 - e0>([&](auto jc) {
+                            constexpr int j = jc;
+                            fl |= sFl[slot][j][lr + shr[e0 + j]];
+                        });
+                        sGood[slot][l] = (uint8_t)(((par >> 31) == 0) && fl == 0);
+                    }
+                }
             }
             __syncthreads();
+            if constexpr (kStop) {
+                if (paper) {
+                    // rows of this layer in index order, continuing the run
+                    if (l == 0) {
+                        constexpr long long Mrows = (long long)MB * Z;
+                        int lead = 0, trail = 0;
+                        bool all = true;
+                        for (int k = 0; k < Z; ++k) {
+                            if (sGood[slot][k]) {
+                                ++trail;
+                                if (all) ++lead;
+                            } else {
+                                all = false;
+                                trail = 0;
+                            }
+                        }
+                        int kstop = -1;
+                        if (!pstop && run + lead >= Mrows) kstop = (int)(Mrows - run - 1);
+                        sStop[slot] = kstop;
+                        sRun[slot] = all ? run + Z : trail;
+                    }
+                    __syncthreads();
+                    const int kstop = sStop[slot];
+                    run = sRun[slot];
+                    if (!pstop && kstop >= 0) {
+                        // stop after row kstop: rows beyond it in this layer are undone
+                        Mask xs = xb;
+                        static_for<e0, e1>([&](auto ec) {
+                            constexpr int e = ec;
+                            constexpr int b = TT::T.eb[e];
+                            if (wrap_lo<Z>(lv - sh[e]) > kstop)
+                                xs = (xs & ~(Mask(1) << b)) | (xb_prev & (Mask(1) << b));
+                        });
+                        xb_stop = xs;
+                        pstop = true;
+                    }
+                    __syncthreads();
+                }
+            }
             if constexpr (!kBelief) {
                 // phase 3: lane = variable, normalized min-sum C2V
                 static_for<e0, e1>([&](auto ec) {
@@ -557,7 +630,7 @@ hipError_t launch_qc_reg(int k, int algo, const int *sht, const float *llr, uint
         }                                                                                     \
         CBP_LAUNCH_ALGO(G, false)                                                             \
     }
-    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1;
+    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1 || p.stop_rule == 1;
     CBP_QC_GRAPHS(CBP_LAUNCH)
 #undef CBP_LAUNCH
 #undef CBP_LAUNCH_ALGO

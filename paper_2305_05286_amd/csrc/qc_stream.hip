@@ -61,6 +61,7 @@ struct StreamArgs {
     const StreamCode *codes;
     int ncodes;
     int lanes;
+    int dcmax;
     int xfloats;              // LDS floats of one exchange array (lanes * dcmax, even)
     int max_slots;
     const int64_t *qstart;    // [ncodes+1] or NULL (one code, frames [0, batch))
@@ -101,6 +102,15 @@ void qc_stream_kernel(StreamArgs A) {
     int *sBad = sFlags + 2 * MS;                         // [2][MS]
     int *sAct = sFlags + 4 * MS;                         // [MS]
     int *sFresh = sFlags + 5 * MS;                       // [MS]
+    // paper's stopping rule (debug instantiation only; its launches allocate
+    // these): per-row verdicts [lanes], per-edge flips and previous decisions
+    // [dcmax][lanes] bytes, stop row and run per slot
+    constexpr bool kStop = kDbg && kBelief;
+    long long *sRunAll = reinterpret_cast<long long *>(sFlags + 6 * MS);  // [MS]
+    int *sStopAll = reinterpret_cast<int *>(sRunAll + MS);                 // [MS]
+    uint8_t *sGoodAll = reinterpret_cast<uint8_t *>(sStopAll + MS);        // [lanes]
+    uint8_t *sFlAll = sGoodAll + A.lanes;                                  // [lanes * dcmax]
+    uint8_t *sOldAll = sFlAll + (size_t)A.lanes * A.dcmax;                 // [lanes * dcmax]
 
     for (int visit = 0; visit < A.ncodes; ++visit) {
         const int c = (int)(((unsigned)gid_x() + (unsigned)visit) % (unsigned)A.ncodes);
@@ -117,6 +127,15 @@ void qc_stream_kernel(StreamArgs A) {
         float *sX = sXall + (size_t)slot * dcm * Z;
         float *sQ = sQall + (size_t)slot * dcm * Z;
         float2 *sRow = sRowAll + (size_t)slot * Z;
+        [[maybe_unused]] uint8_t *sGood = sGoodAll + (size_t)slot * Z;
+        [[maybe_unused]] uint8_t *sFl = sFlAll + (size_t)slot * dcm * Z;
+        [[maybe_unused]] uint8_t *sOld = sOldAll + (size_t)slot * dcm * Z;
+        // paper's stopping rule: rows in a row (across sweeps) with Omega > 0 and
+        // no flipped decision; on reaching M mid-layer the decisions of the
+        // layer's later rows are reverted and the frame's decisions frozen
+        const bool paper = kStop && A.p.stop_rule == 1;
+        long long run = 0;
+        bool pstop = false;
 
         // State: byte offsets of this slot's arrays in the workgroup's buffer.
         const Ws W{__builtin_amdgcn_make_buffer_rsrc(A.ws + (int64_t)gid_x() * A.group_bytes, 0,
@@ -170,7 +189,7 @@ void qc_stream_kernel(StreamArgs A) {
             if (bad) sBad[pb * MS + slot] = 1;
             __syncthreads();
             const bool ok = sBad[pb * MS + slot] == 0;
-            const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok);
+            const bool done = !have || t >= A.max_iter || (A.p.stop_rule == 0 && ok) || (paper && pstop);
             const bool claim = done && have;
             if (claim) {
                 for (int b = 0; b < NB; ++b) A.bits[fo + (int64_t)b * Z + l] = (uint8_t)W.ldb(oXB + b * Z + l);
@@ -184,6 +203,8 @@ void qc_stream_kernel(StreamArgs A) {
                 k = sF[slot];
                 have = k < qn;
                 t = 0;
+                run = 0;
+                pstop = false;
                 if (have) {
                     f = frame_of(k);
                     fo = offset_of(f);
@@ -221,6 +242,7 @@ void qc_stream_kernel(StreamArgs A) {
                         float q, rci;
                         float2 om;
                         bool has;
+                        uint32_t xold;
                     };
                     auto ld_edge = [&](int e, In &in) {
                         in.ed = edge(erec, e);
@@ -230,6 +252,7 @@ void qc_stream_kernel(StreamArgs A) {
                         in.q = W.ld(oQ + 4u * in.iv);
                         in.rci = W.ld(oR + 4u * (e * Z + l));
                         in.has = !(first && in.ed.first);
+                        if constexpr (kStop) in.xold = paper ? W.ldb(oXB + in.iv) : 0u;
                         in.om = make_float2(0.0f, 0.0f);
                         if (in.has) {
                             int kp = l - in.ed.epsh;
@@ -255,7 +278,14 @@ void qc_stream_kernel(StreamArgs A) {
                             own = in.ed.ep == e;
                         }
                         const float lam = q + rn;
-                        if (in.ed.last) W.stb(oXB + in.iv, lam < 0.0f);
+                        if (kStop && paper) {  // every visit decides; frozen once stopped
+                            const uint32_t nx = lam < 0.0f;
+                            sFl[(e - e0) * Z + in.kc] = (uint8_t)(nx != in.xold);
+                            sOld[(e - e0) * Z + l] = (uint8_t)in.xold;
+                            if (!pstop) W.stb(oXB + in.iv, nx != 0);
+                        } else if (in.ed.last) {
+                            W.stb(oXB + in.iv, lam < 0.0f);
+                        }
                         const float qn2 = lam - (own ? rn : in.rci);
                         const float fq = kAlgo == kCBP ? phi2_clamped(qn2, a, lmax)
                                                        : __builtin_fminf(__builtin_fabsf(qn2), lmax);
@@ -322,8 +352,49 @@ void qc_stream_kernel(StreamArgs A) {
                         if constexpr (kBelief) W.st2(oOM + 8u * (r * Z + l), make_float2(with_sign(m1, par), m2));
                         else sRow[l] = make_float2(with_sign(m1, par), m2);
                     }
+                    if constexpr (kStop) {
+                        if (paper) {  // Step 2(3): this row keeps Omega > 0 and flips nothing
+                            uint8_t fl = 0;
+                            for (int j = 0; j < e1 - e0; ++j) fl |= sFl[j * Z + l];
+                            sGood[l] = (uint8_t)(!par && fl == 0);
+                        }
+                    }
                 }
                 __syncthreads();
+                if constexpr (kStop) {
+                    if (paper) {
+                        if (l == 0) {  // rows of this layer in index order, continuing the run
+                            const long long Mrows = (long long)MB * Z;
+                            int lead = 0, trail = 0;
+                            bool all = true;
+                            for (int kk = 0; kk < Z; ++kk) {
+                                if (sGood[kk]) {
+                                    ++trail;
+                                    if (all) ++lead;
+                                } else {
+                                    all = false;
+                                    trail = 0;
+                                }
+                            }
+                            sStopAll[slot] = (!pstop && run + lead >= Mrows) ? (int)(Mrows - run - 1) : -1;
+                            sRunAll[slot] = all ? run + Z : trail;
+                        }
+                        __syncthreads();
+                        const int kstop = sStopAll[slot];
+                        run = sRunAll[slot];
+                        if (!pstop && kstop >= 0) {
+                            // stop after row kstop: the layer's later rows are undone
+                            for (int e = e0; e < e1; ++e) {
+                                const Edge ed = edge(erec, e);
+                                int kc = l - ed.sh;
+                                kc += (kc < 0) ? Z : 0;
+                                if (kc > kstop) W.stb(oXB + ed.b * Z + l, sOld[(e - e0) * Z + l] != 0);
+                            }
+                            pstop = true;
+                        }
+                        __syncthreads();
+                    }
+                }
                 if constexpr (!kBelief) {
                     // phase 3: lane = variable
                     auto c2v = [&](int e, const Edge &ed) {
@@ -497,10 +568,12 @@ void launch_algo(int algo, dim3 grid, dim3 block, size_t lds, hipStream_t s, con
 
 }  // namespace
 
-size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots) {
+size_t stream_lds_bytes(int algo, int lanes, int dcmax, int max_slots, bool dbg) {
     const bool belief = algo == kCBP || algo == kCBPNMS;
     const size_t xfloats = ((size_t)lanes * dcmax + 1) & ~(size_t)1;
-    return 4 * xfloats * (belief ? 1 : 2) + 8 * (size_t)lanes + 4 * 6 * (size_t)max_slots;
+    size_t b = 4 * xfloats * (belief ? 1 : 2) + 8 * (size_t)lanes + 4 * 6 * (size_t)max_slots;
+    if (dbg && belief) b += 12 * (size_t)max_slots + (size_t)lanes * (1 + 2 * (size_t)dcmax);
+    return b;
 }
 
 int stream_groups_per_cu(int algo, int lanes, size_t lds) {
@@ -521,6 +594,7 @@ hipError_t launch_qc_stream(int algo, const StreamLaunch &L, const float *llr, u
     A.codes = L.codes;
     A.ncodes = L.ncodes;
     A.lanes = L.lanes;
+    A.dcmax = L.dcmax;
     A.xfloats = (int)(((size_t)L.lanes * L.dcmax + 1) & ~(size_t)1);
     A.max_slots = L.max_slots;
     A.qstart = qstart;
@@ -533,9 +607,9 @@ hipError_t launch_qc_stream(int algo, const StreamLaunch &L, const float *llr, u
     A.d = d;
     A.ws = (char *)ws;
     A.group_bytes = L.group_bytes;
-    const size_t lds = stream_lds_bytes(algo, L.lanes, L.dcmax, L.max_slots);
+    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1 || p.stop_rule == 1;
+    const size_t lds = stream_lds_bytes(algo, L.lanes, L.dcmax, L.max_slots, dbg);
     const dim3 grid(L.groups), block(L.lanes);
-    const bool dbg = (d.sweep > 0 && d.frames > 0) || p.hd_mode == 1;
     if (dbg) launch_algo<true>(algo, grid, block, lds, s, A);
     else launch_algo<false>(algo, grid, block, lds, s, A);
     return hipGetLastError();

@@ -62,6 +62,28 @@ __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, 
     return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
 }
 
+// Flushed posterior after a stop in the middle of sweep t, right after row
+// istop: v's latest check is its last row <= istop in this sweep, else (t > 1)
+// its last row of the previous sweep, else none (B2V 0).  The column's edges
+// are walked backwards from its last edge through pred_edge.
+template <bool kMin>
+__device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, int64_t lf, int v, const Params &p,
+                                int istop, int t) {
+    const int64_t S = w.stride;
+    const float q = w.a0[(int64_t)v * S + lf];
+    int e = ldc(g.last_edge, v);
+    while (ldc(g.edge_row, e) > istop) {
+        if (ldc(g.first, e)) {  // no visit of v yet in this sweep
+            if (t == 1) return q;
+            e = ldc(g.last_edge, v);
+            break;
+        }
+        e = ldc(g.pred_edge, e);
+    }
+    const int j = ldc(g.edge_row, e);
+    return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
+}
+
 // kMin: the normalized min-sum check rule (OmM = min1 | parity, OmS = min2).
 template <bool kMin>
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
@@ -79,6 +101,9 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     p.lmax *= us;
     uint8_t *xb = w.xb;
     bool active = valid;
+    // paper's stopping rule (stop_rule 1): check updates in a row, across
+    // sweeps, whose belief is positive and that flipped no decision
+    int64_t run = 0;
     // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
     if (valid) {
         for (int v = 0; v < g.N; ++v) {
@@ -96,9 +121,11 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
         if (__ballot(active) == 0) break;
         if (active) {
             // Step 2: check-nodes in index order
+            bool paper_stop = false;
+            int istop = 0;
             for (int i = 0; i < g.M; ++i) {
                 float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
-                bool par = false;
+                bool par = false, flip = false;
                 for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) {
                     const int v = ldc(g.col_idx, e);
                     const int64_t iv = (int64_t)v * S + lf;
@@ -112,7 +139,9 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                         R[(int64_t)ldc(g.pred_edge, e) * S + lf] = rn;
                     }
                     const float lam = q + rn;                 // eq. equ_s4e20
-                    xb[iv] = lam < 0.0f;                      // eq. equ_s2e7
+                    const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
+                    if (p.stop_rule == 1) flip |= nx != xb[iv];
+                    xb[iv] = nx;
                     const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
                     Q[iv] = qn;
                     if constexpr (!kMin) {
@@ -128,6 +157,22 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                 }
                 OmM[(int64_t)i * S + lf] = with_sign(Mx, par);  // eq. equ_s4e23
                 OmS[(int64_t)i * S + lf] = Sr;
+                if (p.stop_rule == 1) {  // Step 2(3): M updates in a row with Omega > 0, no flip
+                    run = (!par && !flip) ? run + 1 : 0;
+                    if (run >= g.M) {
+                        paper_stop = true;
+                        istop = i;
+                        break;
+                    }
+                }
+            }
+            if (paper_stop) {
+                if (p.hd_mode == 1)
+                    for (int v = 0; v < g.N; ++v)
+                        xb[(int64_t)v * S + lf] = cbp_flushed_at<kMin>(g, w, lf, v, p, istop, t) < 0.0f;
+                write_out(g, xb, S, lf, bits, iters, f, t);
+                active = false;
+                continue;
             }
             if (p.hd_mode == 1)
                 for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed<kMin>(g, w, lf, v, p) < 0.0f;

@@ -102,8 +102,14 @@ def test_decode_argument_errors_without_gpu(L):
     assert L.fbp_nms_decode(c.handle, None, None, None, 5, 8, None, None) == cbp.CBP_EINVAL
     # option errors are reported before any device work
     fake = ctypes.c_void_p(16)
-    o.stop_rule = 1
-    assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+    o.stop_rule = 1       # the paper's rule is defined for CBP only
+    assert L.lbp_nms_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    o.hd_mode = 1         # ... and with flushed decisions needs the sparse kernel
+    q = cbp.Code.from_workload(get_code("qc2304"))
+    assert L.cbp_decode(q.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+    o.hd_mode = 0
+    o.stop_rule = 3
+    assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
     o.stop_rule = 0
     o.kernel = cbp.KERNELS["qc_reg"]
     assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED

@@ -240,8 +240,44 @@ def test_kernel_selection_errors():
         cbp.cbp_decode(c, t, 5, kernel="qc_reg")
     assert ei.value.status == cbp.CBP_EUNSUPPORTED
     with pytest.raises(cbp.CbpError) as ei:
-        cbp.cbp_decode(c, t, 5, stop_rule=1)
-    assert ei.value.status == cbp.CBP_EUNSUPPORTED
+        cbp.lbp_nms_decode(c, t, 5, stop_rule=1)
+    assert ei.value.status == cbp.CBP_EINVAL
+
+
+# ---------------------------------------------- the paper's stopping rule
+
+PAPER_STOP = [("qc2304", "cbp", "qc_reg"), ("qc2304", "cbp_nms", "qc_reg"), ("qc_t64s", "cbp", "qc_reg"),
+              ("qc2304", "cbp", "qc_stream"), ("qc_t64s", "cbp_nms", "qc_stream"),
+              ("qc26112", "cbp", "qc_stream"), ("reg36_n96", "cbp", "sparse"),
+              ("reg36_n96", "cbp_nms", "sparse"), ("qc_t16", "cbp", "sparse")]
+
+
+@pytest.mark.parametrize("name,algo,kernel", PAPER_STOP, ids=[f"{a}-{b}-{c}" for a, b, c in PAPER_STOP])
+def test_paper_stopping_rule_matches_oracle(name, algo, kernel):
+    """Step 2(3): stop after M consecutive check updates with Omega > 0 and no flipped
+    decision, possibly in the middle of a layer (the layer's later rows are undone)."""
+    code = get_code(name)
+    B = 128 if name == "qc26112" else 1000
+    for k, snr in enumerate([1.5, 2.5] if name != "qc26112" else [1.25]):
+        llr, _ = make_frames(code, snr, B, key=(61, k))
+        say(f"[gpu] paper stop {name} {algo} {kernel} snr={snr}")
+        gb, gi = run_gpu(code, llr, 30, algo, kernel=kernel, stop_rule=1)
+        o = oracle.decode(code, llr, 30, algo, stop_rule=1)
+        ok = agree(gb, gi, o["bits"], o["iters"])
+        conv = o["iters"] < 30
+        say(f"    parity {ok.mean():.5f} (stopped early {conv.mean():.3f}), mean iters gpu "
+            f"{gi.mean():.3f} oracle {o['iters'].mean():.3f}")
+        assert (gi == o["iters"]).mean() >= PARITY
+        if conv.any():
+            assert ok[conv].mean() >= PARITY
+
+
+def test_paper_stopping_rule_flushed_sparse():
+    code = get_code("reg36_n96")
+    llr, _ = make_frames(code, 2.0, 1000, key=(62,))
+    gb, gi = run_gpu(code, llr, 30, "cbp", kernel="sparse", stop_rule=1, hd_mode=1)
+    o = oracle.decode(code, llr, 30, "cbp", stop_rule=1, hd_mode=1)
+    assert agree(gb, gi, o["bits"], o["iters"]).mean() >= PARITY
 
 
 def test_full_batch_sampled_parity():
