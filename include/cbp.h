@@ -145,6 +145,12 @@ void cbp_opts_default(cbp_opts_t *opts);
  *   normalized min-sum check rule alpha * prod sgn * min |Q| (|Q| <= lmax).
  * fbp_nms_decode: flooding BP (Sec. II-A, eqs. equ_s2e3/equ_s2e6/equ_s2e7)
  *   with the same normalized min-sum check rule.
+ * lbp_decode, fbp_decode: the same two schedules with the paper's own check
+ *   rule, the log-tanh C2V of eq. equ_s2e4 (phi of the sum of phi(|Q|) over
+ *   the row's other edges, |Q| clamped to [phi(lmax), lmax] as in
+ *   cbp_decode): the LBP and FBP the paper compares CBP with (Sec. V).
+ *   They run on the sparse kernel (opts->kernel AUTO or CBP_KERNEL_SPARSE,
+ *   else CBP_EUNSUPPORTED) for any code.
  */
 int cbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
                int32_t *iters_out, int32_t max_iter, int64_t batch,
@@ -155,9 +161,16 @@ int lbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_ou
 int fbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
                    int32_t *iters_out, int32_t max_iter, int64_t batch,
                    const cbp_opts_t *opts, void *stream);
+int lbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
+               int32_t *iters_out, int32_t max_iter, int64_t batch,
+               const cbp_opts_t *opts, void *stream);
+int fbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
+               int32_t *iters_out, int32_t max_iter, int64_t batch,
+               const cbp_opts_t *opts, void *stream);
 
 /* Device workspace (bytes) the given decoder needs for `batch` frames with
- * these options; decoder: 0 = cbp_decode, 1 = lbp_nms_decode, 2 = fbp_nms_decode. */
+ * these options; decoder: 0 = cbp_decode, 1 = lbp_nms_decode, 2 = fbp_nms_decode,
+ * 3 = lbp_decode, 4 = fbp_decode. */
 int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch,
                        const cbp_opts_t *opts, size_t *bytes);
 

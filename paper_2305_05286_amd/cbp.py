@@ -21,12 +21,12 @@ LIB_PATH = Path(__file__).resolve().parent / "libcbp.so"
 CBP_OK, CBP_EINVAL, CBP_EUNSUPPORTED, CBP_EHIP, CBP_ENOMEM = 0, -1, -2, -3, -4
 KERNELS = {"auto": 0, "qc_reg": 1, "qc_stream": 2, "sparse": 4}
 RULES = {"log_tanh": 0, "min_sum": 1}
-DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2}
+DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2, "lbp": 3, "fbp": 4}
 
 # exported names declared in include/cbp.h
 EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info",
            "cbp_opts_default", "cbp_decode", "lbp_nms_decode", "fbp_nms_decode",
-           "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
+           "lbp_decode", "fbp_decode", "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
            "cbp_version", "cbp_mix_create", "cbp_mix_free", "cbp_mix_get_schedule",
            "cbp_mix_set_schedule", "cbp_mix_workspace_size", "cbp_mix_decode", "cbp_mix_tune",
            "cbp_mix_graph_create", "cbp_graph_launch", "cbp_graph_free",
@@ -84,7 +84,9 @@ def lib():
                                     ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.cbp_opts_default.argtypes = [ctypes.POINTER(Opts)]
         L.cbp_opts_default.restype = None
-        for name in ("cbp_decode", "lbp_nms_decode", "fbp_nms_decode"):
+        for name in ("cbp_decode", "lbp_nms_decode", "fbp_nms_decode", "lbp_decode", "fbp_decode"):
+            if not hasattr(L, name):
+                continue
             getattr(L, name).argtypes = [vp, vp, vp, vp, i32, i64, ctypes.POINTER(Opts), vp]
             getattr(L, name).restype = ctypes.c_int
         L.cbp_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(Opts), ctypes.POINTER(sz)]
@@ -222,7 +224,7 @@ def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, 
     o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace, check_rule)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode",
-                         "fbp_nms": "fbp_nms_decode"}[which])
+                         "fbp_nms": "fbp_nms_decode", "lbp": "lbp_decode", "fbp": "fbp_decode"}[which])
     with torch.cuda.device(dev):
         check(fn(code.handle, llr.data_ptr(), bits.data_ptr(), iters.data_ptr(), int(max_iter),
                  B, ctypes.byref(o), ctypes.c_void_p(s.cuda_stream)))
@@ -247,8 +249,19 @@ def fbp_nms_decode(code: Code, llr, max_iter: int, **kw):
     return _run("fbp_nms", code, llr, max_iter, **kw)
 
 
+def lbp_decode(code: Code, llr, max_iter: int, **kw):
+    """Layered BP with the log-tanh check rule (sparse kernel; same arguments as cbp_decode)."""
+    return _run("lbp", code, llr, max_iter, **kw)
+
+
+def fbp_decode(code: Code, llr, max_iter: int, **kw):
+    """Flooding BP with the log-tanh check rule (sparse kernel; same arguments as cbp_decode)."""
+    return _run("fbp", code, llr, max_iter, **kw)
+
+
 def decode(code: Code, llr, max_iter: int, algo: str = "cbp", **kw):
-    """algo: "cbp", "cbp_nms" (cbp_decode with the min-sum rule), "lbp_nms", "fbp_nms"."""
+    """algo: "cbp", "cbp_nms" (cbp_decode with the min-sum rule), "lbp_nms", "fbp_nms",
+    "lbp", "fbp"."""
     return _run(algo, code, llr, max_iter, **kw)
 
 

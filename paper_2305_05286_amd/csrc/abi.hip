@@ -306,6 +306,9 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     if (o->dump_sweep < 0 || o->dump_frames < 0) return fail(CBP_EINVAL, "negative dump option");
     int k = o->kernel;
     const bool stream_ok = code->qc && code->Z <= 1024 && code->mb < 32768 && code->nb < 65536;
+    if ((algo == kLBP || algo == kFBP) && k != CBP_KERNEL_AUTO && k != CBP_KERNEL_SPARSE)
+        return fail(CBP_EUNSUPPORTED, "lbp_decode and fbp_decode run on the sparse kernel only");
+    if (algo == kLBP || algo == kFBP) k = CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_AUTO)
         k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : stream_ok ? CBP_KERNEL_QC_STREAM : CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_QC_REG && code->qc_reg_id < 0)
@@ -335,7 +338,10 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     return CBP_OK;
 }
 
-constexpr int64_t kSparseChunkBytes = (int64_t)1 << 30;
+// Frames of one sparse launch, workspace at most 32 GiB (e.g. 175k frames of
+// an n = 8192 code).  A launch lasts as long as its slowest frame, so large
+// batches should run in as few launches as memory allows.
+constexpr int64_t kSparseChunkBytes = (int64_t)32 << 30;
 
 int64_t sparse_chunk_frames(int algo, const SparseDev &g, int64_t batch) {
     const size_t per = sparse_ws_bytes(algo, g, 64) / 64 + 1;
@@ -1008,20 +1014,32 @@ int fbp_nms_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_ou
     return decode(kFBPNMS, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
 }
 
+int lbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out, int32_t *iters_out,
+               int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
+    return decode(kLBP, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
+}
+
+int fbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out, int32_t *iters_out,
+               int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
+    return decode(kFBP, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
+}
+
 int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch, const cbp_opts_t *opts,
                        size_t *bytes) {
     if (!code || !bytes) return fail(CBP_EINVAL, "code/bytes is NULL");
-    if (decoder < 0 || decoder > 2) return fail(CBP_EINVAL, "decoder must be 0, 1 or 2");
-    if (decoder == 0 && opts && opts->check_rule == CBP_RULE_MIN_SUM) decoder = kCBPNMS;
+    if (decoder < 0 || decoder > 4) return fail(CBP_EINVAL, "decoder must be 0 .. 4");
+    static const int kDecoderAlgo[5] = {kCBP, kLBPNMS, kFBPNMS, kLBP, kFBP};
+    int algo = kDecoderAlgo[decoder];
+    if (algo == kCBP && opts && opts->check_rule == CBP_RULE_MIN_SUM) algo = kCBPNMS;
     if (batch < 0) return fail(CBP_EINVAL, "batch < 0");
     Resolved r;
-    int rc = resolve_opts(code, decoder, batch, opts, &r);
+    int rc = resolve_opts(code, algo, batch, opts, &r);
     if (rc) return rc;
     SparseDev g{};
     g.M = code->M;
     g.N = code->N;
     g.E = (int)code->E;
-    *bytes = batch == 0 ? 0 : needed_ws(decoder, code, g, r.kernel, batch);
+    *bytes = batch == 0 ? 0 : needed_ws(algo, code, g, r.kernel, batch);
     return CBP_OK;
 }
 

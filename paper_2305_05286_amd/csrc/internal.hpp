@@ -6,8 +6,9 @@
 namespace cbp {
 
 // kCBPNMS: CBP with the normalized min-sum check rule (cbp_decode with
-// CBP_RULE_MIN_SUM).
-enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2, kCBPNMS = 3 };
+// CBP_RULE_MIN_SUM).  kLBP / kFBP: layered / flooding BP with the log-tanh
+// check rule (sparse kernel only).
+enum Algo : int { kCBP = 0, kLBPNMS = 1, kFBPNMS = 2, kCBPNMS = 3, kLBP = 4, kFBP = 5 };
 
 // Work-item and workgroup ids straight from the hardware registers.  (The
 // device code is built with relaxed NaN handling, which keeps the compiler

@@ -14,6 +14,7 @@ namespace cbp {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kChunk = 8;  // edges of a row whose loads are issued together
 constexpr int kSyndromeBlock = 256;
 constexpr int kFillBlock = 256;
 
@@ -126,34 +127,66 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             for (int i = 0; i < g.M; ++i) {
                 float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
                 bool par = false, flip = false;
-                for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) {
-                    const int v = ldc(g.col_idx, e);
-                    const int64_t iv = (int64_t)v * S + lf;
-                    const float q = Q[iv];
-                    float rn = 0.0f;
-                    if (!(t == 1 && ldc(g.first, e))) {
-                        // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
-                        // from its belief, then committed to R(c_j -> v) first.
-                        const int64_t ij = (int64_t)ldc(g.pred_row, e) * S + lf;
-                        rn = b2v<kMin>(OmM[ij], OmS[ij], PQ[iv], q, p);
-                        R[(int64_t)ldc(g.pred_edge, e) * S + lf] = rn;
+                const int e1 = ldc(g.row_ptr, i + 1);
+                // The row's edges in chunks of kChunk: every load of a chunk is
+                // issued before its first store, so a chunk costs one memory
+                // round trip instead of one per edge.  Within a row the columns
+                // differ, so no load of a chunk reads what an earlier edge of
+                // the same chunk stores, except R(c_i -> v) when v's latest
+                // check is c_i itself (a column of weight one): that commit is
+                // forwarded in registers.
+                for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
+                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    float q[kChunk], pq[kChunk], om[kChunk], os[kChunk], r[kChunk];
+                    uint8_t x0[kChunk];
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        if (k < n) {
+                            const int e = c0 + k;
+                            const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
+                            q[k] = Q[iv];
+                            if (!kMin) pq[k] = PQ[iv];
+                            if (!(t == 1 && ldc(g.first, e))) {
+                                const int64_t ij = (int64_t)ldc(g.pred_row, e) * S + lf;
+                                om[k] = OmM[ij];
+                                os[k] = OmS[ij];
+                            }
+                            r[k] = R[(int64_t)e * S + lf];
+                            if (p.stop_rule == 1) x0[k] = xb[iv];
+                        }
                     }
-                    const float lam = q + rn;                 // eq. equ_s4e20
-                    const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
-                    if (p.stop_rule == 1) flip |= nx != xb[iv];
-                    xb[iv] = nx;
-                    const float qn = lam - R[(int64_t)e * S + lf];  // V2C, eq. equ_s4e19
-                    Q[iv] = qn;
-                    if constexpr (!kMin) {
-                        const float fq = phi2_clamped(qn, p.a, p.lmax);
-                        PQ[iv] = fq;
-                        fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
-                    } else {                                  // eq. equ_s4e21xx
-                        const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
-                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
-                        Mx = __builtin_fminf(Mx, aq);
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        if (k < n) {
+                            const int e = c0 + k;
+                            const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
+                            float rn = 0.0f, rc = r[k];
+                            if (!(t == 1 && ldc(g.first, e))) {
+                                // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
+                                // from its belief, then committed to R(c_j -> v) first.
+                                rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
+                                const int pe = ldc(g.pred_edge, e);
+                                R[(int64_t)pe * S + lf] = rn;
+                                if (pe == e) rc = rn;
+                            }
+                            const float lam = q[k] + rn;              // eq. equ_s4e20
+                            const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
+                            if (p.stop_rule == 1) flip |= nx != x0[k];
+                            xb[iv] = nx;
+                            const float qn = lam - rc;                // V2C, eq. equ_s4e19
+                            Q[iv] = qn;
+                            if constexpr (!kMin) {
+                                const float fq = phi2_clamped(qn, p.a, p.lmax);
+                                PQ[iv] = fq;
+                                fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
+                            } else {                                  // eq. equ_s4e21xx
+                                const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
+                                Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
+                                Mx = __builtin_fminf(Mx, aq);
+                            }
+                            par ^= (qn < 0.0f);
+                        }
                     }
-                    par ^= (qn < 0.0f);
                 }
                 OmM[(int64_t)i * S + lf] = with_sign(Mx, par);  // eq. equ_s4e23
                 OmS[(int64_t)i * S + lf] = Sr;
@@ -202,11 +235,15 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
 }
 
 // --------------------------------------------------------------------------
-// Normalized min-sum baselines.  ws: a0 = Lambda[N], a1 = R[E],
-// a2 = Lambda accumulator of the flooding schedule [N].
+// Layered and flooding BP baselines (Sec. II-A, II-B).  ws: a0 = Lambda[N],
+// a1 = R[E], a2 = Lambda accumulator of the flooding schedule [N].
+// kMin: the normalized min-sum check rule (alpha * sign * min of the other
+// clamped |Q|).  Otherwise the log-tanh rule of eq. equ_s2e4 in log2 units
+// (as in the CBP kernel): each row folds g(|Q|) of its edges into a
+// (max, rest) pair and excludes an edge's own term from it exactly.
 // --------------------------------------------------------------------------
-template <bool kFlood>
-__global__ __launch_bounds__(kWave) void nms_sparse_kernel(
+template <bool kFlood, bool kMin>
+__global__ __launch_bounds__(kWave) void bp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
     Dump d) {
@@ -215,11 +252,15 @@ __global__ __launch_bounds__(kWave) void nms_sparse_kernel(
     const int64_t f = f0 + lf;
     const int64_t S = w.stride;
     float *Lam = w.a0, *R = w.a1, *Acc = w.a2;
+    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
+    const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
+    p.a *= us;
+    p.lmax *= us;
     uint8_t *xb = w.xb;
     bool active = valid;
     if (valid) {
         for (int v = 0; v < g.N; ++v) {
-            const float l = llr[f * g.N + v];
+            const float l = llr[f * g.N + v] * us;
             Lam[(int64_t)v * S + lf] = l;
             xb[(int64_t)v * S + lf] = l < 0.0f;
         }
@@ -236,37 +277,80 @@ __global__ __launch_bounds__(kWave) void nms_sparse_kernel(
                 for (int v = 0; v < g.N; ++v) Acc[(int64_t)v * S + lf] = 0.0f;
             for (int i = 0; i < g.M; ++i) {
                 const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
-                float m1 = __builtin_inff(), m2 = __builtin_inff();
+                // min-sum: (m1, m2) = two smallest |Q|; log-tanh: (m1, m2) = (max, rest) of g(|Q|)
+                float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
                 bool par = false;
-                for (int e = e0; e < e1; ++e) {
-                    const float q = Lam[(int64_t)ldc(g.col_idx, e) * S + lf] - R[(int64_t)e * S + lf];
-                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-                    m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
-                    m1 = __builtin_fminf(m1, aq);
-                    par ^= (q < 0.0f);
+                // Edges in chunks of kChunk with all loads of a chunk issued
+                // together (the columns of a row differ, so they never read what
+                // the chunk stores).  A row of at most kChunk edges keeps its V2C
+                // messages in registers between the two passes.
+                float qs[kChunk];
+                for (int c0 = e0; c0 < e1; c0 += kChunk) {
+                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    float lv[kChunk], rv[kChunk];
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k)
+                        if (k < n) {
+                            lv[k] = Lam[(int64_t)ldc(g.col_idx, c0 + k) * S + lf];
+                            rv[k] = R[(int64_t)(c0 + k) * S + lf];
+                        }
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k)
+                        if (k < n) {
+                            // V2C, eq. equ_s2e3 (flooding: Lambda of the previous sweep) / equ_s2e10
+                            const float q = lv[k] - rv[k];
+                            qs[k] = q;
+                            if constexpr (kMin) {
+                                const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                                m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
+                                m1 = __builtin_fminf(m1, aq);
+                            } else {
+                                fold(m1, m2, phi2_clamped(q, p.a, p.lmax));
+                            }
+                            par ^= (q < 0.0f);
+                        }
                 }
-                for (int e = e0; e < e1; ++e) {
-                    const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
-                    const int64_t ie = (int64_t)e * S + lf;
-                    const float q = Lam[iv] - R[ie];
-                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-                    const float rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
-                    R[ie] = rn;
-                    if (kFlood) Acc[iv] += rn;
-                    else Lam[iv] = q + rn;  // eq. equ_s2e12
+                const bool kept = e1 - e0 <= kChunk;
+                for (int c0 = e0; c0 < e1; c0 += kChunk) {
+                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    float qv[kChunk], av[kChunk];
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k)
+                        if (k < n) {
+                            const int64_t iv = (int64_t)ldc(g.col_idx, c0 + k) * S + lf;
+                            qv[k] = kept ? qs[k] : Lam[iv] - R[(int64_t)(c0 + k) * S + lf];
+                            if (kFlood) av[k] = Acc[iv];
+                        }
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k)
+                        if (k < n) {
+                            const int64_t iv = (int64_t)ldc(g.col_idx, c0 + k) * S + lf;
+                            const float q = qv[k];
+                            float rn;
+                            if constexpr (kMin) {
+                                const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                                rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
+                            } else {  // C2V, eq. equ_s2e4
+                                rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))),
+                                               par ^ (q < 0.0f));
+                            }
+                            R[(int64_t)(c0 + k) * S + lf] = rn;
+                            if (kFlood) Acc[iv] = av[k] + rn;
+                            else Lam[iv] = q + rn;  // eq. equ_s2e12
+                        }
                 }
             }
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) {
                     const int64_t iv = (int64_t)v * S + lf;
-                    Lam[iv] = llr[f * g.N + v] + Acc[iv];  // eq. equ_s2e6
+                    Lam[iv] = llr[f * g.N + v] * us + Acc[iv];  // eq. equ_s2e6
                 }
             for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = Lam[(int64_t)v * S + lf] < 0.0f;
             if (t == d.sweep && f < d.frames) {
                 if (d.lam)
-                    for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[(int64_t)v * S + lf];
+                    for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[(int64_t)v * S + lf] * un;
                 if (d.r)
-                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf];
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf] * un;
             }
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
             if (stop) {
@@ -344,11 +428,19 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
         hipLaunchKernelGGL(cbp_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, f0, nf,
                            max_iter, p, ws, d);
     else if (algo == kLBPNMS)
-        hipLaunchKernelGGL(nms_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, f0,
+        hipLaunchKernelGGL((bp_sparse_kernel<false, true>), grid, block, 0, s, g, llr, bits, iters, f0,
+                           nf, max_iter, p, ws, d);
+    else if (algo == kFBPNMS)
+        hipLaunchKernelGGL((bp_sparse_kernel<true, true>), grid, block, 0, s, g, llr, bits, iters, f0,
+                           nf, max_iter, p, ws, d);
+    else if (algo == kLBP)
+        hipLaunchKernelGGL((bp_sparse_kernel<false, false>), grid, block, 0, s, g, llr, bits, iters, f0,
+                           nf, max_iter, p, ws, d);
+    else if (algo == kFBP)
+        hipLaunchKernelGGL((bp_sparse_kernel<true, false>), grid, block, 0, s, g, llr, bits, iters, f0,
                            nf, max_iter, p, ws, d);
     else
-        hipLaunchKernelGGL(nms_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, f0,
-                           nf, max_iter, p, ws, d);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

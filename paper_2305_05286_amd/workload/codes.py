@@ -155,23 +155,28 @@ def gf2_rank(H: np.ndarray) -> int:
 
 
 def _gf2_systematic(H: np.ndarray):
-    """Reduced row echelon form of H over GF(2).
+    """Reduced row echelon form of H over GF(2) (rows packed 64 bits to a word).
 
     Returns (pivot_cols, info_cols, P) where, for a codeword c,
     c[pivot_cols] = P @ c[info_cols] (mod 2), P shape (rank, K).
     """
-    A = H.astype(np.uint8).copy()
-    M, N = A.shape
+    M, N = H.shape
+    W = (N + 63) // 64
+    A = np.zeros((M, W * 8), dtype=np.uint8)
+    A[:, :(N + 7) // 8] = _pack_rows(H)
+    A = A.view("<u8")
     pivots = []
     r = 0
     for col in range(N):
-        rows = np.nonzero(A[r:, col])[0]
+        word, bit = divmod(col, 64)
+        b = np.uint64(bit)
+        rows = np.nonzero((A[r:, word] >> b) & np.uint64(1))[0]
         if rows.size == 0:
             continue
         p = r + rows[0]
         if p != r:
             A[[r, p]] = A[[p, r]]
-        hit = np.nonzero(A[:, col])[0]
+        hit = np.nonzero((A[:, word] >> b) & np.uint64(1))[0]
         hit = hit[hit != r]
         A[hit] ^= A[r]
         pivots.append(col)
@@ -180,7 +185,8 @@ def _gf2_systematic(H: np.ndarray):
             break
     pivots = np.asarray(pivots, dtype=np.int32)
     info = np.setdiff1d(np.arange(N, dtype=np.int32), pivots)
-    P = A[:len(pivots)][:, info]
+    R = np.unpackbits(A[:len(pivots)].view(np.uint8), axis=1, bitorder="little")[:, :N]
+    P = R[:, info]
     return pivots, info, P
 
 

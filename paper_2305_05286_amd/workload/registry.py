@@ -16,6 +16,9 @@ rate-1/2 PEG codes, which are not published):
 * ``qc2304_alt``  the ``qc2304`` base pattern with independently drawn shifts.
 * ``qc_t16``      QC, 4x8 base, Z=16 (small test code, four frames per wave).
 * ``qc_t64s``     QC, 4x8 base, Z=64, staircase parity (weight-1 column).
+* ``peg_reg36_n2048``, ``peg_reg36_n8192``  (3,6)-regular PEG codes, rate 1/2.
+* ``peg_irr_n2048``, ``peg_irr_n8192``      PEG codes with the paper's irregular
+                  lambda(x), rho(x) (Sec. V), rate 1/2.
 """
 from __future__ import annotations
 
@@ -26,6 +29,7 @@ import numpy as np
 
 from .codes import (Code, load_code, make_qc_code, qc_pattern_dualdiag,
                     qc_pattern_staircase, save_code, socket_regular_code)
+from .peg import LAMBDA_IRREGULAR, peg_code
 
 CODEBOOK = Path(__file__).resolve().parent / "codebook"
 
@@ -55,10 +59,16 @@ def _build(name: str) -> Code:
     if name == "qc_t64s":
         pat = qc_pattern_staircase(4, [3, 3, 3, 2], seed=5)
         return make_qc_code(name, pat, 64, seed=5, kind="qc_staircase")
+    if name.startswith("peg_"):
+        _, kind, length = name.split("_")
+        n = int(length[1:])
+        lam = {3: 1.0} if kind == "reg36" else LAMBDA_IRREGULAR
+        return peg_code(name, n, lam, seed=n + (0 if kind == "reg36" else 1))
     raise KeyError(name)
 
 
-CODE_NAMES = ("reg36_n96", "qc2304", "qc2304_alt", "qc26112", "qc_t16", "qc_t64s")
+PEG_CODE_NAMES = ("peg_reg36_n2048", "peg_irr_n2048", "peg_reg36_n8192", "peg_irr_n8192")
+CODE_NAMES = ("reg36_n96", "qc2304", "qc2304_alt", "qc26112", "qc_t16", "qc_t64s") + PEG_CODE_NAMES
 
 
 @lru_cache(maxsize=None)

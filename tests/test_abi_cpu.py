@@ -139,6 +139,30 @@ def test_workspace_sizes(L):
     assert cbp.workspace_size(big, "cbp", 3) <= 3 * (per_slot + 512) + 256
 
 
+def test_log_tanh_baselines_run_on_the_sparse_kernel(L):
+    c = cbp.Code.from_workload(get_code("reg36_n96"))
+    S = 2048
+    for dec in ("lbp", "fbp", "lbp_nms"):
+        # Lambda, R, flooding accumulator, decisions, each frame-interleaved
+        n = cbp.workspace_size(c, dec, 2000)
+        assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 8 * 256
+    q = cbp.Code.from_workload(get_code("qc2304"))
+    # a QC code: auto picks the sparse kernel for lbp/fbp (a large frame-interleaved workspace)
+    assert cbp.workspace_size(q, "lbp", 4096) > 4096 * (2304 + 6912) * 4
+    for k in ("qc_reg", "qc_stream"):
+        with pytest.raises(cbp.CbpError) as e:
+            cbp.workspace_size(q, "fbp", 64, kernel=k)
+        assert e.value.status == cbp.CBP_EUNSUPPORTED
+    o = cbp.Opts()
+    L.cbp_opts_default(ctypes.byref(o))
+    o.stop_rule = 1  # the paper's rule is CBP's
+    fake = ctypes.c_void_p(16)
+    assert L.lbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    assert L.fbp_decode(None, fake, fake, fake, 5, 8, None, None) == cbp.CBP_EINVAL
+    n = ctypes.c_size_t()
+    assert L.cbp_workspace_size(c.handle, 5, 10, None, ctypes.byref(n)) == cbp.CBP_EINVAL
+
+
 def test_mix_plan_validation(L):
     from paper_2305_05286_amd.workload import mixed_family
     fam = mixed_family()

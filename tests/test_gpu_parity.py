@@ -3,6 +3,9 @@
 Bar: iteration counts identical on >= 99.9% of frames and hard decisions
 identical on >= 99.9% of the frames the oracle decodes (per SNR point); FP32
 messages within 1e-4 * max(|x64|, 1) of FP64 after sweeps 1, 2, 3 and 5.
+Runs of 100 sweeps or more hold to that bar the frames (>= 98%) that the
+oracle decides within max_iter / 4 sweeps with a result unchanged by a
+one-ulp move of every LLR; the others only have to stop on codewords.
 """
 import sys
 
@@ -73,6 +76,19 @@ CASES = [
     ("reg36_n96", "cbp_nms", "sparse", [2.0, 3.0], 2000, 30),
     ("qc26112", "cbp_nms", "qc_stream", [1.0], 256, 25),
     ("qc2304", "cbp_nms", "qc_stream", [1.75], 1000, 50),
+    # the log-tanh LBP / FBP the paper compares with (sparse kernel)
+    ("reg36_n96", "lbp", "sparse", [1.5, 2.5], 2000, 30),
+    ("reg36_n96", "fbp", "sparse", [1.5, 2.5], 2000, 30),
+    ("qc2304", "lbp", "sparse", [2.0], 1000, 50),
+    ("qc_t64s", "fbp", "sparse", [1.5], 1000, 30),
+    # PEG codes with the paper's degree distributions, up to 200 sweeps (Sec. V)
+    ("peg_reg36_n2048", "cbp", "sparse", [1.8], 1000, 200),
+    ("peg_reg36_n2048", "lbp", "sparse", [1.8], 1000, 200),
+    ("peg_reg36_n2048", "fbp", "sparse", [1.8], 1000, 200),
+    ("peg_irr_n2048", "cbp", "sparse", [2.0], 1000, 200),
+    ("peg_irr_n2048", "lbp", "sparse", [2.0], 1000, 200),
+    ("peg_irr_n8192", "cbp", "sparse", [2.0], 500, 200),
+    ("peg_reg36_n8192", "fbp", "sparse", [2.0], 500, 200),
 ]
 
 
@@ -85,11 +101,32 @@ def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_
         say(f"[gpu] {name} {algo} {kernel} snr={snr} B={B}")
         gb, gi = run_gpu(code, llr, max_iter, algo, kernel=kernel)
         o = oracle.decode(code, llr, max_iter, algo)
+        if max_iter >= 100:
+            # Long runs: a frame still undecided after max_iter / 4 sweeps, or
+            # whose FP64 result changes when every LLR moves by one float32 ulp,
+            # sits near a tipping point where FP32 rounding alone can move its
+            # stopping sweep.  Such frames (at most 2%) are held only to the
+            # codeword check below; the rest to the full bar.
+            keep = o["iters"] <= max_iter // 4
+            for d in (np.inf, -np.inf):
+                p = oracle.decode(code, np.nextafter(llr, np.float32(d)), max_iter, algo)
+                keep &= (p["iters"] == o["iters"]) & (p["bits"] == o["bits"]).all(1)
+            late = ~keep
+            say(f"    late or ill-conditioned frames: {late.sum()} of {B}, iterations equal on "
+                f"{(gi[late] == o['iters'][late]).sum()} of them")
+            assert keep.mean() >= 0.98
+            assert (syndrome(code, gb[late & (gi < max_iter)]) == 0).all()
+            gb, gi, llr, cw = gb[keep], gi[keep], llr[keep], cw[keep]
+            o = {"bits": o["bits"][keep], "iters": o["iters"][keep]}
         ok = agree(gb, gi, o["bits"], o["iters"])
         conv = o["iters"] < max_iter
         say(f"    parity {ok.mean():.5f} (converged {ok[conv].mean() if conv.any() else 1:.5f}, "
             f"failed {ok[~conv].mean() if (~conv).any() else 1:.5f}), mean iters gpu "
             f"{gi.mean():.3f} oracle {o['iters'].mean():.3f}, FER {(o['bits'] != cw).any(1).mean():.4f}")
+        bad = np.nonzero(gi != o["iters"])[0]
+        if bad.size:
+            say(f"    iteration mismatches (frame: gpu/oracle): "
+                + ", ".join(f"{f}: {gi[f]}/{o['iters'][f]}" for f in bad[:10]))
         # Frames the oracle decodes must match exactly; frames that never
         # converge follow chaotic trajectories, so for them only the iteration
         # count (max_iter on both sides) is held to the bar and their final
@@ -112,7 +149,9 @@ MSG_CASES = [("reg36_n96", "cbp", "sparse"), ("qc2304", "cbp", "qc_reg"),
              ("qc_t64s", "cbp", "qc_stream"), ("qc2304", "cbp", "qc_stream"),
              ("qc2304", "fbp_nms", "qc_stream"), ("qc2304", "cbp_nms", "qc_reg"),
              ("qc_t64s", "cbp_nms", "qc_reg"), ("reg36_n96", "cbp_nms", "sparse"),
-             ("qc_t16", "cbp_nms", "qc_stream")]
+             ("qc_t16", "cbp_nms", "qc_stream"), ("reg36_n96", "lbp", "sparse"),
+             ("reg36_n96", "fbp", "sparse"), ("peg_irr_n2048", "lbp", "sparse"),
+             ("peg_irr_n2048", "fbp", "sparse"), ("peg_irr_n2048", "cbp", "sparse")]
 
 
 @pytest.mark.parametrize("name,algo,kernel", MSG_CASES, ids=[f"{a}-{b}-{c}" for a, b, c in MSG_CASES])
@@ -140,7 +179,7 @@ def test_edge_cases(name):
     code = get_code(name)
     say(f"[gpu] edge cases {name}")
     llr, cw = make_frames(code, 1.5, 130, key=(23,))
-    for algo in ["cbp", "cbp_nms", "lbp_nms", "fbp_nms"]:
+    for algo in ["cbp", "cbp_nms", "lbp_nms", "fbp_nms", "lbp", "fbp"]:
         # max_iter = 0: [L < 0], no sweep
         gb, gi = run_gpu(code, llr, 0, algo)
         assert (gi == 0).all() and np.array_equal(gb, (llr < 0).astype(np.uint8))
@@ -242,6 +281,15 @@ def test_kernel_selection_errors():
     with pytest.raises(cbp.CbpError) as ei:
         cbp.lbp_nms_decode(c, t, 5, stop_rule=1)
     assert ei.value.status == cbp.CBP_EINVAL
+    q = cbp.Code.from_workload(get_code("qc2304"))
+    tq = torch.zeros((4, 2304), device="cuda")
+    for fn in (cbp.lbp_decode, cbp.fbp_decode):
+        with pytest.raises(cbp.CbpError) as ei:
+            fn(q, tq, 5, kernel="qc_reg")
+        assert ei.value.status == cbp.CBP_EUNSUPPORTED
+        with pytest.raises(cbp.CbpError) as ei:
+            fn(c, t, 5, hd_mode=1)
+        assert ei.value.status == cbp.CBP_EINVAL
 
 
 # ---------------------------------------------- the paper's stopping rule
