@@ -69,7 +69,8 @@ int cbp_code_info(const cbp_code_t *code, int32_t *M, int32_t *N, int64_t *E, in
 #define CBP_KERNEL_AUTO 0
 #define CBP_KERNEL_QC_REG 1    /* QC: frame state in VGPRs + LDS (compiled base patterns) */
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
-#define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, frame-interleaved state     */
+#define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, persistent (lanes take new  */
+                               /* frames as theirs stop), state per wave contiguous      */
 
 #define CBP_RULE_LOG_TANH 0
 #define CBP_RULE_MIN_SUM 1
@@ -114,8 +115,10 @@ typedef struct {
     float *dump_r;
     float *dump_om;
     float *dump_lam;
-    /* Optional caller-provided device workspace (see cbp_workspace_size); if
-     * NULL or too small the call allocates one stream-ordered. */
+    /* Optional caller-provided device workspace (see cbp_workspace_size),
+     * 256-byte aligned; if NULL or too small the call allocates one
+     * stream-ordered.  Its contents on entry are ignored (frame counters in it
+     * are reset by the call); calls sharing one workspace must not overlap. */
     void *workspace;
     size_t workspace_bytes;
 } cbp_opts_t;
@@ -170,7 +173,9 @@ int fbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
 
 /* Device workspace (bytes) the given decoder needs for `batch` frames with
  * these options; decoder: 0 = cbp_decode, 1 = lbp_nms_decode, 2 = fbp_nms_decode,
- * 3 = lbp_decode, 4 = fbp_decode. */
+ * 3 = lbp_decode, 4 = fbp_decode.  The sparse kernel's workspace holds at most
+ * 131072 frames' state (and at most 32 GiB): it does not grow with larger
+ * batches. */
 int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch,
                        const cbp_opts_t *opts, size_t *bytes);
 

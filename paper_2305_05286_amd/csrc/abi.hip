@@ -338,17 +338,24 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     return CBP_OK;
 }
 
-// Frames of one sparse launch, workspace at most 32 GiB (e.g. 175k frames of
-// an n = 8192 code).  A launch lasts as long as its slowest frame, so large
-// batches should run in as few launches as memory allows.
-constexpr int64_t kSparseChunkBytes = (int64_t)32 << 30;
+// State slots (lanes) of the persistent sparse launch: one per frame, up to
+// 2048 waves and at most 32 GiB of frame state (e.g. 131k slots, 25 GB, for an
+// n = 8192 code).  Measured on n = 2048 and 8192 codes, throughput stops
+// growing at about 1000 waves; once the batch is drained a launch waits only
+// for its slowest frames.
+#ifndef CBP_SPARSE_MAX_WAVES
+#define CBP_SPARSE_MAX_WAVES 2048
+#endif
+constexpr int64_t kSparseMaxLanes = (int64_t)CBP_SPARSE_MAX_WAVES * 64;
+constexpr int64_t kSparseMaxBytes = (int64_t)32 << 30;
+constexpr size_t kSparseCounterBytes = 256;  // frame counter ahead of the slots
 
-int64_t sparse_chunk_frames(int algo, const SparseDev &g, int64_t batch) {
-    const size_t per = sparse_ws_bytes(algo, g, 64) / 64 + 1;
-    int64_t n = kSparseChunkBytes / (int64_t)per;
-    n = n / 64 * 64;
+int64_t sparse_lanes(int algo, const SparseDev &g, int64_t batch) {
+    const int64_t per = (int64_t)(sparse_ws_bytes(algo, g, 64) / 64) + 1;
+    int64_t n = std::min<int64_t>(kSparseMaxLanes, kSparseMaxBytes / per) / 64 * 64;
     if (n < 64) n = 64;
-    return batch < n ? batch : n;
+    const int64_t b = (batch + 63) / 64 * 64;
+    return b < n ? b : n;
 }
 
 // Streamed QC kernel: at most this many frames (slots) in flight per call,
@@ -393,7 +400,7 @@ size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kerne
         const StreamLaunch L = single_stream(algo, code, batch);
         return 256 + (size_t)L.groups * L.group_bytes;
     }
-    return sparse_ws_bytes(algo, g, sparse_chunk_frames(algo, g, batch));
+    return kSparseCounterBytes + sparse_ws_bytes(algo, g, sparse_lanes(algo, g, batch));
 }
 
 int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, int32_t *iters,
@@ -445,12 +452,10 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
             e = launch_qc_stream(algo, L, llr, bits, iters, batch, nullptr, nullptr, nullptr,
                                  (unsigned int *)ws, max_iter, r.p, r.d, (char *)ws + 256, s);
     } else {
-        const int64_t chunk = sparse_chunk_frames(algo, *g, batch);
-        SparseWs w = sparse_ws_carve(algo, *g, chunk, ws);
-        for (int64_t f0 = 0; f0 < batch && e == hipSuccess; f0 += chunk) {
-            const int64_t nf = batch - f0 < chunk ? batch - f0 : chunk;
-            e = launch_sparse(algo, *g, llr, bits, iters, f0, nf, max_iter, r.p, w, r.d, s);
-        }
+        const SparseWs w = sparse_ws_carve(algo, *g, sparse_lanes(algo, *g, batch),
+                                           (char *)ws + kSparseCounterBytes);
+        e = launch_sparse(algo, *g, llr, bits, iters, batch, max_iter, r.p, w, r.d,
+                          (unsigned long long *)ws, s);
     }
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);

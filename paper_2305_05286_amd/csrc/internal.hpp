@@ -52,19 +52,26 @@ struct SparseDev {
     const int *last_edge; // [N]  edge of the highest row of each column
 };
 
-// Frame-interleaved workspace of the sparse kernels: element (index, frame)
-// lives at array[index * stride + frame].
+// Workspace of the sparse kernels: one contiguous block per wave (its 64
+// lanes' state), frame-interleaved inside it — element (index, lane) of wave
+// w lives at array[w * block_bytes + index * stride + lane] with stride = 64,
+// so a wave's accesses are 256-byte lines within a few MB of its own.
 struct SparseWs {
-    int64_t stride;
-    float *a0, *a1, *a2, *a3, *a4;  // meaning depends on the algorithm
+    int64_t stride;       // lanes per block (64)
+    int64_t block_bytes;  // bytes from one wave's block to the next
+    int64_t waves;        // blocks (= state slots / 64)
+    float *a0, *a1, *a2, *a3, *a4;  // wave 0's arrays; meaning depends on the algorithm
     uint8_t *xb;
 };
 
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames);
 SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base);
+// Persistent sparse launch: one wave per block of `ws`, lanes take frames
+// 0 .. nf-1 from `counter` (8 bytes, reset by the launch).
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
-                         int32_t *iters, int64_t f0, int64_t nf, int max_iter,
-                         const Params &p, const SparseWs &ws, const Dump &d, hipStream_t s);
+                         int32_t *iters, int64_t nf, int max_iter, const Params &p,
+                         const SparseWs &ws, const Dump &d, unsigned long long *counter,
+                         hipStream_t s);
 hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);

@@ -5,8 +5,10 @@
 // reads are wave-uniform (scalar loads through the constant address space)
 // and the per-frame state is stored
 // frame-interleaved (index-major, frame-minor) so that each access of a wave
-// is one contiguous 256-byte line.  Frames that have stopped are masked off;
-// the wave leaves its loop once every lane has stopped.
+// is one contiguous 256-byte line.  The grid is persistent: a lane owns one
+// state slot and takes the next frame of the batch from a global counter as
+// soon as its frame stops, so a slow frame holds up only its own lane; the
+// wave leaves its loop once the batch is exhausted and every lane is done.
 #include "internal.hpp"
 #include "phi.hpp"
 
@@ -32,6 +34,32 @@ __device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int6
                           uint8_t *bits, int32_t *iters, int64_t f, int t) {
     for (int v = 0; v < g.N; ++v) bits[f * g.N + v] = xb[(int64_t)v * S + lf];
     iters[f] = t;
+}
+
+// This wave's block of the workspace.
+__device__ __forceinline__ SparseWs wave_block(SparseWs w) {
+    const int64_t off = (int64_t)gid_x() * w.block_bytes;
+    auto at = [off](auto *p) { return p ? (decltype(p))((char *)p + off) : p; };
+    w.a0 = at(w.a0);
+    w.a1 = at(w.a1);
+    w.a2 = at(w.a2);
+    w.a3 = at(w.a3);
+    w.a4 = at(w.a4);
+    w.xb = at(w.xb);
+    return w;
+}
+
+// The next frame index for every lane in `want` (a wave-uniform ballot): one
+// atomic add per wave on the batch's frame counter, then each wanting lane
+// takes base + (wanting lanes below it).  Values of other lanes are undefined.
+__device__ __forceinline__ int64_t claim_frames(unsigned long long *counter, uint64_t want) {
+    const int leader = __builtin_ctzll(want);
+    unsigned long long base = 0;
+    if (tid_x() == leader) base = atomicAdd(counter, (unsigned long long)__builtin_popcountll(want));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+    const uint64_t below = want & ((1ull << tid_x()) - 1ull);
+    return (int64_t)((((uint64_t)hi << 32) | lo) + (uint64_t)__builtin_popcountll(below));
 }
 
 // --------------------------------------------------------------------------
@@ -89,11 +117,10 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, int64_t l
 template <bool kMin>
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
-    int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
-    Dump d) {
-    const int64_t lf = (int64_t)gid_x() * kWave + tid_x();
-    const bool valid = lf < nf;
-    const int64_t f = f0 + lf;
+    int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
+    unsigned long long *counter) {
+    w = wave_block(w);
+    const int64_t lf = tid_x();  // this lane's slot in its wave's block
     const int64_t S = w.stride;
     float *Q = w.a0, *PQ = w.a1, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
@@ -101,26 +128,40 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     p.a *= us;
     p.lmax *= us;
     uint8_t *xb = w.xb;
-    bool active = valid;
+    int64_t f = 0;  // the lane's frame
+    int t = 0;      // sweeps done on it
+    bool need = true, done = false;
     // paper's stopping rule (stop_rule 1): check updates in a row, across
     // sweeps, whose belief is positive and that flipped no decision
     int64_t run = 0;
-    // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
-    if (valid) {
-        for (int v = 0; v < g.N; ++v) {
-            const float l = llr[f * g.N + v] * us;
-            Q[(int64_t)v * S + lf] = l;
-            xb[(int64_t)v * S + lf] = l < 0.0f;
+    for (;;) {
+        for (uint64_t want = __ballot(need); want != 0; want = __ballot(need)) {
+            const int64_t fn = claim_frames(counter, want);
+            if (need) {
+                need = false;
+                f = fn;
+                if (f >= nf) {
+                    done = true;
+                } else {
+                    // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
+                    for (int v = 0; v < g.N; ++v) {
+                        const float l = llr[f * g.N + v] * us;
+                        Q[(int64_t)v * S + lf] = l;
+                        xb[(int64_t)v * S + lf] = l < 0.0f;
+                    }
+                    for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+                    t = 0;
+                    run = 0;
+                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf))) {
+                        write_out(g, xb, S, lf, bits, iters, f, 0);
+                        need = true;
+                    }
+                }
+            }
         }
-        for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
-        if (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) {
-            write_out(g, xb, S, lf, bits, iters, f, 0);
-            active = false;
-        }
-    }
-    for (int t = 1; t <= max_iter; ++t) {
-        if (__ballot(active) == 0) break;
-        if (active) {
+        if (__ballot(!done) == 0) break;
+        if (!done) {
+            ++t;
             // Step 2: check-nodes in index order
             bool paper_stop = false;
             int istop = 0;
@@ -204,7 +245,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                     for (int v = 0; v < g.N; ++v)
                         xb[(int64_t)v * S + lf] = cbp_flushed_at<kMin>(g, w, lf, v, p, istop, t) < 0.0f;
                 write_out(g, xb, S, lf, bits, iters, f, t);
-                active = false;
+                need = true;
                 continue;
             }
             if (p.hd_mode == 1)
@@ -227,11 +268,10 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
             if (stop) {
                 write_out(g, xb, S, lf, bits, iters, f, t);
-                active = false;
+                need = true;
             }
         }
     }
-    if (active) write_out(g, xb, S, lf, bits, iters, f, max_iter);  // max_iter == 0
 }
 
 // --------------------------------------------------------------------------
@@ -245,11 +285,10 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
 template <bool kFlood, bool kMin>
 __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
-    int32_t *__restrict__ iters, int64_t f0, int64_t nf, int max_iter, Params p, SparseWs w,
-    Dump d) {
-    const int64_t lf = (int64_t)gid_x() * kWave + tid_x();
-    const bool valid = lf < nf;
-    const int64_t f = f0 + lf;
+    int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
+    unsigned long long *counter) {
+    w = wave_block(w);
+    const int64_t lf = tid_x();  // this lane's slot in its wave's block
     const int64_t S = w.stride;
     float *Lam = w.a0, *R = w.a1, *Acc = w.a2;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
@@ -257,22 +296,35 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
     p.a *= us;
     p.lmax *= us;
     uint8_t *xb = w.xb;
-    bool active = valid;
-    if (valid) {
-        for (int v = 0; v < g.N; ++v) {
-            const float l = llr[f * g.N + v] * us;
-            Lam[(int64_t)v * S + lf] = l;
-            xb[(int64_t)v * S + lf] = l < 0.0f;
+    int64_t f = 0;  // the lane's frame
+    int t = 0;      // sweeps done on it
+    bool need = true, done = false;
+    for (;;) {
+        for (uint64_t want = __ballot(need); want != 0; want = __ballot(need)) {
+            const int64_t fn = claim_frames(counter, want);
+            if (need) {
+                need = false;
+                f = fn;
+                if (f >= nf) {
+                    done = true;
+                } else {
+                    for (int v = 0; v < g.N; ++v) {
+                        const float l = llr[f * g.N + v] * us;
+                        Lam[(int64_t)v * S + lf] = l;
+                        xb[(int64_t)v * S + lf] = l < 0.0f;
+                    }
+                    for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+                    t = 0;
+                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf))) {
+                        write_out(g, xb, S, lf, bits, iters, f, 0);
+                        need = true;
+                    }
+                }
+            }
         }
-        for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
-        if (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) {
-            write_out(g, xb, S, lf, bits, iters, f, 0);
-            active = false;
-        }
-    }
-    for (int t = 1; t <= max_iter; ++t) {
-        if (__ballot(active) == 0) break;
-        if (active) {
+        if (__ballot(!done) == 0) break;
+        if (!done) {
+            ++t;
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) Acc[(int64_t)v * S + lf] = 0.0f;
             for (int i = 0; i < g.M; ++i) {
@@ -355,11 +407,10 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
             if (stop) {
                 write_out(g, xb, S, lf, bits, iters, f, t);
-                active = false;
+                need = true;
             }
         }
     }
-    if (active) write_out(g, xb, S, lf, bits, iters, f, max_iter);
 }
 
 __global__ __launch_bounds__(kSyndromeBlock) void syndrome_kernel(SparseDev g, const uint8_t *__restrict__ bits,
@@ -384,61 +435,69 @@ __global__ __launch_bounds__(kFillBlock) void fill_i32_kernel(int *p, int n, int
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Bytes of one wave's block: each array padded to 256 bytes.
+static int64_t sparse_block_bytes(int algo, const SparseDev &g) {
+    auto arr = [](int64_t n, int64_t bytes) { return round_up(n * kWave * bytes, 256); };
+    if (algo == kCBP || algo == kCBPNMS)
+        return 2 * arr(g.N, 4) + arr(g.E, 4) + 2 * arr(g.M, 4) + arr(g.N, 1);
+    return 2 * arr(g.N, 4) + arr(g.E, 4) + arr(g.N, 1);
+}
+
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames) {
-    const int64_t S = round_up(frames, kWave);
-    const bool belief = algo == kCBP || algo == kCBPNMS;
-    int64_t floats = belief ? (2LL * g.N + g.E + 2LL * g.M) : (2LL * g.N + g.E);
-    // each array starts on a 256-byte boundary
-    return (size_t)(floats * S * 4 + (int64_t)g.N * S + 8 * 256);
+    return (size_t)(round_up(frames, kWave) / kWave * sparse_block_bytes(algo, g));
 }
 
 SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base) {
     SparseWs w{};
-    w.stride = round_up(frames, kWave);
-    const int64_t S = w.stride;
+    w.stride = kWave;
+    w.block_bytes = sparse_block_bytes(algo, g);
+    w.waves = round_up(frames, kWave) / kWave;
     char *p = (char *)base;
-    auto take = [&](int64_t bytes) {
+    auto take = [&](int64_t n, int64_t bytes) {
         char *r = p;
-        p += round_up(bytes, 256);
+        p += round_up(n * kWave * bytes, 256);
         return r;
     };
     if (algo == kCBP || algo == kCBPNMS) {
-        w.a0 = (float *)take(4LL * g.N * S);
-        w.a1 = (float *)take(4LL * g.N * S);
-        w.a2 = (float *)take(4LL * g.E * S);
-        w.a3 = (float *)take(4LL * g.M * S);
-        w.a4 = (float *)take(4LL * g.M * S);
+        w.a0 = (float *)take(g.N, 4);
+        w.a1 = (float *)take(g.N, 4);
+        w.a2 = (float *)take(g.E, 4);
+        w.a3 = (float *)take(g.M, 4);
+        w.a4 = (float *)take(g.M, 4);
     } else {
-        w.a0 = (float *)take(4LL * g.N * S);
-        w.a1 = (float *)take(4LL * g.E * S);
-        w.a2 = (float *)take(4LL * g.N * S);
+        w.a0 = (float *)take(g.N, 4);
+        w.a1 = (float *)take(g.E, 4);
+        w.a2 = (float *)take(g.N, 4);
     }
-    w.xb = (uint8_t *)take((int64_t)g.N * S);
+    w.xb = (uint8_t *)take(g.N, 1);
     return w;
 }
 
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
-                         int32_t *iters, int64_t f0, int64_t nf, int max_iter, const Params &p,
-                         const SparseWs &ws, const Dump &d, hipStream_t s) {
-    const dim3 grid((unsigned)((nf + kWave - 1) / kWave)), block(kWave);
+                         int32_t *iters, int64_t nf, int max_iter, const Params &p,
+                         const SparseWs &ws, const Dump &d, unsigned long long *counter,
+                         hipStream_t s) {
+    // one lane per state slot; the frame counter starts at zero
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kFillBlock), 0, s, (int *)counter, 2, 0);
+    const dim3 grid((unsigned)ws.waves), block(kWave);
     if (algo == kCBP)
-        hipLaunchKernelGGL(cbp_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, f0, nf,
-                           max_iter, p, ws, d);
+        hipLaunchKernelGGL(cbp_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, nf,
+                           max_iter, p, ws, d, counter);
     else if (algo == kCBPNMS)
-        hipLaunchKernelGGL(cbp_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, f0, nf,
-                           max_iter, p, ws, d);
+        hipLaunchKernelGGL(cbp_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, nf,
+                           max_iter, p, ws, d, counter);
     else if (algo == kLBPNMS)
-        hipLaunchKernelGGL((bp_sparse_kernel<false, true>), grid, block, 0, s, g, llr, bits, iters, f0,
-                           nf, max_iter, p, ws, d);
+        hipLaunchKernelGGL((bp_sparse_kernel<false, true>), grid, block, 0, s, g, llr, bits, iters,
+                           nf, max_iter, p, ws, d, counter);
     else if (algo == kFBPNMS)
-        hipLaunchKernelGGL((bp_sparse_kernel<true, true>), grid, block, 0, s, g, llr, bits, iters, f0,
-                           nf, max_iter, p, ws, d);
+        hipLaunchKernelGGL((bp_sparse_kernel<true, true>), grid, block, 0, s, g, llr, bits, iters,
+                           nf, max_iter, p, ws, d, counter);
     else if (algo == kLBP)
-        hipLaunchKernelGGL((bp_sparse_kernel<false, false>), grid, block, 0, s, g, llr, bits, iters, f0,
-                           nf, max_iter, p, ws, d);
+        hipLaunchKernelGGL((bp_sparse_kernel<false, false>), grid, block, 0, s, g, llr, bits, iters,
+                           nf, max_iter, p, ws, d, counter);
     else if (algo == kFBP)
-        hipLaunchKernelGGL((bp_sparse_kernel<true, false>), grid, block, 0, s, g, llr, bits, iters, f0,
-                           nf, max_iter, p, ws, d);
+        hipLaunchKernelGGL((bp_sparse_kernel<true, false>), grid, block, 0, s, g, llr, bits, iters,
+                           nf, max_iter, p, ws, d, counter);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

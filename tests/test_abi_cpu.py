@@ -145,7 +145,7 @@ def test_log_tanh_baselines_run_on_the_sparse_kernel(L):
     for dec in ("lbp", "fbp", "lbp_nms"):
         # Lambda, R, flooding accumulator, decisions, each frame-interleaved
         n = cbp.workspace_size(c, dec, 2000)
-        assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 8 * 256
+        assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 9 * 256
     q = cbp.Code.from_workload(get_code("qc2304"))
     # a QC code: auto picks the sparse kernel for lbp/fbp (a large frame-interleaved workspace)
     assert cbp.workspace_size(q, "lbp", 4096) > 4096 * (2304 + 6912) * 4
