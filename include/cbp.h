@@ -235,7 +235,8 @@ int cbp_mix_workspace_size(const cbp_mix_t *mix, int32_t decoder, int64_t batch,
  *   iters_out    device int32 [batch]: sweeps executed; -1 for a frame whose
  *                code index is outside the plan or whose LLRs leave
  *                [0, llr_elems) (its decisions are not written).
- *   workspace    device buffer of at least cbp_mix_workspace_size bytes.
+ *   workspace    device buffer of at least cbp_mix_workspace_size bytes, 256-byte
+ *                aligned (CBP_EINVAL otherwise).
  * The call only launches kernels on `stream`: no allocation, no host
  * synchronisation, no memset node, so it may be captured in a HIP graph once
  * the plan has been used on the device (the first call uploads the code
@@ -298,7 +299,8 @@ void cbp_graph_free(cbp_graph_t *graph);
  *   grad_llr     device float32 [batch][N]: dLoss/d llr_in, or NULL.
  *   grad_w, grad_beta  device float32 [sweeps][nb]: dLoss/dw, dLoss/dbeta
  *                (summed over the batch; written, not accumulated).
- *   workspace    device buffer of at least cbp_unrolled_workspace_size bytes;
+ *   workspace    device buffer of at least cbp_unrolled_workspace_size bytes,
+ *                256-byte aligned (CBP_EINVAL otherwise);
  *                cbp_unrolled_backward must get the workspace of the
  *                cbp_unrolled_forward call with the same code, llr_in, batch,
  *                sweeps, w and beta, unmodified in between.

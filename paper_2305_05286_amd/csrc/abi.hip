@@ -333,6 +333,8 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     r->d.om = o->dump_om;
     r->d.lam = o->dump_lam;
     if (r->d.sweep == 0) r->d.frames = 0;
+    if (o->workspace && ((uintptr_t)o->workspace & 255))
+        return fail(CBP_EINVAL, "workspace must be 256-byte aligned");
     r->ws = o->workspace;
     r->ws_bytes = o->workspace_bytes;
     return CBP_OK;
@@ -567,6 +569,7 @@ int mix_decode_impl(const cbp_mix *mc, int32_t decoder, const float *llr, int64_
     L.codes = dc;
     const size_t need = mix_ws_bytes(L, batch);
     if (!ws || ws_bytes < need) return fail(CBP_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(CBP_EINVAL, "workspace must be 256-byte aligned");
     char *w = (char *)ws;
     unsigned int *counter = (unsigned int *)w;
     int64_t *qstart = (int64_t *)(w + 1024);
@@ -643,6 +646,7 @@ int unrolled_run(bool backward, const cbp_code_t *code, const float *llr, int64_
         return fail(CBP_EINVAL, "NULL buffer");
     const size_t need = (size_t)G.gpart_bytes + (size_t)G.groups * G.group_bytes;
     if (!ws || ws_bytes < need) return fail(CBP_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(CBP_EINVAL, "workspace must be 256-byte aligned");
     int dev = 0;
     const SparseDev *sg = nullptr;
     const DevTables *tab = nullptr;

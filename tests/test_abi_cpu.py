@@ -120,6 +120,12 @@ def test_decode_argument_errors_without_gpu(L):
     o.lmax = 20.0
     o.hd_mode = 1
     assert L.lbp_nms_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    o.hd_mode = 0
+    o.workspace = 4096 + 8  # a caller workspace must be 256-byte aligned
+    o.workspace_bytes = 1 << 30
+    assert L.lbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
+    assert b"aligned" in L.cbp_last_error()
+    o.workspace = None
     assert L.cbp_syndrome(None, None, None, 3, None) == cbp.CBP_EINVAL
 
 
