@@ -287,10 +287,13 @@ void cbp_graph_free(cbp_graph_t *graph);
  * streamed layout only.
  *
  * Memory: the forward pass keeps a checkpoint of the frame state (Q, R,
- * check-beliefs) after every sweep in the workspace; the backward pass
- * recomputes one sweep at a time from its checkpoint and runs the adjoint
- * backwards through it, so the workspace grows with sweeps x frame state, not
- * with the per-edge history of all sweeps.
+ * check-beliefs) at the start of every sweep after the first, and the final
+ * state, in the workspace; the backward pass recomputes one sweep at a time in
+ * place on its checkpoint and runs the adjoint backwards through it, so the
+ * workspace grows with sweeps x frame state, not with the per-edge history of
+ * all sweeps.  The backward pass consumes the checkpoints: call it at most
+ * once per forward call (a second call on the same workspace gives wrong
+ * gradients; run the forward again first).
  *
  *   w, beta      device float32 [sweeps][nb] (nb = base block-columns).
  *   llr_in       device float32 [batch][N].

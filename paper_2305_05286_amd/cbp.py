@@ -448,6 +448,9 @@ def _unrolled_fn():
 
         @staticmethod
         def backward(ctx, gout):
+            if ctx.ws is None:
+                raise RuntimeError("the unrolled decoder's backward pass consumes the forward pass's "
+                                   "checkpoints: run the forward pass again (retain_graph is not supported)")
             llr, w, beta = ctx.saved_tensors
             gout = gout.contiguous()
             B = llr.shape[0]

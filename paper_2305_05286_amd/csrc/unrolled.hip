@@ -14,11 +14,13 @@
 // pass performs exactly the streamed kernel's operations.
 //
 // Memory: the forward pass stores the state (Q, R, Omega) at the start of every
-// sweep after the first and after the last one (checkpoints).  The backward pass
-// walks the sweeps in reverse; for each it restores the checkpoint, recomputes
-// the sweep while writing a per-edge tape (Q_v before the visit, the excluded
-// phi-domain sum, R(c_i -> v) as read, the belief's parity), then applies the
-// adjoint layer by layer in reverse order.  Adjoint state: lambda_Q [N],
+// sweep after the first (checkpoints) and leaves the final state in the working
+// area.  The backward pass walks the sweeps in reverse; for each it recomputes
+// the sweep in place on the checkpoint it started from (which no later step
+// needs), writing a per-edge tape (Q_v before the visit, the excluded phi-domain
+// sum, R(c_i -> v) as read, the belief's parity), then applies the adjoint
+// layer by layer in reverse order.  The backward pass therefore consumes the
+// checkpoints: one backward per forward.  Adjoint state: lambda_Q [N],
 // lambda_R [E], lambda_T [M] (adjoint of each check's phi-domain total).  The
 // adjoint of a check total read by a B2V is scattered to the check's rows
 // through LDS (row k gathers from lane (k + s) mod Z), so no atomics are used and
@@ -59,8 +61,8 @@ __device__ __forceinline__ float dphi2(float x) {
     const float y2 = y * y;
     const float sh_small = y * (1.0f + y2 * (0.16666667f + y2 * (0.0083333333f + y2 * 0.00019841270f)));
     const float t = __builtin_amdgcn_exp2f(-x);
-    const float sh_large = (1.0f - t * t) / (2.0f * t);
-    return -1.0f / (y < 0.35f ? sh_small : sh_large);
+    const float sh_large = (1.0f - t * t) * __builtin_amdgcn_rcpf(2.0f * t);
+    return -__builtin_amdgcn_rcpf(y < 0.35f ? sh_small : sh_large);  // 1 ulp reciprocal
 }
 
 // d clamp(|q|) / dq
@@ -100,7 +102,7 @@ __device__ __forceinline__ Frame frame_of(const UnArgs &A, int slot, int l, int 
     F.oR = base + 4u * N;
     F.oOM = base + 4u * (N + EZ);
     F.oCk = base + F.ck;
-    const uint32_t after = F.oCk + F.ck * (uint32_t)A.T;  // checkpoints 1 .. T
+    const uint32_t after = F.oCk + F.ck * (uint32_t)(A.T - 1);  // checkpoints 1 .. T-1
     F.oLQ = after;
     F.oLR = after + 4u * N;
     F.oLT = after + 4u * (N + EZ);
@@ -108,11 +110,13 @@ __device__ __forceinline__ Frame frame_of(const UnArgs &A, int slot, int l, int 
     return F;
 }
 
-// One sweep of weighted CBP on the working state; kTape also writes the tape.
+// One sweep of weighted CBP, in place on the state at byte offset `st`
+// (Q [N], R [E][Z], Omega [M] float2 back to back); kTape also writes the tape.
 template <bool kTape>
-__device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const int4 *erec, int t,
+__device__ void sweep(const UnArgs &A, const Frame &F, uint32_t st, const int *rstart, const int4 *erec, int t,
                       float *sX, float a2, float lmax2) {
     const int Z = F.Z, l = F.l, NB = F.NB;
+    const uint32_t oQ = st, oR = st + 4u * (NB * Z), oOM = st + 4u * (NB * Z + F.E * Z);
     for (int r = 0; r < F.MB; ++r) {
         const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
         // two edges at a time: all loads before any store (distinct block-columns;
@@ -125,10 +129,10 @@ __device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const 
         };
         auto ld_edge = [&](int e, In &in) {
             in.ed = edge(erec, e);
-            in.q = F.W.ld(F.oQ + 4u * (in.ed.b * Z + l));
-            in.rci = F.W.ld(F.oR + 4u * (e * Z + l));
+            in.q = F.W.ld(oQ + 4u * (in.ed.b * Z + l));
+            in.rci = F.W.ld(oR + 4u * (e * Z + l));
             in.has = !(t == 0 && in.ed.first);
-            in.om = in.has ? F.W.ld2(F.oOM + 8u * (in.ed.epr * Z + wrapz(l - in.ed.epsh, Z))) : make_float2(0.0f, 0.0f);
+            in.om = in.has ? F.W.ld2(oOM + 8u * (in.ed.epr * Z + wrapz(l - in.ed.epsh, Z))) : make_float2(0.0f, 0.0f);
         };
         auto fin_edge = [&](int e, const In &in) {
             const Edge &ed = in.ed;
@@ -140,13 +144,13 @@ __device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const 
                 const int k = t * NB + ed.b;
                 const float mag = __builtin_fmaxf(ldc(A.w, k) * phi2(d) - ldc(A.beta, k) * kLog2e, 0.0f);
                 rn = with_sign(mag, sign_bit(in.om.x) ^ (q < 0.0f));
-                F.W.st(F.oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v)
+                F.W.st(oR + 4u * (ed.ep * Z + l), rn);  // commit R(c_j -> v)
                 own = ed.ep == e;
                 par = sign_bit(in.om.x) ? 1.0f : 0.0f;
             }
             const float rold = own ? rn : in.rci;
             const float qn = q + rn - rold;
-            F.W.st(F.oQ + 4u * (ed.b * Z + l), qn);
+            F.W.st(oQ + 4u * (ed.b * Z + l), qn);
             sX[(e - e0) * Z + wrapz(l - ed.sh, Z)] = with_sign(phi2_clamped(qn, a2, lmax2), qn < 0.0f);
             if constexpr (kTape) F.W.st4(F.oTape + 16u * (e * Z + l), make_float4(q, d, rold, par));
         };
@@ -172,7 +176,7 @@ __device__ void sweep(const UnArgs &A, const Frame &F, const int *rstart, const 
                 p ^= sign_bit(x);
                 fold(Mx, Sr, abs_bits(x));
             }
-            F.W.st2(F.oOM + 8u * (r * Z + l), make_float2(with_sign(Mx, p), Sr));
+            F.W.st2(oOM + 8u * (r * Z + l), make_float2(with_sign(Mx, p), Sr));
         }
         __syncthreads();
     }
@@ -209,9 +213,8 @@ __global__ __launch_bounds__(1024) void unrolled_fwd_kernel(UnArgs A) {
     __syncthreads();
     for (int t = 0; t < A.T; ++t) {
         if (t > 0) copy_state(F, F.oQ, F.oCk + F.ck * (uint32_t)(t - 1));
-        sweep<false>(A, F, rstart, erec, t, sX, a2, lmax2);
+        sweep<false>(A, F, F.oQ, rstart, erec, t, sX, a2, lmax2);
     }
-    copy_state(F, F.oQ, F.oCk + F.ck * (uint32_t)(A.T - 1));  // state after the last sweep
     for (int b = 0; b < NB; ++b) {
         const int el = ldc(cs->elast, b);
         const float2 om = F.W.ld2(F.oOM + 8u * (ldc(cs->er, el) * Z + wrapz(l - ldc(cs->esh, el), Z)));
@@ -238,8 +241,8 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
     const int64_t f = (int64_t)gid_x() * SL + slot;
     const bool have = f < A.batch;
     const float a2 = A.a * kLog2e, lmax2 = A.lmax * kLog2e;
-    const int DM = A.dcmax > NB ? A.dcmax : NB;
-    // LDS: exchange [SL][dcmax][Z], row adjoints [SL][Z], scatter [SL][DM][Z],
+    const int DM = A.dcmax;
+    // LDS: exchange [SL][dcmax][Z], row adjoints [SL][Z], scatter [SL][dcmax][Z],
     // weight-gradient accumulators [NB][lanes] x 2
     float *sX = smem + (size_t)slot * A.dcmax * Z;
     float *sLall = smem + (size_t)A.lanes * A.dcmax;
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
     float *sAw = sLall + A.lanes + (size_t)A.lanes * DM;
     float *sAb = sAw + (size_t)NB * A.lanes;
     const Frame F = frame_of(A, slot, l, Z, NB, MB, E);
-    const uint32_t oFinal = F.oCk + F.ck * (uint32_t)(A.T - 1);
+    const uint32_t oFinal = F.oQ;  // the forward pass leaves the final state here
 
     for (int b = 0; b < NB; ++b) {
         sAw[b * A.lanes + tid] = 0.0f;
@@ -257,47 +260,54 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
     for (int e = 0; e < E; ++e) F.W.st(F.oLR + 4u * (e * Z + l), 0.0f);
     for (int r = 0; r < MB; ++r) F.W.st(F.oLT + 4u * (r * Z + l), 0.0f);
 
-    // ---- adjoint of the soft output o_v = Q_v + weighted B2V (last weights)
-    for (int b = 0; b < NB; ++b) {
-        const int el = ldc(cs->elast, b);
-        const float2 om = F.W.ld2(oFinal + 4u * (uint32_t)(N + E * Z) +
-                                  8u * (ldc(cs->er, el) * Z + wrapz(l - ldc(cs->esh, el), Z)));
-        const float q = F.W.ld(oFinal + 4u * (b * Z + l));
-        const float go = have ? A.gout[f * N + b * Z + l] * kLn2 : 0.0f;
-        const float d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
-        const int k = (A.T - 1) * NB + b;
-        const float wk = ldc(A.w, k), m = phi2(d);
-        const bool act = wk * m - ldc(A.beta, k) * kLog2e > 0.0f;
-        const bool neg = sign_bit(om.x) ^ (q < 0.0f);
-        const float lmag = neg ? -go : go;            // d o / d mag = sgn
-        const float lm = act ? lmag * wk : 0.0f;
-        sAw[b * A.lanes + tid] += act ? lmag * m : 0.0f;
-        sAb[b * A.lanes + tid] += act ? -lmag : 0.0f;
-        const float ld = lm * dphi2(d);
-        const float lq = go - ld * dphi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2)) *
-                                  dclamp(q, a2, lmax2);
-        F.W.st(F.oLQ + 4u * (b * Z + l), lq);
-        sD[b * Z + l] = ld;
+    // ---- adjoint of the soft output o_v = Q_v + weighted B2V (last weights),
+    // block-columns in chunks of DM (the scatter buffer's depth)
+    for (int b0 = 0; b0 < NB; b0 += DM) {
+        const int b1 = b0 + DM < NB ? b0 + DM : NB;
+        for (int b = b0; b < b1; ++b) {
+            const int el = ldc(cs->elast, b);
+            const float2 om = F.W.ld2(oFinal + 4u * (uint32_t)(N + E * Z) +
+                                      8u * (ldc(cs->er, el) * Z + wrapz(l - ldc(cs->esh, el), Z)));
+            const float q = F.W.ld(oFinal + 4u * (b * Z + l));
+            const float go = have ? A.gout[f * N + b * Z + l] * kLn2 : 0.0f;
+            const float d = excl_sum(abs_bits(om.x), om.y, phi2_clamped(q, a2, lmax2));
+            const int k = (A.T - 1) * NB + b;
+            const float wk = ldc(A.w, k), m = phi2(d);
+            const bool act = wk * m - ldc(A.beta, k) * kLog2e > 0.0f;
+            const bool neg = sign_bit(om.x) ^ (q < 0.0f);
+            const float lmag = neg ? -go : go;            // d o / d mag = sgn
+            const float lm = act ? lmag * wk : 0.0f;
+            sAw[b * A.lanes + tid] += act ? lmag * m : 0.0f;
+            sAb[b * A.lanes + tid] += act ? -lmag : 0.0f;
+            const float ld = lm * dphi2(d);
+            const float lq = go - ld * dphi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2)) *
+                                      dclamp(q, a2, lmax2);
+            F.W.st(F.oLQ + 4u * (b * Z + l), lq);
+            sD[(b - b0) * Z + l] = ld;
+        }
+        __syncthreads();
+        for (int b = b0; b < b1; ++b) {  // lane = row l of each check layer
+            const int el = ldc(cs->elast, b);
+            const uint32_t o = F.oLT + 4u * (ldc(cs->er, el) * Z + l);
+            F.W.st(o, F.W.ld(o) + sD[(b - b0) * Z + wrapz(l + ldc(cs->esh, el), Z)]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int b = 0; b < NB; ++b) {  // lane = row l of each check layer
-        const int el = ldc(cs->elast, b);
-        const uint32_t o = F.oLT + 4u * (ldc(cs->er, el) * Z + l);
-        F.W.st(o, F.W.ld(o) + sD[b * Z + wrapz(l + ldc(cs->esh, el), Z)]);
-    }
-    __syncthreads();
 
     for (int t = A.T - 1; t >= 0; --t) {
-        // restore the state at the start of sweep t and recompute it with the tape
+        // recompute sweep t with the tape, in place on the state it started
+        // from: checkpoint t (no longer needed once this sweep is differentiated),
+        // or for t = 0 the initial state rebuilt in the working area
+        uint32_t st = F.oQ;
         if (t > 0) {
-            copy_state(F, F.oCk + F.ck * (uint32_t)(t - 1), F.oQ);
+            st = F.oCk + F.ck * (uint32_t)(t - 1);
         } else {
             for (int b = 0; b < NB; ++b)
                 F.W.st(F.oQ + 4u * (b * Z + l), have ? A.llr[f * N + b * Z + l] * kLog2e : 0.0f);
             for (int e = 0; e < E; ++e) F.W.st(F.oR + 4u * (e * Z + l), 0.0f);
         }
         __syncthreads();
-        sweep<true>(A, F, rstart, erec, t, sX, a2, lmax2);
+        sweep<true>(A, F, st, rstart, erec, t, sX, a2, lmax2);
 
         for (int r = MB - 1; r >= 0; --r) {
             const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
@@ -307,11 +317,27 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                 F.W.st(o, 0.0f);
             }
             __syncthreads();
-            for (int e = e0; e < e1; ++e) {  // lane = variable
-                const Edge ed = edge(erec, e);
+            // lane = variable.  Two edges at a time, all loads before any store:
+            // the edges of a layer are distinct block-columns, so no load of
+            // one reads what the other stores (its own R(c_j -> v) and
+            // R(c_i -> v) coincide only in a degree-1 column, handled below).
+            struct AIn {
+                Edge ed;
+                float4 tp;        // tape: Q before the visit, excluded sum d, R(c_i -> v) read, parity
+                float lq, lrep, lre, lf;
+            };
+            auto ld_adj = [&](int e, AIn &in) {
+                in.ed = edge(erec, e);
+                in.tp = F.W.ld4(F.oTape + 16u * (e * Z + l));
+                in.lq = F.W.ld(F.oLQ + 4u * (in.ed.b * Z + l));
+                in.lrep = F.W.ld(F.oLR + 4u * (in.ed.ep * Z + l));
+                in.lre = F.W.ld(F.oLR + 4u * (e * Z + l));
+                in.lf = sL[wrapz(l - in.ed.sh, Z)];
+            };
+            auto fin_adj = [&](int e, const AIn &in) {
+                const Edge &ed = in.ed;
                 const int iv = ed.b * Z + l;
-                const float4 tp = F.W.ld4(F.oTape + 16u * (e * Z + l));
-                const float q = tp.x, d = tp.y, rold = tp.z;
+                const float q = in.tp.x, d = in.tp.y, rold = in.tp.z;
                 const bool has = d >= 0.0f;
                 float rn = 0.0f, m = 0.0f, wk = 0.0f;
                 bool act = false, neg = false;
@@ -320,20 +346,18 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                     wk = ldc(A.w, k);
                     m = phi2(d);
                     act = wk * m - ldc(A.beta, k) * kLog2e > 0.0f;
-                    neg = (tp.w != 0.0f) ^ (q < 0.0f);
+                    neg = (in.tp.w != 0.0f) ^ (q < 0.0f);
                     rn = with_sign(__builtin_fmaxf(wk * m - ldc(A.beta, k) * kLog2e, 0.0f), neg);
                 }
                 const bool own = has && ed.ep == e;
                 const float qn = q + rn - rold;
                 const float cn = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(qn), a2), lmax2);
-                const float lf = sL[wrapz(l - ed.sh, Z)];
-                const float lqn = F.W.ld(F.oLQ + 4u * iv) + lf * dphi2(cn) * dclamp(qn, a2, lmax2);
+                const float lqn = in.lq + in.lf * dphi2(cn) * dclamp(qn, a2, lmax2);
                 float lq = lqn;  // through lam = q + rn
                 float ld = 0.0f;
                 if (has) {
-                    const uint32_t oep = F.oLR + 4u * (ed.ep * Z + l);
-                    const float lrn = lqn + (own ? -lqn : 0.0f) + F.W.ld(oep);
-                    F.W.st(oep, 0.0f);  // R(c_j -> v) before the commit is dead
+                    const float lrn = lqn + (own ? -lqn : 0.0f) + in.lrep;
+                    F.W.st(F.oLR + 4u * (ed.ep * Z + l), 0.0f);  // R(c_j -> v) before the commit is dead
                     const float lmag = neg ? -lrn : lrn;
                     const float lm = act ? lmag * wk : 0.0f;
                     sAw[ed.b * A.lanes + tid] += act ? lmag * m : 0.0f;
@@ -342,12 +366,25 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                     const float cq = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2);
                     lq -= ld * dphi2(cq) * dclamp(q, a2, lmax2);
                 }
-                if (!own) {  // R(c_i -> v) as read by this visit
-                    const uint32_t oe = F.oLR + 4u * (e * Z + l);
-                    F.W.st(oe, F.W.ld(oe) - lqn);
-                }
+                if (!own)  // R(c_i -> v) as read by this visit (a different slot from R(c_j -> v) above)
+                    F.W.st(F.oLR + 4u * (e * Z + l), in.lre - lqn);
                 F.W.st(F.oLQ + 4u * iv, lq);
                 sD[(e - e0) * Z + l] = ld;
+            };
+            {
+                int e = e0;
+                for (; e + 1 < e1; e += 2) {
+                    AIn p0, p1;
+                    ld_adj(e, p0);
+                    ld_adj(e + 1, p1);
+                    fin_adj(e, p0);
+                    fin_adj(e + 1, p1);
+                }
+                if (e < e1) {
+                    AIn p0;
+                    ld_adj(e, p0);
+                    fin_adj(e, p0);
+                }
             }
             __syncthreads();
             for (int e = e0; e < e1; ++e) {  // lane = row l of the B2V's latest check
@@ -381,19 +418,33 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
             A.gllr[f * N + b * Z + l] = F.W.ld(F.oLQ + 4u * (b * Z + l)) * kLog2e;
 }
 
-// grad_w[t][b] = sum over workgroups, in workgroup order (deterministic);
-// beta enters in log2 units, hence the log2 e factor.
-__global__ __launch_bounds__(256) void unrolled_reduce_kernel(const float *gpart, int groups, int TNB,
-                                                              float *gw, float *gb) {
-    const int i = gid_x() * 256 + tid_x();
-    if (i >= TNB) return;
-    float sw = 0.0f, sb = 0.0f;
-    for (int g = 0; g < groups; ++g) {
-        sw += gpart[((int64_t)g * TNB + i) * 2];
-        sb += gpart[((int64_t)g * TNB + i) * 2 + 1];
+// grad_w[t][b] = sum over workgroups (deterministic: thread k sums workgroups
+// k, k + 256, ... in order, then a fixed-shape tree over the 256 partial sums);
+// one workgroup per (t, b).  beta enters in log2 units, hence the log2 e factor.
+constexpr int kReduceBlock = 256;
+__global__ __launch_bounds__(kReduceBlock) void unrolled_reduce_kernel(const float *gpart, int groups, int TNB,
+                                                                       float *gw, float *gb) {
+    __shared__ float sw[kReduceBlock], sb[kReduceBlock];
+    const int i = gid_x(), k = tid_x();
+    float w = 0.0f, b = 0.0f;
+    for (int g = k; g < groups; g += kReduceBlock) {
+        w += gpart[((int64_t)g * TNB + i) * 2];
+        b += gpart[((int64_t)g * TNB + i) * 2 + 1];
     }
-    gw[i] = sw;
-    gb[i] = sb * kLog2e;
+    sw[k] = w;
+    sb[k] = b;
+    __syncthreads();
+    for (int h = kReduceBlock / 2; h > 0; h /= 2) {
+        if (k < h) {
+            sw[k] += sw[k + h];
+            sb[k] += sb[k + h];
+        }
+        __syncthreads();
+    }
+    if (k == 0) {
+        gw[i] = sw[0];
+        gb[i] = sb[0] * kLog2e;
+    }
 }
 
 }  // namespace
@@ -401,7 +452,7 @@ __global__ __launch_bounds__(256) void unrolled_reduce_kernel(const float *gpart
 int64_t unrolled_frame_bytes(const StreamCode &c, int T) {
     const int64_t N = c.N, EZ = (int64_t)c.E * c.Z, M = (int64_t)c.mb * c.Z;
     const int64_t state = 4 * (N + EZ) + 8 * M;
-    int64_t b = state * (1 + T) + 4 * (N + EZ + M);
+    int64_t b = state * T + 4 * (N + EZ + M);  // working state + T-1 checkpoints, adjoints
     b = (b + 15) & ~(int64_t)15;
     b += 16 * EZ;  // tape
     return (b + 255) & ~(int64_t)255;
@@ -410,8 +461,7 @@ int64_t unrolled_frame_bytes(const StreamCode &c, int T) {
 size_t unrolled_lds_bytes(const StreamCode &c, int lanes, bool backward) {
     const size_t x = (size_t)lanes * c.dcmax;
     if (!backward) return 4 * x;
-    const int DM = c.dcmax > c.nb ? c.dcmax : c.nb;
-    return 4 * (x + lanes + (size_t)lanes * DM + 2 * (size_t)c.nb * lanes);
+    return 4 * (2 * x + lanes + 2 * (size_t)c.nb * lanes);
 }
 
 bool unrolled_fits(const StreamCode &c, int lanes) {
@@ -456,8 +506,7 @@ hipError_t launch_unrolled(bool backward, const StreamCode &host_code, const Str
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int TNB = T * host_code.nb;
-    hipLaunchKernelGGL(unrolled_reduce_kernel, dim3((TNB + 255) / 256), dim3(256), 0, s, gpart, groups, TNB,
-                       gw, gb);
+    hipLaunchKernelGGL(unrolled_reduce_kernel, dim3(TNB), dim3(kReduceBlock), 0, s, gpart, groups, TNB, gw, gb);
     return hipGetLastError();
 }
 

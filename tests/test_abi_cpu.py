@@ -202,7 +202,9 @@ def test_unrolled_workspace_and_validation(L):
     q = cbp.Code.from_workload(get_code("qc2304"))
     n = cbp.unrolled_workspace_size(q, 10, 8192)
     state = 4 * (2304 + 7296) + 8 * 1152                # Q, R, check-beliefs per frame
-    per_frame = state * 11 + 4 * (2304 + 7296 + 1152) + 16 * 7296
+    # working state + 9 checkpoints (the final state stays in the working
+    # area), adjoints, one sweep of tape
+    per_frame = state * 10 + 4 * (2304 + 7296 + 1152) + 16 * 7296
     assert 8192 * per_frame <= n <= 8192 * (per_frame + 512) + 4096 * 10 * 24 * 8 + 256
     assert cbp.unrolled_workspace_size(q, 10, 0) == 0
     for sweeps in (0, 65):

@@ -144,6 +144,26 @@ def test_backward_is_deterministic():
     assert torch.isfinite(grads[0][0]).all() and grads[0][0].abs().sum() > 0
 
 
+def test_second_backward_is_refused():
+    """The backward pass recomputes in place on the checkpoints, so it runs once per forward."""
+    code = get_code("qc_t16")
+    c = cbp.Code.from_workload(code)
+    llr, cw = make_frames(code, 2.0, 8, key=(56,))
+    wt = torch.ones((3, code.N // code.Z), device="cuda", requires_grad=True)
+    bt = torch.zeros((3, code.N // code.Z), device="cuda", requires_grad=True)
+    o = cbp.unrolled_cbp(c, torch.from_numpy(llr).cuda(), wt, bt, 3)
+    loss = o.square().mean()
+    loss.backward(retain_graph=True)
+    g1 = wt.grad.clone()
+    with pytest.raises(RuntimeError, match="consumes"):
+        loss.backward()
+    # a fresh forward gives the same gradients again
+    wt.grad = None
+    o = cbp.unrolled_cbp(c, torch.from_numpy(llr).cuda(), wt, bt, 3)
+    o.square().mean().backward()
+    assert torch.equal(wt.grad, g1)
+
+
 def test_training_lowers_the_loss():
     code = get_code("qc2304")
     c = cbp.Code.from_workload(code)
