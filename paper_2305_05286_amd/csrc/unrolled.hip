@@ -227,6 +227,18 @@ __global__ __launch_bounds__(1024) void unrolled_fwd_kernel(UnArgs A) {
     }
 }
 
+// Sum over the 64 lanes of a wave (xor butterfly; every lane gets the total,
+// lane 0's in a fixed order).  Only for workgroups of whole waves.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// kWaveSum: weight-gradient contributions are summed over each wave per edge
+// and accumulated per (block-column, wave) in LDS (workgroups of whole waves);
+// otherwise per (block-column, lane).
+template <bool kWaveSum>
 __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
     extern __shared__ float smem[];
     using CS = const __attribute__((address_space(4))) StreamCode;
@@ -243,19 +255,36 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
     const float a2 = A.a * kLog2e, lmax2 = A.lmax * kLog2e;
     const int DM = A.dcmax;
     // LDS: exchange [SL][dcmax][Z], row adjoints [SL][Z], scatter [SL][dcmax][Z],
-    // weight-gradient accumulators [NB][lanes] x 2
+    // weight-gradient accumulators [NB][ACC] x 2, ACC = waves (kWaveSum) or lanes
     float *sX = smem + (size_t)slot * A.dcmax * Z;
     float *sLall = smem + (size_t)A.lanes * A.dcmax;
     float *sL = sLall + (size_t)slot * Z;
     float *sD = sLall + A.lanes + (size_t)slot * DM * Z;
+    const int ACC = kWaveSum ? A.lanes / 64 : A.lanes;
+    const int acc_i = kWaveSum ? tid / 64 : tid;  // this lane's accumulator column
     float *sAw = sLall + A.lanes + (size_t)A.lanes * DM;
-    float *sAb = sAw + (size_t)NB * A.lanes;
+    float *sAb = sAw + (size_t)NB * ACC;
+    // add this edge's contributions (cw to w[b], cb to beta[b]); every lane of
+    // the workgroup calls it for the same b
+    auto accumulate = [&](int b, float cw, float cb) {
+        if constexpr (kWaveSum) {
+            cw = wave_sum(cw);
+            cb = wave_sum(cb);
+            if ((tid & 63) == 0) {
+                sAw[b * ACC + acc_i] += cw;
+                sAb[b * ACC + acc_i] += cb;
+            }
+        } else {
+            sAw[b * ACC + acc_i] += cw;
+            sAb[b * ACC + acc_i] += cb;
+        }
+    };
     const Frame F = frame_of(A, slot, l, Z, NB, MB, E);
     const uint32_t oFinal = F.oQ;  // the forward pass leaves the final state here
 
-    for (int b = 0; b < NB; ++b) {
-        sAw[b * A.lanes + tid] = 0.0f;
-        sAb[b * A.lanes + tid] = 0.0f;
+    for (int i = tid; i < NB * ACC; i += A.lanes) {
+        sAw[i] = 0.0f;
+        sAb[i] = 0.0f;
     }
     for (int e = 0; e < E; ++e) F.W.st(F.oLR + 4u * (e * Z + l), 0.0f);
     for (int r = 0; r < MB; ++r) F.W.st(F.oLT + 4u * (r * Z + l), 0.0f);
@@ -277,8 +306,7 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
             const bool neg = sign_bit(om.x) ^ (q < 0.0f);
             const float lmag = neg ? -go : go;            // d o / d mag = sgn
             const float lm = act ? lmag * wk : 0.0f;
-            sAw[b * A.lanes + tid] += act ? lmag * m : 0.0f;
-            sAb[b * A.lanes + tid] += act ? -lmag : 0.0f;
+            accumulate(b, act ? lmag * m : 0.0f, act ? -lmag : 0.0f);
             const float ld = lm * dphi2(d);
             const float lq = go - ld * dphi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2)) *
                                       dclamp(q, a2, lmax2);
@@ -335,6 +363,7 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                 in.lf = sL[wrapz(l - in.ed.sh, Z)];
             };
             auto fin_adj = [&](int e, const AIn &in) {
+                float cw = 0.0f, cb = 0.0f;  // this edge's weight-gradient contributions
                 const Edge &ed = in.ed;
                 const int iv = ed.b * Z + l;
                 const float q = in.tp.x, d = in.tp.y, rold = in.tp.z;
@@ -360,8 +389,8 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                     F.W.st(F.oLR + 4u * (ed.ep * Z + l), 0.0f);  // R(c_j -> v) before the commit is dead
                     const float lmag = neg ? -lrn : lrn;
                     const float lm = act ? lmag * wk : 0.0f;
-                    sAw[ed.b * A.lanes + tid] += act ? lmag * m : 0.0f;
-                    sAb[ed.b * A.lanes + tid] += act ? -lmag : 0.0f;
+                    cw = act ? lmag * m : 0.0f;
+                    cb = act ? -lmag : 0.0f;
                     ld = lm * dphi2(d);
                     const float cq = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2);
                     lq -= ld * dphi2(cq) * dclamp(q, a2, lmax2);
@@ -370,6 +399,7 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
                     F.W.st(F.oLR + 4u * (e * Z + l), in.lre - lqn);
                 F.W.st(F.oLQ + 4u * iv, lq);
                 sD[(e - e0) * Z + l] = ld;
+                accumulate(ed.b, cw, cb);
             };
             {
                 int e = e0;
@@ -395,21 +425,21 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
             }
             __syncthreads();
         }
-        // this sweep's weight gradients: sum over the workgroup's lanes
+        // this sweep's weight gradients: sum over the workgroup's accumulators
         for (int b = tid; b < NB; b += A.lanes) {
             float sw = 0.0f, sb = 0.0f;
-            for (int i = 0; i < A.lanes; ++i) {
-                sw += sAw[b * A.lanes + i];
-                sb += sAb[b * A.lanes + i];
+            for (int i = 0; i < ACC; ++i) {
+                sw += sAw[b * ACC + i];
+                sb += sAb[b * ACC + i];
             }
             float *gp = A.gpart + (((int64_t)gid_x() * A.T + t) * NB + b) * 2;
             gp[0] = sw;
             gp[1] = sb;
         }
         __syncthreads();
-        for (int b = 0; b < NB; ++b) {
-            sAw[b * A.lanes + tid] = 0.0f;
-            sAb[b * A.lanes + tid] = 0.0f;
+        for (int i = tid; i < NB * ACC; i += A.lanes) {
+            sAw[i] = 0.0f;
+            sAb[i] = 0.0f;
         }
         __syncthreads();
     }
@@ -461,7 +491,8 @@ int64_t unrolled_frame_bytes(const StreamCode &c, int T) {
 size_t unrolled_lds_bytes(const StreamCode &c, int lanes, bool backward) {
     const size_t x = (size_t)lanes * c.dcmax;
     if (!backward) return 4 * x;
-    return 4 * (2 * x + lanes + 2 * (size_t)c.nb * lanes);
+    const size_t acc = lanes % 64 == 0 ? lanes / 64 : lanes;
+    return 4 * (2 * x + lanes + 2 * (size_t)c.nb * acc);
 }
 
 bool unrolled_fits(const StreamCode &c, int lanes) {
@@ -469,8 +500,9 @@ bool unrolled_fits(const StreamCode &c, int lanes) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fw, reinterpret_cast<const void *>(unrolled_fwd_kernel), lanes,
                                                      unrolled_lds_bytes(c, lanes, false)) != hipSuccess)
         return false;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bw, reinterpret_cast<const void *>(unrolled_bwd_kernel), lanes,
-                                                     unrolled_lds_bytes(c, lanes, true)) != hipSuccess)
+    const void *bwd = lanes % 64 == 0 ? reinterpret_cast<const void *>(unrolled_bwd_kernel<true>)
+                                      : reinterpret_cast<const void *>(unrolled_bwd_kernel<false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bw, bwd, lanes, unrolled_lds_bytes(c, lanes, true)) != hipSuccess)
         return false;
     return fw > 0 && bw > 0;
 }
@@ -502,7 +534,10 @@ hipError_t launch_unrolled(bool backward, const StreamCode &host_code, const Str
         hipLaunchKernelGGL(unrolled_fwd_kernel, dim3(groups), dim3(lanes), lds, s, A);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(unrolled_bwd_kernel, dim3(groups), dim3(lanes), lds, s, A);
+    if (lanes % 64 == 0)
+        hipLaunchKernelGGL(unrolled_bwd_kernel<true>, dim3(groups), dim3(lanes), lds, s, A);
+    else
+        hipLaunchKernelGGL(unrolled_bwd_kernel<false>, dim3(groups), dim3(lanes), lds, s, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int TNB = T * host_code.nb;

@@ -22,6 +22,12 @@ def say(*a):
     sys.stdout.flush()
 
 
+def z72_code():
+    """A QC code whose frame (Z = 72 lanes) does not fill whole waves."""
+    from paper_2305_05286_amd.workload import make_qc_code, qc_pattern_dualdiag
+    return make_qc_code("qc_t72", qc_pattern_dualdiag(4, [3, 3, 2, 2], seed=4), 72, seed=9, kind="qc_dualdiag")
+
+
 def gpu_forward(code_w, llr, w, beta):
     c = cbp.Code.from_workload(code_w)
     t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
@@ -37,9 +43,9 @@ def bce64(o, c):
     return float(np.mean(c * np.logaddexp(0.0, o) + (1 - c) * np.logaddexp(0.0, -o)))
 
 
-@pytest.mark.parametrize("name", ["qc_t64s", "qc2304"])
+@pytest.mark.parametrize("name", ["qc_t64s", "qc2304", "qc_t72"])
 def test_unit_weights_equal_streamed_flushed_posterior(name):
-    code = get_code(name)
+    code = get_code(name) if name != "qc_t72" else z72_code()
     T = 5
     llr, _ = make_frames(code, 1.75, 64, key=(51,))
     nb = code.N // code.Z
@@ -71,8 +77,9 @@ def test_forward_matches_fp64_oracle(name):
     assert err.max() <= 1e-2
 
 
-def test_gradients_match_fp64_finite_differences():
-    code = get_code("qc_t16")
+@pytest.mark.parametrize("name", ["qc_t16", "qc_t72"])
+def test_gradients_match_fp64_finite_differences(name):
+    code = get_code(name) if name != "qc_t72" else z72_code()
     T, nb = 3, code.N // code.Z
     rng = np.random.default_rng(53)
     w = rng.uniform(0.7, 1.3, size=(T, nb)).astype(np.float32).astype(np.float64)
