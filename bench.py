@@ -89,6 +89,8 @@ def main() -> int:
                     help="skip the mixed-code batch (25 QC codes in one persistent launch)")
     ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps of the unrolled differentiable CBP (0 = skip)")
+    ap.add_argument("--no-peg", action="store_true",
+                    help="skip the CBP / LBP / FBP comparison on the PEG codes (sparse kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter scaling)")
     args = ap.parse_args()
@@ -248,10 +250,24 @@ def main() -> int:
                             "trans_wave_instructions_per_launch": v["trans_wave_instructions_per_launch"]}
 
     # ---------------- 4. the n=26112 code (streamed kernel) ----------------
+    del llr_t, cw_t
+    torch.cuda.empty_cache()
+    # measured device-copy bandwidth (read + write of 1 GiB), the practical
+    # ceiling the HBM-streamed kernels are compared with beside the 8 TB/s peak
+    ca = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for s_, e_ in cev:
+        s_.record(stream)
+        cb.copy_(ca)
+        e_.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * ca.numel() / (float(np.median([s_.elapsed_time(e_) for s_, e_ in cev])) / 1e3) / 1e9
+    del ca, cb
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write)")
     large = None
     if not args.no_large:
-        del llr_t, cw_t
-        torch.cuda.empty_cache()
         big = get_code("qc26112")
         bh = cbp.Code.from_workload(big)
         nb_frames, big_snr, big_mi = 4096, 1.0, 25
@@ -277,10 +293,54 @@ def main() -> int:
             large[algo] = {"ms": round(t * 1e3, 3), "gbps": round(nb_frames * big.K / t / 1e9, 3),
                            "fer": fer, "mean_iters": round(its, 3),
                            "edge_updates_per_s": nb_frames * its * big.E / t}
+            if algo == "cbp":  # algorithmic state bytes (same count as the headline roofline)
+                ab = algorithmic_bytes(bit.cpu().numpy(), big.E, big.M, big.N) / t / 1e9
+                large[algo].update({"algorithmic_gbs": round(ab, 1), "frac_of_peak": round(ab / HBM_PEAK_GBS, 4),
+                                    "frac_of_copy": round(ab / copy_gbs, 4)})
             log(f"[bench] n=26112 {algo}: {t * 1e3:.2f} ms, FER {fer:.2e}, iters {its:.2f}")
         del bl_t, bc_t, bbits, bit, bws
 
-    # ---------------- 5. mixed-code batch (one persistent launch) ----------
+    # ---------------- 5. the paper's comparison on PEG codes (sparse kernel) --
+    peg = None
+    if not args.no_peg:
+        from paper_2305_05286_amd.workload import encode
+        PB, PMI, PSNR = 131072, 200, 2.0
+        peg = {"frames": PB, "ebn0_db": PSNR, "max_iter": PMI, "kernel": "sparse",
+               "note": "codewords from a pool of 1024 seeded random codewords, fresh GPU noise"}
+        for name in ("peg_reg36_n2048", "peg_irr_n8192"):
+            pc = get_code(name)
+            ph = cbp.Code.from_workload(pc)
+            rng = np.random.default_rng(np.random.SeedSequence([2026, pc.N, pc.E]))
+            pool = torch.from_numpy(encode(pc, rng.integers(0, 2, size=(1024, pc.K), dtype=np.uint8))).to(dev)
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(2026 + pc.N)
+            cw_p = pool[torch.randint(0, 1024, (PB,), device=dev, generator=gen)]
+            s2 = 1.0 / (2.0 * pc.rate * 10.0 ** (PSNR / 10.0))
+            llr_p = ((2.0 / s2) * ((1.0 - 2.0 * cw_p.float()) +
+                                   (s2 ** 0.5) * torch.randn(cw_p.shape, device=dev, generator=gen))).contiguous()
+            pbits = torch.empty((PB, pc.N), dtype=torch.uint8, device=dev)
+            pit = torch.empty((PB,), dtype=torch.int32, device=dev)
+            peg[name] = {}
+            for algo in ("cbp", "lbp", "fbp"):
+                pws = torch.empty(cbp.workspace_size(ph, algo, PB), dtype=torch.uint8, device=dev)
+                s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s_.record(stream)
+                cbp.decode(ph, llr_p, PMI, algo, out=(pbits, pit), workspace=pws)
+                e_.record(stream)
+                torch.cuda.synchronize()
+                t = s_.elapsed_time(e_) / 1e3
+                fe = int((pbits != cw_p).any(dim=1).sum().item())
+                its = pit.double()
+                peg[name][algo] = {"ms": round(t * 1e3, 1), "fer": fe / PB, "frame_errors": fe,
+                                   "mean_iters": round(its.mean().item(), 3), "max_iters": int(its.max().item()),
+                                   "gbps": round(PB * pc.K / t / 1e9, 3)}
+                log(f"[bench] {name} {algo}: {t * 1e3:.0f} ms, FER {fe / PB:.2e}, "
+                    f"sweeps {its.mean().item():.2f}")
+                del pws
+            del pool, cw_p, llr_p, pbits, pit
+            torch.cuda.empty_cache()
+
+    # ---------------- 6. mixed-code batch (one persistent launch) ----------
     mixed = None
     if not args.no_mixed:
         from paper_2305_05286_amd.workload import RATES, make_mixed_batch, mixed_family
@@ -340,7 +400,7 @@ def main() -> int:
             f"{mixed['gbps']:.2f} Gbit/s, iters {mixed['mean_iters']:.2f}, FER {mixed['fer']:.3f}")
         del ml, mc, mo, mbits, mit, mws, lws, graph
 
-    # ---------------- 6. unrolled differentiable CBP: training steps -----
+    # ---------------- 7. unrolled differentiable CBP: training steps -----
     train = None
     if args.train_steps > 0:
         from paper_2305_05286_amd.train_unrolled import train as train_unrolled
@@ -353,7 +413,7 @@ def main() -> int:
             f"{tr['untrained']['bce']:.5f} -> {tr['trained']['bce']:.5f}, "
             f"FER {tr['untrained']['fer']:.4f} -> {tr['trained']['fer']:.4f}")
 
-    # ---------------- 7. CPU baseline: the FP64 oracle ----------------------
+    # ---------------- 8. CPU baseline: the FP64 oracle ----------------------
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -395,7 +455,9 @@ def main() -> int:
                                                                for k, x in v["quality"].items()}}
                             for a, v in results.items()},
         "matched_fer": matched or None,
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "large_code": large,
+        "peg_codes": peg,
         "mixed_batch": mixed,
         "unrolled_training": train,
         "sweep": {a: [{k: (round(x, 6) if isinstance(x, float) else x) for k, x in p.items()} for p in v]

@@ -26,6 +26,14 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
     return ((const __attribute__((address_space(4))) T *)p)[i];
 }
 
+// A byte of such a table.  Scalar loads are dword-sized, so a byte read through
+// ldc would become a vector load; this reads the containing dword (the table
+// must start 4-byte aligned and be readable up to the next multiple of 4 bytes)
+// and extracts the byte.
+__device__ __forceinline__ uint32_t ldc_u8(const uint8_t *p, int64_t i) {
+    return (ldc((const uint32_t *)p, i >> 2) >> (8 * (uint32_t)(i & 3))) & 0xffu;
+}
+
 struct Params {
     float a;       // phi(lmax): lower clamp of |Q| entering phi
     float lmax;    // upper clamp

@@ -102,7 +102,7 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, int64_t l
     const float q = w.a0[(int64_t)v * S + lf];
     int e = ldc(g.last_edge, v);
     while (ldc(g.edge_row, e) > istop) {
-        if (ldc(g.first, e)) {  // no visit of v yet in this sweep
+        if (ldc_u8(g.first, e)) {  // no visit of v yet in this sweep
             if (t == 1) return q;
             e = ldc(g.last_edge, v);
             break;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                             const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
                             q[k] = Q[iv];
                             if (!kMin) pq[k] = PQ[iv];
-                            if (!(t == 1 && ldc(g.first, e))) {
+                            if (!(t == 1 && ldc_u8(g.first, e))) {
                                 const int64_t ij = (int64_t)ldc(g.pred_row, e) * S + lf;
                                 om[k] = OmM[ij];
                                 os[k] = OmS[ij];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                             const int e = c0 + k;
                             const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
                             float rn = 0.0f, rc = r[k];
-                            if (!(t == 1 && ldc(g.first, e))) {
+                            if (!(t == 1 && ldc_u8(g.first, e))) {
                                 // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
                                 // from its belief, then committed to R(c_j -> v) first.
                                 rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
