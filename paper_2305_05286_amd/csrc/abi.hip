@@ -192,7 +192,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             q_er = mb + 1;
             q_esh = q_er + qE;
             q_elast = q_esh + qE;
-            const size_t off0 = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size();
+            const size_t off0 = (size_t)(M + 1) + 4 * (size_t)E + 3 * (size_t)kSparseTablePad + (size_t)N + sht.size();
             while ((off0 + qt.size()) % 4) qt.push_back(0);
             q_erec = qt.size();
             for (int e = 0; e < qE; ++e) {
@@ -205,23 +205,24 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             q_sc = qt.size();
             qt.resize(q_sc + (sizeof(StreamCode) + 3) / 4, 0);  // filled once the device address is known
         }
-        const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + (size_t)N + sht.size() + qt.size();
-        const size_t bytes = ints * 4 + (size_t)E + 64;
+        const size_t P = kSparseTablePad;  // padding of col_idx, pred_edge, pred_row, first
+        const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size();
+        const size_t bytes = ints * 4 + (size_t)E + P + 64;
         void *buf = nullptr;
         e = hipMalloc(&buf, bytes);
         if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-        std::vector<int> host(ints);
+        std::vector<int> host(ints, 0);
         int *p = host.data();
         std::memcpy(p, c->row_ptr.data(), 4 * (size_t)(M + 1));
         p += M + 1;
         std::memcpy(p, c->col_idx.data(), 4 * (size_t)E);
-        p += E;
+        p += E + P;
         std::memcpy(p, c->edge_row.data(), 4 * (size_t)E);
         p += E;
         std::memcpy(p, c->pred_edge.data(), 4 * (size_t)E);
-        p += E;
+        p += E + P;
         std::memcpy(p, c->pred_row.data(), 4 * (size_t)E);
-        p += E;
+        p += E + P;
         std::memcpy(p, c->last_edge.data(), 4 * (size_t)N);
         p += N;
         if (!sht.empty()) std::memcpy(p, sht.data(), 4 * sht.size());
@@ -246,8 +247,11 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         }
         if (!qt.empty()) std::memcpy(p, qt.data(), 4 * qt.size());
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy((char *)buf + ints * 4, c->first.data(), (size_t)E, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            std::vector<uint8_t> fp(c->first);
+            fp.resize((size_t)E + P, 0);
+            e = hipMemcpy((char *)buf + ints * 4, fp.data(), (size_t)E + P, hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             (void)hipFree(buf);
             return hip_fail(e, "hipMemcpy of code tables");
@@ -259,13 +263,13 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         t.g.row_ptr = d;
         d += M + 1;
         t.g.col_idx = d;
-        d += E;
+        d += E + P;
         t.g.edge_row = d;
         d += E;
         t.g.pred_edge = d;
-        d += E;
+        d += E + P;
         t.g.pred_row = d;
-        d += E;
+        d += E + P;
         t.g.last_edge = d;
         d += N;
         t.qc_sht = sht.empty() ? nullptr : d;
@@ -454,6 +458,10 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
             e = launch_qc_stream(algo, L, llr, bits, iters, batch, nullptr, nullptr, nullptr,
                                  (unsigned int *)ws, max_iter, r.p, r.d, (char *)ws + 256, s);
     } else {
+        if ((int64_t)std::max({g->N, g->M, g->E}) * 64 >= ((int64_t)1 << 32)) {
+            if (own) (void)hipFreeAsync(ws, s);
+            return fail(CBP_EUNSUPPORTED, "the sparse kernel indexes its state with 32 bits: at most 2^26 edges");
+        }
         const SparseWs w = sparse_ws_carve(algo, *g, sparse_lanes(algo, *g, batch),
                                            (char *)ws + kSparseCounterBytes);
         e = launch_sparse(algo, *g, llr, bits, iters, batch, max_iter, r.p, w, r.d,

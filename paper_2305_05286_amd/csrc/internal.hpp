@@ -60,6 +60,11 @@ struct SparseDev {
     const int *last_edge; // [N]  edge of the highest row of each column
 };
 
+// col_idx, pred_edge, pred_row and first are readable (zeros) for this many
+// entries past E: the sparse kernels read a chunk's entries unconditionally,
+// so that the scalar loads of a chunk go out together.
+constexpr int kSparseTablePad = 16;
+
 // Workspace of the sparse kernels: one contiguous block per wave (its 64
 // lanes' state), frame-interleaved inside it — element (index, lane) of wave
 // w lives at array[w * block_bytes + index * stride + lane] with stride = 64,

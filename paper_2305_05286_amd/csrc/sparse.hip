@@ -20,19 +20,34 @@ constexpr int kChunk = 8;  // edges of a row whose loads are issued together
 constexpr int kSyndromeBlock = 256;
 constexpr int kFillBlock = 256;
 
-__device__ bool lane_syndrome_ok(const SparseDev &g, const uint8_t *xb, int64_t S, int64_t lf) {
+// Element (index, lane) of an array of a wave's state block: 32-bit index
+// arithmetic (a block stays below 2 GiB, checked at launch).
+__device__ __forceinline__ uint32_t at(int idx, uint32_t lane) { return (uint32_t)idx * (uint32_t)kWave + lane; }
+
+// Edges in chunks of kChunk: the chunk's column indices are read
+// unconditionally (the table is padded) so the scalar loads go out together,
+// then its decision bytes.
+__device__ bool lane_syndrome_ok(const SparseDev &g, const uint8_t *xb, uint32_t lf) {
     uint32_t bad = 0;
     for (int i = 0; i < g.M; ++i) {
         uint32_t p = 0;
-        for (int e = ldc(g.row_ptr, i); e < ldc(g.row_ptr, i + 1); ++e) p ^= xb[(int64_t)ldc(g.col_idx, e) * S + lf];
+        const int e1 = ldc(g.row_ptr, i + 1);
+        for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
+            int col[kChunk];
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k)
+                if (c0 + k < e1) p ^= xb[at(col[k], lf)];
+        }
         bad |= p;
     }
     return bad == 0;
 }
 
-__device__ void write_out(const SparseDev &g, const uint8_t *xb, int64_t S, int64_t lf,
+__device__ void write_out(const SparseDev &g, const uint8_t *xb, uint32_t lf,
                           uint8_t *bits, int32_t *iters, int64_t f, int t) {
-    for (int v = 0; v < g.N; ++v) bits[f * g.N + v] = xb[(int64_t)v * S + lf];
+    for (int v = 0; v < g.N; ++v) bits[f * g.N + v] = xb[at(v, lf)];
     iters[f] = t;
 }
 
@@ -83,12 +98,11 @@ __device__ float b2v(float om, float os, float pq, float q, const Params &p) {
 }
 
 template <bool kMin>
-__device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, int v, const Params &p) {
-    const int64_t S = w.stride;
+__device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, uint32_t lf, int v, const Params &p) {
     const int e = ldc(g.last_edge, v);
     const int j = ldc(g.edge_row, e);
-    const float q = w.a0[(int64_t)v * S + lf];
-    return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
+    const float q = w.a0[at(v, lf)];
+    return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
 }
 
 // Flushed posterior after a stop in the middle of sweep t, right after row
@@ -96,10 +110,9 @@ __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, int64_t lf, 
 // its last row of the previous sweep, else none (B2V 0).  The column's edges
 // are walked backwards from its last edge through pred_edge.
 template <bool kMin>
-__device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, int64_t lf, int v, const Params &p,
+__device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, uint32_t lf, int v, const Params &p,
                                 int istop, int t) {
-    const int64_t S = w.stride;
-    const float q = w.a0[(int64_t)v * S + lf];
+    const float q = w.a0[at(v, lf)];
     int e = ldc(g.last_edge, v);
     while (ldc(g.edge_row, e) > istop) {
         if (ldc_u8(g.first, e)) {  // no visit of v yet in this sweep
@@ -110,7 +123,7 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, int64_t l
         e = ldc(g.pred_edge, e);
     }
     const int j = ldc(g.edge_row, e);
-    return q + b2v<kMin>(w.a3[(int64_t)j * S + lf], w.a4[(int64_t)j * S + lf], w.a1[(int64_t)v * S + lf], q, p);
+    return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
 }
 
 // kMin: the normalized min-sum check rule (OmM = min1 | parity, OmS = min2).
@@ -120,8 +133,7 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
     unsigned long long *counter) {
     w = wave_block(w);
-    const int64_t lf = tid_x();  // this lane's slot in its wave's block
-    const int64_t S = w.stride;
+    const uint32_t lf = tid_x();  // this lane's slot in its wave's block
     float *Q = w.a0, *PQ = w.a1, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
     const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
@@ -146,14 +158,14 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                     // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
                     for (int v = 0; v < g.N; ++v) {
                         const float l = llr[f * g.N + v] * us;
-                        Q[(int64_t)v * S + lf] = l;
-                        xb[(int64_t)v * S + lf] = l < 0.0f;
+                        Q[at(v, lf)] = l;
+                        xb[at(v, lf)] = l < 0.0f;
                     }
-                    for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+                    for (int e = 0; e < g.E; ++e) R[at(e, lf)] = 0.0f;
                     t = 0;
                     run = 0;
-                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf))) {
-                        write_out(g, xb, S, lf, bits, iters, f, 0);
+                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, lf))) {
+                        write_out(g, xb, lf, bits, iters, f, 0);
                         need = true;
                     }
                 }
@@ -178,21 +190,30 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                 // forwarded in registers.
                 for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
                     const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    // the chunk's table entries, unconditionally (padded tables)
+                    int col[kChunk], pe[kChunk], pr[kChunk];
+                    uint32_t fi[kChunk];
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        col[k] = ldc(g.col_idx, c0 + k);
+                        pe[k] = ldc(g.pred_edge, c0 + k);
+                        pr[k] = ldc(g.pred_row, c0 + k);
+                        fi[k] = ldc_u8(g.first, c0 + k);
+                    }
                     float q[kChunk], pq[kChunk], om[kChunk], os[kChunk], r[kChunk];
                     uint8_t x0[kChunk];
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k) {
                         if (k < n) {
-                            const int e = c0 + k;
-                            const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
+                            const uint32_t iv = at(col[k], lf);
                             q[k] = Q[iv];
                             if (!kMin) pq[k] = PQ[iv];
-                            if (!(t == 1 && ldc_u8(g.first, e))) {
-                                const int64_t ij = (int64_t)ldc(g.pred_row, e) * S + lf;
+                            if (!(t == 1 && fi[k])) {
+                                const uint32_t ij = at(pr[k], lf);
                                 om[k] = OmM[ij];
                                 os[k] = OmS[ij];
                             }
-                            r[k] = R[(int64_t)e * S + lf];
+                            r[k] = R[at(c0 + k, lf)];
                             if (p.stop_rule == 1) x0[k] = xb[iv];
                         }
                     }
@@ -200,15 +221,14 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                     for (int k = 0; k < kChunk; ++k) {
                         if (k < n) {
                             const int e = c0 + k;
-                            const int64_t iv = (int64_t)ldc(g.col_idx, e) * S + lf;
+                            const uint32_t iv = at(col[k], lf);
                             float rn = 0.0f, rc = r[k];
-                            if (!(t == 1 && ldc_u8(g.first, e))) {
+                            if (!(t == 1 && fi[k])) {
                                 // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
                                 // from its belief, then committed to R(c_j -> v) first.
                                 rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
-                                const int pe = ldc(g.pred_edge, e);
-                                R[(int64_t)pe * S + lf] = rn;
-                                if (pe == e) rc = rn;
+                                R[at(pe[k], lf)] = rn;
+                                if (pe[k] == e) rc = rn;
                             }
                             const float lam = q[k] + rn;              // eq. equ_s4e20
                             const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
@@ -229,8 +249,8 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                         }
                     }
                 }
-                OmM[(int64_t)i * S + lf] = with_sign(Mx, par);  // eq. equ_s4e23
-                OmS[(int64_t)i * S + lf] = Sr;
+                OmM[at(i, lf)] = with_sign(Mx, par);  // eq. equ_s4e23
+                OmS[at(i, lf)] = Sr;
                 if (p.stop_rule == 1) {  // Step 2(3): M updates in a row with Omega > 0, no flip
                     run = (!par && !flip) ? run + 1 : 0;
                     if (run >= g.M) {
@@ -243,31 +263,31 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             if (paper_stop) {
                 if (p.hd_mode == 1)
                     for (int v = 0; v < g.N; ++v)
-                        xb[(int64_t)v * S + lf] = cbp_flushed_at<kMin>(g, w, lf, v, p, istop, t) < 0.0f;
-                write_out(g, xb, S, lf, bits, iters, f, t);
+                        xb[at(v, lf)] = cbp_flushed_at<kMin>(g, w, lf, v, p, istop, t) < 0.0f;
+                write_out(g, xb, lf, bits, iters, f, t);
                 need = true;
                 continue;
             }
             if (p.hd_mode == 1)
-                for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = cbp_flushed<kMin>(g, w, lf, v, p) < 0.0f;
+                for (int v = 0; v < g.N; ++v) xb[at(v, lf)] = cbp_flushed<kMin>(g, w, lf, v, p) < 0.0f;
             if (t == d.sweep && f < d.frames) {
                 for (int v = 0; v < g.N; ++v) {
-                    if (d.q) d.q[f * g.N + v] = Q[(int64_t)v * S + lf] * un;
+                    if (d.q) d.q[f * g.N + v] = Q[at(v, lf)] * un;
                     if (d.lam) d.lam[f * g.N + v] = cbp_flushed<kMin>(g, w, lf, v, p) * un;
                 }
                 if (d.r)
-                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf] * un;
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[at(e, lf)] * un;
                 if (d.om)
                     for (int i = 0; i < g.M; ++i) {
-                        const float om = OmM[(int64_t)i * S + lf];
+                        const float om = OmM[at(i, lf)];
                         d.om[f * g.M + i] =
                             kMin ? with_sign(p.alpha * abs_bits(om), sign_bit(om))
-                                 : with_sign(phi2(abs_bits(om) + OmS[(int64_t)i * S + lf]) * un, sign_bit(om));
+                                 : with_sign(phi2(abs_bits(om) + OmS[at(i, lf)]) * un, sign_bit(om));
                     }
             }
-            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
+            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, lf)) || t == max_iter;
             if (stop) {
-                write_out(g, xb, S, lf, bits, iters, f, t);
+                write_out(g, xb, lf, bits, iters, f, t);
                 need = true;
             }
         }
@@ -288,8 +308,7 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
     int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
     unsigned long long *counter) {
     w = wave_block(w);
-    const int64_t lf = tid_x();  // this lane's slot in its wave's block
-    const int64_t S = w.stride;
+    const uint32_t lf = tid_x();  // this lane's slot in its wave's block
     float *Lam = w.a0, *R = w.a1, *Acc = w.a2;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
     const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
@@ -310,13 +329,13 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
                 } else {
                     for (int v = 0; v < g.N; ++v) {
                         const float l = llr[f * g.N + v] * us;
-                        Lam[(int64_t)v * S + lf] = l;
-                        xb[(int64_t)v * S + lf] = l < 0.0f;
+                        Lam[at(v, lf)] = l;
+                        xb[at(v, lf)] = l < 0.0f;
                     }
-                    for (int e = 0; e < g.E; ++e) R[(int64_t)e * S + lf] = 0.0f;
+                    for (int e = 0; e < g.E; ++e) R[at(e, lf)] = 0.0f;
                     t = 0;
-                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf))) {
-                        write_out(g, xb, S, lf, bits, iters, f, 0);
+                    if (max_iter == 0 || (p.stop_rule == 0 && lane_syndrome_ok(g, xb, lf))) {
+                        write_out(g, xb, lf, bits, iters, f, 0);
                         need = true;
                     }
                 }
@@ -326,7 +345,7 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
         if (!done) {
             ++t;
             if (kFlood)
-                for (int v = 0; v < g.N; ++v) Acc[(int64_t)v * S + lf] = 0.0f;
+                for (int v = 0; v < g.N; ++v) Acc[at(v, lf)] = 0.0f;
             for (int i = 0; i < g.M; ++i) {
                 const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
                 // min-sum: (m1, m2) = two smallest |Q|; log-tanh: (m1, m2) = (max, rest) of g(|Q|)
@@ -339,12 +358,15 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
                 float qs[kChunk];
                 for (int c0 = e0; c0 < e1; c0 += kChunk) {
                     const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    int col[kChunk];  // read unconditionally (padded table)
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
                     float lv[kChunk], rv[kChunk];
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k)
                         if (k < n) {
-                            lv[k] = Lam[(int64_t)ldc(g.col_idx, c0 + k) * S + lf];
-                            rv[k] = R[(int64_t)(c0 + k) * S + lf];
+                            lv[k] = Lam[at(col[k], lf)];
+                            rv[k] = R[at((c0 + k), lf)];
                         }
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k)
@@ -365,18 +387,21 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
                 const bool kept = e1 - e0 <= kChunk;
                 for (int c0 = e0; c0 < e1; c0 += kChunk) {
                     const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+                    int col[kChunk];  // read unconditionally (padded table)
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
                     float qv[kChunk], av[kChunk];
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k)
                         if (k < n) {
-                            const int64_t iv = (int64_t)ldc(g.col_idx, c0 + k) * S + lf;
-                            qv[k] = kept ? qs[k] : Lam[iv] - R[(int64_t)(c0 + k) * S + lf];
+                            const uint32_t iv = at(col[k], lf);
+                            qv[k] = kept ? qs[k] : Lam[iv] - R[at((c0 + k), lf)];
                             if (kFlood) av[k] = Acc[iv];
                         }
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k)
                         if (k < n) {
-                            const int64_t iv = (int64_t)ldc(g.col_idx, c0 + k) * S + lf;
+                            const uint32_t iv = at(col[k], lf);
                             const float q = qv[k];
                             float rn;
                             if constexpr (kMin) {
@@ -386,7 +411,7 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
                                 rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))),
                                                par ^ (q < 0.0f));
                             }
-                            R[(int64_t)(c0 + k) * S + lf] = rn;
+                            R[at((c0 + k), lf)] = rn;
                             if (kFlood) Acc[iv] = av[k] + rn;
                             else Lam[iv] = q + rn;  // eq. equ_s2e12
                         }
@@ -394,19 +419,19 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
             }
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) {
-                    const int64_t iv = (int64_t)v * S + lf;
+                    const uint32_t iv = at(v, lf);
                     Lam[iv] = llr[f * g.N + v] * us + Acc[iv];  // eq. equ_s2e6
                 }
-            for (int v = 0; v < g.N; ++v) xb[(int64_t)v * S + lf] = Lam[(int64_t)v * S + lf] < 0.0f;
+            for (int v = 0; v < g.N; ++v) xb[at(v, lf)] = Lam[at(v, lf)] < 0.0f;
             if (t == d.sweep && f < d.frames) {
                 if (d.lam)
-                    for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[(int64_t)v * S + lf] * un;
+                    for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[at(v, lf)] * un;
                 if (d.r)
-                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[(int64_t)e * S + lf] * un;
+                    for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[at(e, lf)] * un;
             }
-            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, S, lf)) || t == max_iter;
+            const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, lf)) || t == max_iter;
             if (stop) {
-                write_out(g, xb, S, lf, bits, iters, f, t);
+                write_out(g, xb, lf, bits, iters, f, t);
                 need = true;
             }
         }
