@@ -29,7 +29,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define CBP_OK 0
 #define CBP_EINVAL (-1)       /* null pointer, bad shape/size/option, malformed H */
-#define CBP_EUNSUPPORTED (-2) /* valid request this build does not implement      */
+#define CBP_EUNSUPPORTED (-2) /* valid request the library does not implement     */
 #define CBP_EHIP (-3)         /* HIP runtime or launch error                      */
 #define CBP_ENOMEM (-4)       /* device or host allocation failed                 */
 

@@ -103,7 +103,7 @@ void qc_stream_kernel(StreamArgs A) {
     int *sAct = sFlags + 4 * MS;                         // [MS]
     int *sFresh = sFlags + 5 * MS;                       // [MS]
     // paper's stopping rule (debug instantiation only; its launches allocate
-    // these): per-row verdicts [lanes], per-edge flips and previous decisions
+    // these): per-row outcomes [lanes], per-edge flips and previous decisions
     // [dcmax][lanes] bytes, stop row and run per slot
     constexpr bool kStop = kDbg && kBelief;
     long long *sRunAll = reinterpret_cast<long long *>(sFlags + 6 * MS);  // [MS]
