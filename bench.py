@@ -387,6 +387,8 @@ def main() -> int:
                  "graph_ms": round(gsec * 1e3, 3),
                  "gbps": round(float(k_info.sum()) / gsec / 1e9, 3),
                  "frames_per_s": round(MB_ / gsec, 1), "mean_iters": round(float(it_h.mean()), 3),
+                 "edge_updates_per_s": float((it_h.astype(np.float64) *
+                                              np.array([fam[c].E for c in mw["code"]], np.float64)).sum()) / gsec,
                  "fer": round(float(ferr.mean()), 5),
                  "fer_by_rate": {RATES[r][0]: round(float(ferr[rate_of == r].mean()), 5)
                                  for r in range(len(RATES))}}
