@@ -112,18 +112,25 @@ __device__ __forceinline__ Frame frame_of(const UnArgs &A, int slot, int l, int 
 
 // One sweep of weighted CBP, in place on the state at byte offset `st`
 // (Q [N], R [E][Z], Omega [M] float2 back to back); kTape also writes the tape.
-template <bool kTape>
-__device__ void sweep(const UnArgs &A, const Frame &F, uint32_t st, const int *rstart, const int4 *erec, int t,
-                      float *sX, float a2, float lmax2) {
+// kCk (sweeps t >= 1 of the forward pass) also writes the state as it was at
+// the start of the sweep to the checkpoint at `ck`, each element when the sweep
+// first reads it: Q_v at v's first visit; R(c_i -> v) at its own visit, except
+// where the commit at the column's first visit has already replaced it (the
+// column's last edge), whose old value is read just before that commit; a
+// check's belief just before its row stores the new one.
+template <bool kTape, bool kCk>
+__device__ void sweep(const UnArgs &A, const Frame &F, uint32_t st, uint32_t ck, const int *rstart,
+                      const int4 *erec, int t, float *sX, float a2, float lmax2) {
     const int Z = F.Z, l = F.l, NB = F.NB;
     const uint32_t oQ = st, oR = st + 4u * (NB * Z), oOM = st + 4u * (NB * Z + F.E * Z);
+    const uint32_t cQ = ck, cR = ck + 4u * (NB * Z), cOM = ck + 4u * (NB * Z + F.E * Z);
     for (int r = 0; r < F.MB; ++r) {
         const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
         // two edges at a time: all loads before any store (distinct block-columns;
         // R(c_i -> v) is read before R(c_j -> v) is stored, from rn in a degree-1 column)
         struct In {
             Edge ed;
-            float q, rci;
+            float q, rci, rep;  // rep: R(c_j -> v) before its commit (kCk, first visits)
             float2 om;
             bool has;
         };
@@ -133,10 +140,17 @@ __device__ void sweep(const UnArgs &A, const Frame &F, uint32_t st, const int *r
             in.rci = F.W.ld(oR + 4u * (e * Z + l));
             in.has = !(t == 0 && in.ed.first);
             in.om = in.has ? F.W.ld2(oOM + 8u * (in.ed.epr * Z + wrapz(l - in.ed.epsh, Z))) : make_float2(0.0f, 0.0f);
+            if constexpr (kCk)
+                if (in.ed.first && in.ed.ep != e) in.rep = F.W.ld(oR + 4u * (in.ed.ep * Z + l));
         };
         auto fin_edge = [&](int e, const In &in) {
             const Edge &ed = in.ed;
             const float q = in.q;
+            if constexpr (kCk) {
+                if (ed.first) F.W.st(cQ + 4u * (ed.b * Z + l), q);
+                if (!ed.last || ed.ep == e) F.W.st(cR + 4u * (e * Z + l), in.rci);
+                if (ed.first && ed.ep != e) F.W.st(cR + 4u * (ed.ep * Z + l), in.rep);
+            }
             float rn = 0.0f, d = -1.0f, par = 0.0f;
             bool own = false;
             if (in.has) {
@@ -176,18 +190,10 @@ __device__ void sweep(const UnArgs &A, const Frame &F, uint32_t st, const int *r
                 p ^= sign_bit(x);
                 fold(Mx, Sr, abs_bits(x));
             }
+            if constexpr (kCk) F.W.st2(cOM + 8u * (r * Z + l), F.W.ld2(oOM + 8u * (r * Z + l)));
             F.W.st2(oOM + 8u * (r * Z + l), make_float2(with_sign(Mx, p), Sr));
         }
         __syncthreads();
-    }
-}
-
-__device__ __forceinline__ void copy_state(const Frame &F, uint32_t from, uint32_t to) {
-    const int N = F.NB * F.Z, EZ = F.E * F.Z, M = F.MB * F.Z, l = F.l;
-    for (int i = l; i < N + EZ; i += F.Z) F.W.st(to + 4u * i, F.W.ld(from + 4u * i));
-    for (int i = l; i < M; i += F.Z) {
-        const uint32_t o = 4u * (N + EZ) + 8u * i;
-        F.W.st2(to + o, F.W.ld2(from + o));
     }
 }
 
@@ -212,8 +218,10 @@ __global__ __launch_bounds__(1024) void unrolled_fwd_kernel(UnArgs A) {
     for (int e = 0; e < E; ++e) F.W.st(F.oR + 4u * (e * Z + l), 0.0f);
     __syncthreads();
     for (int t = 0; t < A.T; ++t) {
-        if (t > 0) copy_state(F, F.oQ, F.oCk + F.ck * (uint32_t)(t - 1));
-        sweep<false>(A, F, F.oQ, rstart, erec, t, sX, a2, lmax2);
+        if (t > 0)  // the state at the start of sweep t goes to checkpoint t as the sweep reads it
+            sweep<false, true>(A, F, F.oQ, F.oCk + F.ck * (uint32_t)(t - 1), rstart, erec, t, sX, a2, lmax2);
+        else
+            sweep<false, false>(A, F, F.oQ, 0, rstart, erec, t, sX, a2, lmax2);
     }
     for (int b = 0; b < NB; ++b) {
         const int el = ldc(cs->elast, b);
@@ -335,7 +343,7 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
             for (int e = 0; e < E; ++e) F.W.st(F.oR + 4u * (e * Z + l), 0.0f);
         }
         __syncthreads();
-        sweep<true>(A, F, st, rstart, erec, t, sX, a2, lmax2);
+        sweep<true, false>(A, F, st, 0, rstart, erec, t, sX, a2, lmax2);
 
         for (int r = MB - 1; r >= 0; --r) {
             const int e0 = ldc(rstart, r), e1 = ldc(rstart, r + 1);
