@@ -235,6 +235,12 @@ __global__ __launch_bounds__(1024) void unrolled_fwd_kernel(UnArgs A) {
     }
 }
 
+// Edges of a layer whose adjoint accesses are issued together.
+#ifndef CBP_UNROLLED_ADJ_GROUP
+#define CBP_UNROLLED_ADJ_GROUP 2
+#endif
+constexpr int kAdjGroup = CBP_UNROLLED_ADJ_GROUP;
+
 // Sum over the 64 lanes of a wave (xor butterfly; every lane gets the total,
 // lane 0's in a fixed order).  Only for workgroups of whole waves.
 __device__ __forceinline__ float wave_sum(float v) {
@@ -411,17 +417,17 @@ __global__ __launch_bounds__(1024) void unrolled_bwd_kernel(UnArgs A) {
             };
             {
                 int e = e0;
-                for (; e + 1 < e1; e += 2) {
-                    AIn p0, p1;
-                    ld_adj(e, p0);
-                    ld_adj(e + 1, p1);
-                    fin_adj(e, p0);
-                    fin_adj(e + 1, p1);
+                for (; e + kAdjGroup <= e1; e += kAdjGroup) {
+                    AIn in[kAdjGroup];
+#pragma unroll
+                    for (int k = 0; k < kAdjGroup; ++k) ld_adj(e + k, in[k]);
+#pragma unroll
+                    for (int k = 0; k < kAdjGroup; ++k) fin_adj(e + k, in[k]);
                 }
-                if (e < e1) {
-                    AIn p0;
-                    ld_adj(e, p0);
-                    fin_adj(e, p0);
+                for (; e < e1; ++e) {
+                    AIn in;
+                    ld_adj(e, in);
+                    fin_adj(e, in);
                 }
             }
             __syncthreads();
