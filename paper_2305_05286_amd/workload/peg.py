@@ -37,14 +37,20 @@ RHO_IRREGULAR = {5: 0.5467, 6: 0.4533}
 _lib = None
 
 
+def build(force: bool = False) -> Path:
+    """Compile peg.c with gcc (when missing, stale, or forced)."""
+    if force or not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+        tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-o", str(tmp), str(SRC)])
+        os.replace(tmp, LIB)
+    return LIB
+
+
 def _load():
     global _lib
     if _lib is None:
-        if not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
-            tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
-            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
-                                   "-o", str(tmp), str(SRC)])
-            os.replace(tmp, LIB)
+        build()
         lib = ctypes.CDLL(str(LIB))
         lib.peg_build.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p]
@@ -136,5 +142,5 @@ def girth(code: Code, limit: int = 12) -> int:
     return best
 
 
-__all__ = ["LAMBDA_IRREGULAR", "RHO_IRREGULAR", "node_degrees", "peg_edges", "peg_code", "girth",
+__all__ = ["LAMBDA_IRREGULAR", "RHO_IRREGULAR", "build", "node_degrees", "peg_edges", "peg_code", "girth",
            "gf2_rank"]
