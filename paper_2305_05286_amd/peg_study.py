@@ -9,7 +9,9 @@ For each PEG code (regular (3,6) and the paper's irregular lambda/rho, lengths
 * ``cbp``        CBP (Sec. IV-C), stopping on a zero syndrome after a sweep;
 * ``cbp_paper``  CBP with the paper's stopping rule (Step 2(3));
 * ``lbp``        layered BP with the log-tanh check rule (Sec. II-B);
-* ``fbp``        flooding BP with the log-tanh check rule (Sec. II-A),
+* ``fbp``        flooding BP with the log-tanh check rule (Sec. II-A);
+* ``cbp_nms``    CBP with the normalized min-sum rule of Sec. IV-D (``--alpha``,
+                 default 0.75; the paper's Figs. 10-12), on request,
 
 all through the library's sparse kernel.  A point stops after ``--errors``
 frame errors or ``--max-frames`` frames.  Frames: BPSK over AWGN (bit 0 -> +1,
@@ -28,7 +30,8 @@ import time
 import numpy as np
 
 DECODERS = {"cbp": ("cbp", {}), "cbp_paper": ("cbp", {"stop_rule": 1}),
-            "lbp": ("lbp", {}), "fbp": ("fbp", {})}
+            "lbp": ("lbp", {}), "fbp": ("fbp", {}), "cbp_nms": ("cbp_nms", {})}
+DEFAULT_DECODERS = ("cbp", "cbp_paper", "lbp", "fbp")
 CODES = ("peg_reg36_n2048", "peg_irr_n2048", "peg_reg36_n8192", "peg_irr_n8192")
 SNRS = (1.2, 1.4, 1.6, 1.8, 2.0, 2.2)
 
@@ -58,12 +61,13 @@ def run_point(handle, pool, rate, ebn0, algo, kw, max_iter, batch, max_frames, t
             "mean_iters": it_sum / n_fr, "seconds": time.perf_counter() - t0}
 
 
-def study(codes=CODES, snrs=SNRS, decoders=tuple(DECODERS), max_iter=200, batch=131072,
-          max_frames=1 << 18, target_errors=100, pool_size=4096, seed=0, log=print):
+def study(codes=CODES, snrs=SNRS, decoders=DEFAULT_DECODERS, max_iter=200, batch=131072,
+          max_frames=1 << 18, target_errors=100, pool_size=4096, seed=0, alpha=0.75, log=print):
     import torch
     from . import cbp
     from .workload import encode, get_code
-    out = {"max_iter": max_iter, "target_errors": target_errors, "max_frames": max_frames, "points": []}
+    out = {"max_iter": max_iter, "target_errors": target_errors, "max_frames": max_frames, "alpha": alpha,
+           "points": []}
     for name in codes:
         code = get_code(name)
         handle = cbp.Code.from_workload(code)
@@ -73,6 +77,8 @@ def study(codes=CODES, snrs=SNRS, decoders=tuple(DECODERS), max_iter=200, batch=
         for ebn0 in snrs:
             for dname in decoders:
                 algo, kw = DECODERS[dname]
+                if algo.endswith("nms"):
+                    kw = dict(kw, alpha=alpha)
                 gen = torch.Generator(device="cuda")
                 gen.manual_seed(int(seed * 1_000_003 + code.N * 101 + round(ebn0 * 100)))
                 r = run_point(handle, pool, code.rate, ebn0, algo, kw, max_iter, batch, max_frames,
@@ -110,15 +116,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--codes", default=",".join(CODES))
     ap.add_argument("--snrs", default=",".join(str(s) for s in SNRS))
-    ap.add_argument("--decoders", default=",".join(DECODERS))
+    ap.add_argument("--decoders", default=",".join(DEFAULT_DECODERS))
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--batch", type=int, default=131072)
     ap.add_argument("--max-frames", type=int, default=1 << 18)
     ap.add_argument("--errors", type=int, default=100)
+    ap.add_argument("--alpha", type=float, default=0.75, help="normalization of the min-sum decoders")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     res = study(a.codes.split(","), [float(s) for s in a.snrs.split(",")], a.decoders.split(","),
-                a.max_iter, a.batch, a.max_frames, a.errors,
+                a.max_iter, a.batch, a.max_frames, a.errors, alpha=a.alpha,
                 log=lambda m: (print(m), sys.stdout.flush()))
     if a.out:
         with open(a.out, "w") as fh:
