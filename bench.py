@@ -431,6 +431,20 @@ def main() -> int:
                "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"first {n} of the {B} timed frames ({op} dB), FP64 CBP oracle, {dt:.1f}s"}
         log(f"[bench] cpu oracle: {n} frames in {dt:.1f}s on {cpu['cores']} threads")
+        # context: the same oracle on one thread, and the layered min-sum oracle,
+        # each on a small sample (about 2 s)
+        n1 = max(16, int(2.0 / max(per * cpu["cores"], 1e-9)))
+        t0 = time.perf_counter()
+        oracle.decode(code, llr[:n1], MI, "cbp", nthreads=1)
+        d1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.decode(code, llr[:n], MI, "lbp_nms")
+        dl = time.perf_counter() - t0
+        cpu["one_thread"] = {"value": round(n1 * K_info / d1 / 1e9, 7), "frames": n1, "seconds": round(d1, 2)}
+        cpu["lbp_nms_oracle"] = {"value": round(n * K_info / dl / 1e9, 6), "frames": n, "seconds": round(dl, 2),
+                                 "cores": cpu["cores"]}
+        log(f"[bench] cpu oracle on one thread: {n1} frames in {d1:.1f}s; layered min-sum oracle: "
+            f"{n} frames in {dl:.1f}s")
 
     out = {
         "metric": METRIC,
