@@ -109,7 +109,15 @@ typedef struct {
      * Min-sum baselines: dump_lam = posterior, dump_r = R.  Rows of frames
      * that stopped before dump_sweep are not written. */
     int32_t dump_sweep;
-    int32_t reserved0;
+    /* Nonzero: scan llr_in for NaN and +-Inf before decoding and return
+     * CBP_EINVAL, decoding nothing, if one is found (the message names the
+     * first such frame and position).  The scan reads the flag back, so the
+     * call synchronises `stream`; not available in cbp_mix_graph_create
+     * (CBP_EUNSUPPORTED).  Zero (default): no scan; a non-finite LLR leaves
+     * the decisions and iteration count of its own frame unspecified (every
+     * memory access is still indexed from the code tables alone, never from a
+     * value, and every loop is bounded by max_iter). */
+    int32_t validate;
     int64_t dump_frames;
     float *dump_q;
     float *dump_r;

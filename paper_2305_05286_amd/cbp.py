@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("check_rule", ctypes.c_int32),
         ("dump_sweep", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("validate", ctypes.c_int32),
         ("dump_frames", ctypes.c_int64),
         ("dump_q", ctypes.c_void_p),
         ("dump_r", ctypes.c_void_p),
@@ -176,10 +176,11 @@ class Code:
 
 
 def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=None,
-          workspace=None, check_rule="log_tanh") -> Opts:
+          workspace=None, check_rule="log_tanh", validate=False) -> Opts:
     o = Opts()
     lib().cbp_opts_default(ctypes.byref(o))
     o.stop_rule, o.hd_mode, o.lmax, o.alpha = stop_rule, hd_mode, lmax, alpha
+    o.validate = 1 if validate else 0
     o.kernel = KERNELS[kernel]
     o.check_rule = RULES[check_rule]
     if dump is not None:
@@ -196,7 +197,7 @@ def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=Non
 
 def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, lmax=20.0,
          alpha=0.75, kernel="auto", dump_sweep: int = 0, dump_frames: int = 0,
-         workspace=None, out=None, stream=None, check_rule="log_tanh"):
+         workspace=None, out=None, stream=None, check_rule="log_tanh", validate=False):
     import torch
     if not (isinstance(llr, torch.Tensor) and llr.is_cuda and llr.dtype == torch.float32):
         raise TypeError("llr must be a float32 CUDA tensor")
@@ -221,7 +222,7 @@ def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, 
             dump["om"] = torch.full((nd, code.M), float("nan"), device=dev)
     if which == "cbp_nms":  # CBP with the normalized min-sum rule of Sec. IV-D
         which, check_rule = "cbp", "min_sum"
-    o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace, check_rule)
+    o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace, check_rule, validate)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode",
                          "fbp_nms": "fbp_nms_decode", "lbp": "lbp_decode", "fbp": "fbp_decode"}[which])
@@ -235,7 +236,8 @@ def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, 
 
 def cbp_decode(code: Code, llr, max_iter: int, **kw):
     """CBP decoding (Sec. IV-C).  Returns (bits uint8 [B,N], iters int32 [B]) on llr's device,
-    plus a dump dict when dump_sweep/dump_frames are given."""
+    plus a dump dict when dump_sweep/dump_frames are given.  validate=True rejects NaN / +-Inf
+    LLRs (CbpError, CBP_EINVAL) before decoding and synchronises the stream."""
     return _run("cbp", code, llr, max_iter, **kw)
 
 

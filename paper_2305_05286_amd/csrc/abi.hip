@@ -409,6 +409,27 @@ size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kerne
     return kSparseCounterBytes + sparse_ws_bytes(algo, g, sparse_lanes(algo, g, batch));
 }
 
+// opts.validate: scan n LLRs for NaN / +-Inf (frames of `row` values, 0 = no frame
+// structure); blocks on s.
+int validate_llr(const float *llr, int64_t n, int64_t row, hipStream_t s) {
+    unsigned long long *pos = nullptr;
+    hipError_t e = hipMallocAsync((void **)&pos, sizeof(*pos), s);
+    if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMallocAsync(8): %s", hipGetErrorString(e));
+    unsigned long long h = ~0ull;
+    e = launch_nonfinite_scan(llr, n, pos, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, pos, sizeof(h), hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipFreeAsync(pos, s);
+    if (e == hipSuccess) e = e2;
+    e2 = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "llr_in scan");
+    if (h != ~0ull && row <= 0) return fail(CBP_EINVAL, "llr_in element %llu is NaN or infinite", h);
+    if (h != ~0ull)
+        return fail(CBP_EINVAL, "llr_in element %llu (frame %lld, position %lld) is NaN or infinite", h,
+                    (long long)(h / (unsigned long long)row), (long long)(h % (unsigned long long)row));
+    return CBP_OK;
+}
+
 int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, int32_t *iters,
            int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
     if (!code) return fail(CBP_EINVAL, "code is NULL");
@@ -427,6 +448,10 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     rc = ensure_device(code, &dev, &g, &qc_sht, &tab);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (opts && opts->validate) {
+        rc = validate_llr(llr, batch * (int64_t)code->N, code->N, s);
+        if (rc) return rc;
+    }
     const size_t need = needed_ws(algo, code, *g, r.kernel, batch);
     void *ws = r.ws;
     bool own = false;
@@ -578,12 +603,16 @@ int mix_decode_impl(const cbp_mix *mc, int32_t decoder, const float *llr, int64_
     const size_t need = mix_ws_bytes(L, batch);
     if (!ws || ws_bytes < need) return fail(CBP_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((uintptr_t)ws & 255) return fail(CBP_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (o.validate) {
+        rc = validate_llr(llr, llr_elems, 0, s);
+        if (rc) return rc;
+    }
     char *w = (char *)ws;
     unsigned int *counter = (unsigned int *)w;
     int64_t *qstart = (int64_t *)(w + 1024);
     int32_t *perm = (int32_t *)(w + kMixHeader);
     char *groups = w + kMixHeader + (((size_t)4 * batch + 255) & ~(size_t)255);
-    hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_mix_prepare(fcode, foff, batch, llr_elems, dc, L.ncodes, qstart, perm, counter, iters, s);
     if (e == hipSuccess)
         e = launch_qc_stream(algo, L, llr, bits, iters, batch, qstart, perm, foff, counter, max_iter, r.p,
@@ -862,6 +891,8 @@ int cbp_mix_graph_create(const cbp_mix_t *mc, int32_t decoder, const float *llr_
     if (!out) return fail(CBP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!mc) return fail(CBP_EINVAL, "mix is NULL");
+    if (opts && opts->validate)
+        return fail(CBP_EUNSUPPORTED, "opts.validate reads a flag back to the host and cannot be captured");
     cbp_mix *m = const_cast<cbp_mix *>(mc);
     // device tables first: their upload is not capturable
     int dev = 0;

@@ -88,6 +88,9 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
 hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
+// *pos (8 bytes, reset by the call) = flat index of the first NaN / +-Inf
+// among x[0 .. n), or all ones if there is none.
+hipError_t launch_nonfinite_scan(const float *x, int64_t n, unsigned long long *pos, hipStream_t s);
 
 // ---- QC streamed kernels (any base matrix, any mix of codes) --------------
 // Base structure of one QC code in sweep order (block-row major, block-column

@@ -456,6 +456,19 @@ __global__ __launch_bounds__(kFillBlock) void fill_i32_kernel(int *p, int n, int
     if (i < n) p[i] = value;
 }
 
+constexpr int kScanBlock = 256;
+constexpr int64_t kScanMaxBlocks = 16384;
+
+// Flat index of the first NaN or +-Inf among n floats (exponent bits all
+// ones): the atomic minimum over the offending indices is left in *pos, which
+// starts at all ones.
+__global__ __launch_bounds__(kScanBlock) void nonfinite_scan_kernel(const uint32_t *x, int64_t n,
+                                                                    unsigned long long *pos) {
+    const int64_t stride = (int64_t)gridDim.x * kScanBlock;
+    for (int64_t i = (int64_t)gid_x() * kScanBlock + tid_x(); i < n; i += stride)
+        if ((x[i] & 0x7f800000u) == 0x7f800000u) atomicMin(pos, (unsigned long long)i);
+}
+
 }  // namespace
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -532,6 +545,16 @@ hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok,
                            hipStream_t s) {
     const dim3 grid((unsigned)((batch + kSyndromeBlock - 1) / kSyndromeBlock)), block(kSyndromeBlock);
     hipLaunchKernelGGL(syndrome_kernel, grid, block, 0, s, g, bits, ok, batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_scan(const float *x, int64_t n, unsigned long long *pos, hipStream_t s) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kFillBlock), 0, s, (int *)pos, 2, -1);
+    if (n > 0) {
+        const int64_t need = (n + kScanBlock - 1) / kScanBlock;
+        const dim3 grid((unsigned)(need < kScanMaxBlocks ? need : kScanMaxBlocks)), block(kScanBlock);
+        hipLaunchKernelGGL(nonfinite_scan_kernel, grid, block, 0, s, (const uint32_t *)x, n, pos);
+    }
     return hipGetLastError();
 }
 

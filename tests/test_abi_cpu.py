@@ -42,7 +42,7 @@ def test_opts_defaults_and_layout(L):
     assert o.lmax == 20.0 and o.alpha == 0.75
     # 8 x 4-byte fields, int64, 6 pointer-sized fields (C natural alignment)
     assert ctypes.sizeof(cbp.Opts) == 88 and cbp.Opts.dump_frames.offset == 32
-    assert o.check_rule == 0
+    assert o.check_rule == 0 and o.validate == 0 and cbp.Opts.validate.offset == 28
 
 
 def test_strerror_and_version(L):

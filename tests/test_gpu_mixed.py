@@ -160,6 +160,28 @@ def test_mixed_schedules_tuner_and_graph_replays():
         assert torch.equal(gbits, eb) and torch.equal(giters, ei), rep
 
 
+def test_mixed_validate_option():
+    """opts.validate on a mixed batch: a NaN is reported by its flat index; a graph cannot
+    capture the scan (CBP_EUNSUPPORTED); finite inputs decode as without it."""
+    codes = small_family()[:3]
+    b = make_mixed_batch(codes, 120, key=(31, 5))
+    llr, fc, fo = to_dev(b)
+    mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])
+    say("[gpu] mixed validate")
+    rb, ri = mix.decode(llr, fc, fo, 20, "cbp")
+    vb, vi = mix.decode(llr, fc, fo, 20, "cbp", validate=True)
+    assert torch.equal(rb, vb) and torch.equal(ri, vi)
+    pos = int(b["offset"][40]) + 3
+    bad = llr.clone()
+    bad[pos] = float("inf")
+    with pytest.raises(cbp.CbpError) as ei:
+        mix.decode(bad, fc, fo, 20, "cbp", validate=True)
+    assert ei.value.status == cbp.CBP_EINVAL and f"element {pos} is" in str(ei.value)
+    with pytest.raises(cbp.CbpError) as ei:
+        mix.graph(llr.clone(), fc.clone(), fo.clone(), 20, "cbp", validate=True)
+    assert ei.value.status == cbp.CBP_EUNSUPPORTED
+
+
 def test_mixed_empty_batch():
     codes = small_family()[:2]
     mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])

@@ -292,6 +292,33 @@ def test_kernel_selection_errors():
         assert ei.value.status == cbp.CBP_EINVAL
 
 
+@pytest.mark.parametrize("algo,kernel", [("cbp", "qc_reg"), ("cbp", "qc_stream"), ("cbp", "sparse"),
+                                         ("lbp_nms", "qc_reg"), ("fbp_nms", "qc_stream"), ("lbp", "sparse")])
+def test_validate_option(algo, kernel):
+    """opts.validate: a NaN or +-Inf LLR gives CBP_EINVAL naming the first one and decodes
+    nothing; finite inputs decode exactly as without the scan."""
+    code = get_code("qc2304")
+    llr, _ = make_frames(code, 2.0, 300, key=(27,))
+    say(f"[gpu] validate {algo} {kernel}")
+    gb0, gi0 = run_gpu(code, llr, 20, algo, kernel=kernel)
+    gb1, gi1 = run_gpu(code, llr, 20, algo, kernel=kernel, validate=True)
+    assert np.array_equal(gb0, gb1) and np.array_equal(gi0, gi1)
+    c = cbp.Code.from_workload(code)
+    for bad, f, v in [(np.nan, 7, 100), (np.inf, 298, 2303), (-np.inf, 0, 0)]:
+        x = llr.copy()
+        x[f, v] = bad
+        x[299, 5] = np.nan                     # a later one is not the one reported
+        t = torch.from_numpy(x).cuda()
+        bits = torch.full((300, code.N), 9, dtype=torch.uint8, device="cuda")
+        iters = torch.full((300,), -7, dtype=torch.int32, device="cuda")
+        with pytest.raises(cbp.CbpError) as ei:
+            cbp.decode(c, t, 20, algo, kernel=kernel, validate=True, out=(bits, iters))
+        assert ei.value.status == cbp.CBP_EINVAL
+        assert f"frame {f}, position {v}" in str(ei.value)
+        torch.cuda.synchronize()
+        assert (bits == 9).all() and (iters == -7).all()    # nothing decoded
+
+
 # ---------------------------------------------- the paper's stopping rule
 
 PAPER_STOP = [("qc2304", "cbp", "qc_reg"), ("qc2304", "cbp_nms", "qc_reg"), ("qc_t64s", "cbp", "qc_reg"),
