@@ -65,12 +65,31 @@ void cbp_code_free(cbp_code_t *code);
 int cbp_code_info(const cbp_code_t *code, int32_t *M, int32_t *N, int64_t *E, int32_t *Z,
                   int32_t *kernels);
 
+/* Row levels of a code (library-computed at creation): level(i) = 1 + the
+ * highest level of the rows before i that share a variable with it (0 if none),
+ * so rows of one level share no variable and every two rows with a common
+ * variable keep their index order.  Such rows commute in the sequential row
+ * schedule of Sec. IV-C (a row reads and writes only messages of its own
+ * variables), which lets the sparse kernel run a frame's sweep level by level
+ * with its rows in parallel.  Outputs (each may be NULL): *nlev; lvl_ptr
+ * [nlev + 1]; rows [M] sorted by (level, index), level l holding
+ * rows[lvl_ptr[l] .. lvl_ptr[l + 1]). */
+int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int32_t *rows);
+
 /* ---- options ----------------------------------------------------------- */
 #define CBP_KERNEL_AUTO 0
 #define CBP_KERNEL_QC_REG 1    /* QC: frame state in VGPRs + LDS (compiled base patterns) */
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
 #define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, persistent (lanes take new  */
                                /* frames as theirs stop), state per wave contiguous      */
+/* Sparse kernel, slow frames: once every frame of the batch has been taken, a
+ * wave with at most 16 busy lanes (CBP_SPARSE_HANDOFF in the environment:
+ * 0 = never, 1..64) copies their frames into the workspace and a second launch
+ * finishes them one frame per wave, running each sweep level by level (see
+ * cbp_code_levels) with the rows of a level on separate lanes.  Results are
+ * bit-identical to finishing them on their lanes.  Not used with stop_rule 1,
+ * hd_mode 1 or state dumps.  CBP_SPARSE_HANDOFF_ITEMS (> 0) caps the frames
+ * handed over (the rest finish on their lanes); the items take at most 8 GiB. */
 
 #define CBP_RULE_LOG_TANH 0
 #define CBP_RULE_MIN_SUM 1

@@ -24,7 +24,7 @@ RULES = {"log_tanh": 0, "min_sum": 1}
 DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2, "lbp": 3, "fbp": 4}
 
 # exported names declared in include/cbp.h
-EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info",
+EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info", "cbp_code_levels",
            "cbp_opts_default", "cbp_decode", "lbp_nms_decode", "fbp_nms_decode",
            "lbp_decode", "fbp_decode", "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
            "cbp_version", "cbp_mix_create", "cbp_mix_free", "cbp_mix_get_schedule",
@@ -82,6 +82,7 @@ def lib():
         L.cbp_code_free.restype = None
         L.cbp_code_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.cbp_code_levels.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
         L.cbp_opts_default.argtypes = [ctypes.POINTER(Opts)]
         L.cbp_opts_default.restype = None
         for name in ("cbp_decode", "lbp_nms_decode", "fbp_nms_decode", "lbp_decode", "fbp_decode"):
@@ -167,6 +168,16 @@ class Code:
 
     def has_kernel(self, name: str) -> bool:
         return bool(self.kernels & KERNELS[name])
+
+    def levels(self):
+        """Row levels (cbp_code_levels): (nlev, lvl_ptr int32 [nlev+1], rows int32 [M])."""
+        import numpy as np
+        n = ctypes.c_int32()
+        check(lib().cbp_code_levels(self.handle, ctypes.byref(n), None, None))
+        ptr = np.empty(n.value + 1, np.int32)
+        rows = np.empty(self.M, np.int32)
+        check(lib().cbp_code_levels(self.handle, None, ptr.ctypes.data, rows.ctypes.data))
+        return n.value, ptr, rows
 
     def __del__(self):
         h = getattr(self, "_h", None)

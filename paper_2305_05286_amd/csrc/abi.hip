@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -54,6 +55,11 @@ struct cbp_code {
     int64_t E = 0;
     std::vector<int> row_ptr, col_idx, edge_row, pred_edge, pred_row, last_edge;
     std::vector<uint8_t> first;
+    // Row levels: rows that share no variable commute in the sequential
+    // schedule, so a sweep may run level by level, each level's rows at once.
+    // Rows sorted by (level, index): lvl_rows[lvl_ptr[l] .. lvl_ptr[l + 1]).
+    int nlev = 0;
+    std::vector<int> lvl_ptr, lvl_rows;
     bool qc = false;
     int mb = 0, nb = 0, Z = 0;
     std::vector<int> shifts;
@@ -105,6 +111,25 @@ int finish_code(cbp_code *c) {
         c->pred_edge[first_edge[v]] = c->last_edge[v];
     }
     for (int64_t e = 0; e < E; ++e) c->pred_row[e] = c->edge_row[c->pred_edge[e]];
+    // level of a row = 1 + the highest level among the earlier rows sharing a
+    // variable with it (rows in index order), so every pair of rows with a
+    // common variable keeps its order and rows of one level are disjoint
+    std::vector<int> lev(M), col_lev(N, 0);
+    int nlev = 0;
+    for (int i = 0; i < M; ++i) {
+        int l = 0;
+        for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) l = std::max(l, col_lev[c->col_idx[e]]);
+        lev[i] = l;
+        for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) col_lev[c->col_idx[e]] = l + 1;
+        nlev = std::max(nlev, l + 1);
+    }
+    c->nlev = nlev;
+    c->lvl_ptr.assign(nlev + 1, 0);
+    for (int i = 0; i < M; ++i) ++c->lvl_ptr[lev[i] + 1];
+    for (int l = 0; l < nlev; ++l) c->lvl_ptr[l + 1] += c->lvl_ptr[l];
+    c->lvl_rows.resize(M);
+    std::vector<int> fill(c->lvl_ptr.begin(), c->lvl_ptr.end() - 1);
+    for (int i = 0; i < M; ++i) c->lvl_rows[fill[lev[i]]++] = i;
     return CBP_OK;
 }
 
@@ -206,7 +231,9 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             qt.resize(q_sc + (sizeof(StreamCode) + 3) / 4, 0);  // filled once the device address is known
         }
         const size_t P = kSparseTablePad;  // padding of col_idx, pred_edge, pred_row, first
-        const size_t ints = (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size();
+        const size_t lvl_ints = (size_t)c->nlev + 1 + (size_t)M;
+        const size_t ints =
+            (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() + lvl_ints;
         const size_t bytes = ints * 4 + (size_t)E + P + 64;
         void *buf = nullptr;
         e = hipMalloc(&buf, bytes);
@@ -246,6 +273,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             t.sc_dev = reinterpret_cast<const StreamCode *>(dq + q_sc);
         }
         if (!qt.empty()) std::memcpy(p, qt.data(), 4 * qt.size());
+        p += qt.size();
+        std::memcpy(p, c->lvl_ptr.data(), 4 * ((size_t)c->nlev + 1));
+        p += c->nlev + 1;
+        std::memcpy(p, c->lvl_rows.data(), 4 * (size_t)M);
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) {
             std::vector<uint8_t> fp(c->first);
@@ -274,6 +305,11 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         d += N;
         t.qc_sht = sht.empty() ? nullptr : d;
         d += sht.size();
+        d += qt.size();
+        t.g.nlev = c->nlev;
+        t.g.lvl_ptr = d;
+        d += c->nlev + 1;
+        t.g.lvl_rows = d;
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;
@@ -288,6 +324,7 @@ struct Resolved {
     Params p;
     Dump d;
     int kernel;
+    bool handoff;  // the sparse kernel may hand slow frames to the level-parallel kernel
     void *ws;
     size_t ws_bytes;
 };
@@ -337,6 +374,10 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     r->d.om = o->dump_om;
     r->d.lam = o->dump_lam;
     if (r->d.sweep == 0) r->d.frames = 0;
+    // the level-parallel kernel runs whole sweeps with the syndrome test on the
+    // V2C-phase decisions (or fixed sweeps), and writes no dumps
+    r->handoff = k == CBP_KERNEL_SPARSE && o->stop_rule != 1 && o->hd_mode == 0 &&
+                 (o->dump_sweep == 0 || o->dump_frames == 0);
     if (o->workspace && ((uintptr_t)o->workspace & 255))
         return fail(CBP_EINVAL, "workspace must be 256-byte aligned");
     r->ws = o->workspace;
@@ -354,7 +395,39 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
 #endif
 constexpr int64_t kSparseMaxLanes = (int64_t)CBP_SPARSE_MAX_WAVES * 64;
 constexpr int64_t kSparseMaxBytes = (int64_t)32 << 30;
-constexpr size_t kSparseCounterBytes = 256;  // frame counter ahead of the slots
+constexpr size_t kSparseCounterBytes = 256;  // frame counter, hand-off counters ahead of the slots
+
+// Hand-off of slow frames (sparse kernel): once the batch is exhausted, a wave
+// with at most this many busy lanes hands their frames to the level-parallel
+// kernel.  CBP_SPARSE_HANDOFF in the environment overrides it (0 = never,
+// 64 = as soon as the batch is exhausted).  Items take at most
+// kHandoffMaxBytes (CBP_SPARSE_HANDOFF_ITEMS can lower their number; frames
+// beyond it finish on their lanes); the level-parallel launch has at most
+// kHandoffWaves waves.
+constexpr int kHandoffLanes = 16;
+constexpr int64_t kHandoffMaxBytes = (int64_t)8 << 30;
+constexpr int kHandoffWaves = 8192;
+
+// A non-negative integer from the environment, else `def`.
+int64_t env_count(const char *name, int64_t def) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return def;
+    char *end = nullptr;
+    const long long n = std::strtoll(v, &end, 10);
+    if (*end || n < 0) return def;
+    return n > ((int64_t)1 << 40) ? ((int64_t)1 << 40) : (int64_t)n;
+}
+
+int handoff_lanes() { return (int)std::min<int64_t>(env_count("CBP_SPARSE_HANDOFF", kHandoffLanes), 64); }
+
+// Workspace of a sparse decode: header (kSparseCounterBytes), hand-off items
+// (cap x 8 bytes, then cap frame states), then the lanes' blocks.
+struct SparsePlan {
+    int64_t lanes = 0;
+    uint32_t cap = 0;
+    int64_t item_bytes = 0;
+    size_t items_off = 0, state_off = 0, blocks_off = 0, total = 0;
+};
 
 int64_t sparse_lanes(int algo, const SparseDev &g, int64_t batch) {
     const int64_t per = (int64_t)(sparse_ws_bytes(algo, g, 64) / 64) + 1;
@@ -400,13 +473,32 @@ int device_cus(int dev) {
     return cus;
 }
 
-size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch) {
+SparsePlan sparse_plan(int algo, const SparseDev &g, int64_t batch, bool handoff) {
+    SparsePlan sp;
+    sp.lanes = sparse_lanes(algo, g, batch);
+    sp.item_bytes = sparse_item_bytes(algo, g);
+    if (handoff && handoff_lanes() > 0) {
+        // CBP_SPARSE_HANDOFF_ITEMS (> 0) lowers the number of items
+        const int64_t lim = env_count("CBP_SPARSE_HANDOFF_ITEMS", 0);
+        int64_t cap = std::min<int64_t>(sp.lanes, kHandoffMaxBytes / sp.item_bytes);
+        if (lim > 0) cap = std::min(cap, lim);
+        sp.cap = (uint32_t)cap;
+    }
+    sp.items_off = kSparseCounterBytes;
+    sp.state_off = sp.items_off + (size_t)round256(8 * (int64_t)sp.cap);
+    sp.blocks_off = sp.state_off + (size_t)sp.cap * (size_t)sp.item_bytes;
+    sp.total = sp.blocks_off + sparse_ws_bytes(algo, g, sp.lanes);
+    return sp;
+}
+
+size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch,
+                 bool handoff) {
     if (kernel == CBP_KERNEL_QC_REG) return 256;
     if (kernel == CBP_KERNEL_QC_STREAM) {
         const StreamLaunch L = single_stream(algo, code, batch);
         return 256 + (size_t)L.groups * L.group_bytes;
     }
-    return kSparseCounterBytes + sparse_ws_bytes(algo, g, sparse_lanes(algo, g, batch));
+    return sparse_plan(algo, g, batch, handoff).total;
 }
 
 // opts.validate: scan n LLRs for NaN / +-Inf (frames of `row` values, 0 = no frame
@@ -452,7 +544,7 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
         rc = validate_llr(llr, batch * (int64_t)code->N, code->N, s);
         if (rc) return rc;
     }
-    const size_t need = needed_ws(algo, code, *g, r.kernel, batch);
+    const size_t need = needed_ws(algo, code, *g, r.kernel, batch, r.handoff);
     void *ws = r.ws;
     bool own = false;
     if (!ws || r.ws_bytes < need) {
@@ -487,10 +579,22 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
             if (own) (void)hipFreeAsync(ws, s);
             return fail(CBP_EUNSUPPORTED, "the sparse kernel indexes its state with 32 bits: at most 2^26 edges");
         }
-        const SparseWs w = sparse_ws_carve(algo, *g, sparse_lanes(algo, *g, batch),
-                                           (char *)ws + kSparseCounterBytes);
+        const SparsePlan sp = sparse_plan(algo, *g, batch, r.handoff);
+        const SparseWs w = sparse_ws_carve(algo, *g, sp.lanes, (char *)ws + sp.blocks_off);
+        Handoff h{};
+        const int hl = handoff_lanes();
+        if (sp.cap > 0 && hl > 0 && max_iter > 1) {
+            h.lanes = hl;
+            h.cap = sp.cap;
+            h.waves = (int)std::min<int64_t>(sp.cap, kHandoffWaves);
+            h.count = (unsigned int *)((char *)ws + 8);
+            h.claim = (unsigned int *)((char *)ws + 12);
+            h.items = (int2 *)((char *)ws + sp.items_off);
+            h.state = (char *)ws + sp.state_off;
+            h.item_bytes = sp.item_bytes;
+        }
         e = launch_sparse(algo, *g, llr, bits, iters, batch, max_iter, r.p, w, r.d,
-                          (unsigned long long *)ws, s);
+                          (unsigned long long *)ws, h, s);
     }
     if (own) {
         hipError_t e2 = hipFreeAsync(ws, s);
@@ -1031,6 +1135,14 @@ void cbp_code_free(cbp_code_t *c) {
     delete c;
 }
 
+int cbp_code_levels(const cbp_code_t *c, int32_t *nlev, int32_t *lvl_ptr, int32_t *rows) {
+    if (!c) return fail(CBP_EINVAL, "code is NULL");
+    if (nlev) *nlev = c->nlev;
+    if (lvl_ptr) std::memcpy(lvl_ptr, c->lvl_ptr.data(), 4 * ((size_t)c->nlev + 1));
+    if (rows) std::memcpy(rows, c->lvl_rows.data(), 4 * (size_t)c->M);
+    return CBP_OK;
+}
+
 int cbp_code_info(const cbp_code_t *c, int32_t *M, int32_t *N, int64_t *E, int32_t *Z,
                   int32_t *kernels) {
     if (!c) return fail(CBP_EINVAL, "code is NULL");
@@ -1087,7 +1199,7 @@ int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch, c
     g.M = code->M;
     g.N = code->N;
     g.E = (int)code->E;
-    *bytes = batch == 0 ? 0 : needed_ws(algo, code, g, r.kernel, batch);
+    *bytes = batch == 0 ? 0 : needed_ws(algo, code, g, r.kernel, batch, r.handoff);
     return CBP_OK;
 }
 

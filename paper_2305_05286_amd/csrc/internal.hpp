@@ -58,6 +58,9 @@ struct SparseDev {
     const int *pred_row;  // [E]  row of pred_edge
     const uint8_t *first; // [E]  1 if this is the lowest row of its column
     const int *last_edge; // [N]  edge of the highest row of each column
+    int nlev;             // row levels (rows of one level share no variable)
+    const int *lvl_ptr;   // [nlev+1] first entry of each level in lvl_rows
+    const int *lvl_rows;  // [M] rows by (level, index)
 };
 
 // col_idx, pred_edge, pred_row and first are readable (zeros) for this many
@@ -77,14 +80,36 @@ struct SparseWs {
     uint8_t *xb;
 };
 
+__host__ __device__ inline int64_t round256(int64_t x) { return (x + 255) / 256 * 256; }
+
+// Hand-off of slow frames from the one-frame-per-lane kernels to a
+// level-parallel kernel (one frame per wave, the rows of each level on
+// separate lanes).  An item holds one frame's state contiguously: CBP Q, PQ
+// [N], R [E], OmM, OmS [M], decisions [N]; BP Lambda [N], R [E], sums [N],
+// decisions [N]; each array 256-byte aligned.
+struct Handoff {
+    int lanes;            // a wave hands over once the batch is exhausted and at most
+                          // this many of its lanes are busy (0 = never)
+    uint32_t cap;         // items
+    int waves;            // waves of the level-parallel launch
+    unsigned int *count;  // frames handed over (any beyond cap stay on their lanes)
+    unsigned int *claim;  // items taken by the level-parallel launch
+    int2 *items;          // [cap] (frame, sweeps done)
+    char *state;          // [cap] frame states, item_bytes apart
+    int64_t item_bytes;
+};
+int64_t sparse_item_bytes(int algo, const SparseDev &g);
+
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames);
 SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base);
 // Persistent sparse launch: one wave per block of `ws`, lanes take frames
-// 0 .. nf-1 from `counter` (8 bytes, reset by the launch).
+// 0 .. nf-1 from `counter` (16 bytes: the frame counter, then h.count and
+// h.claim; reset by the launch).  With h.lanes > 0 a level-parallel launch
+// over the handed-over frames follows on the same stream.
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
                          const SparseWs &ws, const Dump &d, unsigned long long *counter,
-                         hipStream_t s);
+                         const Handoff &h, hipStream_t s);
 hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);

@@ -64,13 +64,16 @@ __device__ __forceinline__ SparseWs wave_block(SparseWs w) {
     return w;
 }
 
-// The next frame index for every lane in `want` (a wave-uniform ballot): one
-// atomic add per wave on the batch's frame counter, then each wanting lane
-// takes base + (wanting lanes below it).  Values of other lanes are undefined.
+// The next frame index for every lane in `want` (a wave-uniform ballot): the
+// leader adds the number of wanting lanes to the batch's frame counter, then
+// each wanting lane takes base + (wanting lanes below it).  Values of other
+// lanes are undefined.
 __device__ __forceinline__ int64_t claim_frames(unsigned long long *counter, uint64_t want) {
     const int leader = __builtin_ctzll(want);
-    unsigned long long base = 0;
-    if (tid_x() == leader) base = atomicAdd(counter, (unsigned long long)__builtin_popcountll(want));
+    // every active lane executes the atomic (the leader adds the count, the
+    // others 0), so the leader's result is not behind a branch
+    const unsigned long long base =
+        atomicAdd(counter, tid_x() == leader ? (unsigned long long)__builtin_popcountll(want) : 0ull);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
     const uint64_t below = want & ((1ull << tid_x()) - 1ull);
@@ -126,15 +129,193 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, uint32_t 
     return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
 }
 
+// Element idx of a state array whose frames are kStride apart: kStride = 64
+// for lane lf of a wave's frame-interleaved block, 1 (lf = 0) for one frame's
+// contiguous copy.
+template <int kStride>
+__device__ __forceinline__ uint32_t ix(int idx, uint32_t lf) {
+    return (uint32_t)idx * (uint32_t)kStride + lf;
+}
+
+struct CbpState {
+    float *Q, *PQ, *R, *OmM, *OmS;
+    uint8_t *xb;
+};
+
+// One check-node update of CBP on one frame: Step 2(1) a-e for each edge of
+// row i in ascending column order, then Step 2(2).  Returns the sign parity of
+// the new belief; with stop_rule 1 ors into flip whether a decision changed.
+// sweep1: first sweep, where a first-visit edge has no latest check yet.
+template <bool kMin, int kStride>
+__device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, bool sweep1, const CbpState &st, uint32_t lf,
+                                        const Params &p, bool &flip) {
+    float *Q = st.Q, *PQ = st.PQ, *R = st.R;
+    uint8_t *xb = st.xb;
+    float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
+    bool par = false;
+    const int e1 = ldc(g.row_ptr, i + 1);
+    // The row's edges in chunks of kChunk: every load of a chunk is issued
+    // before its first store, so a chunk costs one memory round trip instead
+    // of one per edge.  Within a row the columns differ, so no load of a chunk
+    // reads what an earlier edge of the same chunk stores, except R(c_i -> v)
+    // when v's latest check is c_i itself (a column of weight one): that
+    // commit is forwarded in registers.
+    for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
+        const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+        // the chunk's table entries, unconditionally (padded tables)
+        int col[kChunk], pe[kChunk], pr[kChunk];
+        uint32_t fi[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            col[k] = ldc(g.col_idx, c0 + k);
+            pe[k] = ldc(g.pred_edge, c0 + k);
+            pr[k] = ldc(g.pred_row, c0 + k);
+            fi[k] = ldc_u8(g.first, c0 + k);
+        }
+        float q[kChunk], pq[kChunk], om[kChunk], os[kChunk], r[kChunk];
+        uint8_t x0[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (k < n) {
+                const uint32_t iv = ix<kStride>(col[k], lf);
+                q[k] = Q[iv];
+                if (!kMin) pq[k] = PQ[iv];
+                if (!(sweep1 && fi[k])) {
+                    const uint32_t ij = ix<kStride>(pr[k], lf);
+                    om[k] = st.OmM[ij];
+                    os[k] = st.OmS[ij];
+                }
+                r[k] = R[ix<kStride>(c0 + k, lf)];
+                if (p.stop_rule == 1) x0[k] = xb[iv];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (k < n) {
+                const int e = c0 + k;
+                const uint32_t iv = ix<kStride>(col[k], lf);
+                float rn = 0.0f, rc = r[k];
+                if (!(sweep1 && fi[k])) {
+                    // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
+                    // from its belief, then committed to R(c_j -> v) first.
+                    rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
+                    R[ix<kStride>(pe[k], lf)] = rn;
+                    if (pe[k] == e) rc = rn;
+                }
+                const float lam = q[k] + rn;              // eq. equ_s4e20
+                const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
+                if (p.stop_rule == 1) flip |= nx != x0[k];
+                xb[iv] = nx;
+                const float qn = lam - rc;                // V2C, eq. equ_s4e19
+                Q[iv] = qn;
+                if constexpr (!kMin) {
+                    const float fq = phi2_clamped(qn, p.a, p.lmax);
+                    PQ[iv] = fq;
+                    fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
+                } else {                                  // eq. equ_s4e21xx
+                    const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
+                    Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
+                    Mx = __builtin_fminf(Mx, aq);
+                }
+                par ^= (qn < 0.0f);
+            }
+        }
+    }
+    st.OmM[ix<kStride>(i, lf)] = with_sign(Mx, par);  // eq. equ_s4e23
+    st.OmS[ix<kStride>(i, lf)] = Sr;
+    return par;
+}
+
+// Hand-off of slow frames.  Once the batch is exhausted and a wave has only a
+// few busy lanes left, their frames are copied, by the wave's active lanes, to
+// contiguous items of h (while items are free) and finished by the
+// level-parallel kernel.  An item: (frame, sweeps done) in h.items and the
+// frame's state in h.state.
+__device__ __forceinline__ char *item_base(const Handoff &h, uint32_t k) {
+    return h.state + (int64_t)k * h.item_bytes;
+}
+
+__device__ __forceinline__ CbpState cbp_state(const SparseWs &w) {
+    return CbpState{w.a0, w.a1, w.a2, w.a3, w.a4, w.xb};
+}
+
+__device__ __forceinline__ CbpState cbp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
+    char *b = item_base(h, k);
+    CbpState st;
+    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m4 = round256(4 * (int64_t)g.M);
+    st.Q = (float *)b;
+    st.PQ = (float *)(b + n4);
+    st.R = (float *)(b + 2 * n4);
+    st.OmM = (float *)(b + 2 * n4 + e4);
+    st.OmS = (float *)(b + 2 * n4 + e4 + m4);
+    st.xb = (uint8_t *)(b + 2 * n4 + e4 + 2 * m4);
+    return st;
+}
+
+// The active lanes of the wave (rank r of na) copy lane d's slot
+// (frame-interleaved) into item k (contiguous).
+template <class T>
+__device__ __forceinline__ void copy_slot(T *dst, const T *src, int n, uint32_t d, int r, int na) {
+#pragma unroll 4
+    for (int idx = r; idx < n; idx += na) dst[idx] = src[at(idx, d)];
+}
+
+// Rank of this lane among the active lanes, and their number.
+__device__ __forceinline__ void active_rank(int &r, int &na) {
+    const uint64_t act = __ballot(1);
+    r = __builtin_popcountll(act & ((1ull << tid_x()) - 1ull));
+    na = __builtin_popcountll(act);
+}
+
+// Unfinished frames of the lanes in `hand` (wave-uniform ballot) go to their
+// items hk; each such lane then asks for a new frame.
+__device__ __forceinline__ void hand_over_cbp(const SparseDev &g, const Handoff &h, const CbpState &w,
+                                              uint64_t hand, uint32_t hk, int64_t f, int t) {
+    for (uint64_t m = hand; m != 0; m &= m - 1) {
+        const int d = __builtin_ctzll(m);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)hk, d);
+        const int fd = __builtin_amdgcn_readlane((int)f, d);
+        const int td = __builtin_amdgcn_readlane(t, d);
+        const CbpState it = cbp_item(g, h, k);
+        int r, na;
+        active_rank(r, na);
+        copy_slot(it.Q, w.Q, g.N, d, r, na);
+        copy_slot(it.PQ, w.PQ, g.N, d, r, na);
+        copy_slot(it.xb, w.xb, g.N, d, r, na);
+        copy_slot(it.R, w.R, g.E, d, r, na);
+        copy_slot(it.OmM, w.OmM, g.M, d, r, na);
+        copy_slot(it.OmS, w.OmS, g.M, d, r, na);
+        if (r == 0) h.items[k] = make_int2(fd, td);
+    }
+}
+
+// Whether this wave hands its frames over now: every frame of the batch has
+// been taken and at most h.lanes of its lanes are still busy (each such lane
+// then works alone for a whole sweep at a time).  Each busy lane claims an
+// item; hand = a free item was left for it (hk), else its frame stays.
+__device__ __forceinline__ bool handing_off(const Handoff &h, unsigned long long *counter, int64_t nf, bool busy,
+                                            bool &hand, uint32_t &hk) {
+    const uint64_t bm = __ballot(busy);
+    if (bm == 0 || __builtin_popcountll(bm) > h.lanes) return false;
+    const unsigned long long taken = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane((int)(taken < (unsigned long long)nf))) return false;
+    if (busy) {
+        hk = atomicAdd(h.count, 1u);
+        hand = hk < h.cap;
+    }
+    return __ballot(hand) != 0;
+}
+
 // kMin: the normalized min-sum check rule (OmM = min1 | parity, OmS = min2).
 template <bool kMin>
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
-    unsigned long long *counter) {
+    unsigned long long *counter, Handoff h) {
     w = wave_block(w);
     const uint32_t lf = tid_x();  // this lane's slot in its wave's block
-    float *Q = w.a0, *PQ = w.a1, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
+    const CbpState st = cbp_state(w);
+    float *Q = w.a0, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
     const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
     p.a *= us;
@@ -172,85 +353,16 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             }
         }
         if (__ballot(!done) == 0) break;
+        bool hand = false;
+        uint32_t hk = 0;
         if (!done) {
             ++t;
             // Step 2: check-nodes in index order
             bool paper_stop = false;
             int istop = 0;
             for (int i = 0; i < g.M; ++i) {
-                float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
-                bool par = false, flip = false;
-                const int e1 = ldc(g.row_ptr, i + 1);
-                // The row's edges in chunks of kChunk: every load of a chunk is
-                // issued before its first store, so a chunk costs one memory
-                // round trip instead of one per edge.  Within a row the columns
-                // differ, so no load of a chunk reads what an earlier edge of
-                // the same chunk stores, except R(c_i -> v) when v's latest
-                // check is c_i itself (a column of weight one): that commit is
-                // forwarded in registers.
-                for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
-                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
-                    // the chunk's table entries, unconditionally (padded tables)
-                    int col[kChunk], pe[kChunk], pr[kChunk];
-                    uint32_t fi[kChunk];
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
-                        col[k] = ldc(g.col_idx, c0 + k);
-                        pe[k] = ldc(g.pred_edge, c0 + k);
-                        pr[k] = ldc(g.pred_row, c0 + k);
-                        fi[k] = ldc_u8(g.first, c0 + k);
-                    }
-                    float q[kChunk], pq[kChunk], om[kChunk], os[kChunk], r[kChunk];
-                    uint8_t x0[kChunk];
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
-                        if (k < n) {
-                            const uint32_t iv = at(col[k], lf);
-                            q[k] = Q[iv];
-                            if (!kMin) pq[k] = PQ[iv];
-                            if (!(t == 1 && fi[k])) {
-                                const uint32_t ij = at(pr[k], lf);
-                                om[k] = OmM[ij];
-                                os[k] = OmS[ij];
-                            }
-                            r[k] = R[at(c0 + k, lf)];
-                            if (p.stop_rule == 1) x0[k] = xb[iv];
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
-                        if (k < n) {
-                            const int e = c0 + k;
-                            const uint32_t iv = at(col[k], lf);
-                            float rn = 0.0f, rc = r[k];
-                            if (!(t == 1 && fi[k])) {
-                                // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
-                                // from its belief, then committed to R(c_j -> v) first.
-                                rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
-                                R[at(pe[k], lf)] = rn;
-                                if (pe[k] == e) rc = rn;
-                            }
-                            const float lam = q[k] + rn;              // eq. equ_s4e20
-                            const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
-                            if (p.stop_rule == 1) flip |= nx != x0[k];
-                            xb[iv] = nx;
-                            const float qn = lam - rc;                // V2C, eq. equ_s4e19
-                            Q[iv] = qn;
-                            if constexpr (!kMin) {
-                                const float fq = phi2_clamped(qn, p.a, p.lmax);
-                                PQ[iv] = fq;
-                                fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
-                            } else {                                  // eq. equ_s4e21xx
-                                const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
-                                Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
-                                Mx = __builtin_fminf(Mx, aq);
-                            }
-                            par ^= (qn < 0.0f);
-                        }
-                    }
-                }
-                OmM[at(i, lf)] = with_sign(Mx, par);  // eq. equ_s4e23
-                OmS[at(i, lf)] = Sr;
+                bool flip = false;
+                const bool par = cbp_row<kMin, kWave>(g, i, t == 1, st, lf, p, flip);
                 if (p.stop_rule == 1) {  // Step 2(3): M updates in a row with Omega > 0, no flip
                     run = (!par && !flip) ? run + 1 : 0;
                     if (run >= g.M) {
@@ -291,6 +403,87 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                 need = true;
             }
         }
+        if (h.lanes > 0 && handing_off(h, counter, nf, !done && !need, hand, hk))
+            hand_over_cbp(g, h, st, __ballot(hand), hk, f, t);
+        if (hand) need = true;
+    }
+}
+
+// Syndrome of one contiguous frame, rows spread over the wave's lanes.
+// A row's column entries in chunks of kChunk, read unconditionally (padded
+// table) so that the loads of a chunk go out together.
+__device__ bool wave_syndrome_ok(const SparseDev &g, const uint8_t *xb) {
+    uint32_t bad = 0;
+    for (int i = tid_x(); i < g.M; i += kWave) {
+        uint32_t par = 0;
+        const int e1 = ldc(g.row_ptr, i + 1);
+        for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
+            int col[kChunk];
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k)
+                if (c0 + k < e1) par ^= xb[col[k]];
+        }
+        bad |= par;
+    }
+    return __ballot(bad != 0) == 0;
+}
+
+// The next item for this wave, or false once none is left.  Every active lane
+// executes the atomic (the first adds 1, the others 0) rather than one lane
+// inside a branch, and the item index and count are read into wave-uniform
+// registers: with a per-lane claim inside a branch and a loop bound loaded
+// per lane, the compiler may split the loop by lanes, and the lanes left
+// behind would read a stale index.
+__device__ __forceinline__ bool next_item(const Handoff &h, uint32_t &k) {
+    const int leader = __builtin_ctzll(__ballot(1));
+    const uint32_t v = atomicAdd(h.claim, tid_x() == leader ? 1u : 0u);
+    k = (uint32_t)__builtin_amdgcn_readlane((int)v, leader);
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)*h.count);
+    return k < (n < h.cap ? n : h.cap);
+}
+
+// Item k's (frame, sweeps done), wave-uniform.
+__device__ __forceinline__ int2 item_head(const Handoff &h, uint32_t k) {
+    const int2 it = h.items[k];
+    return make_int2(__builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y));
+}
+
+// Level-parallel CBP on handed-over frames, one frame per wave: each sweep
+// runs the row levels in order, the rows of a level on separate lanes (rows
+// of a level share no variable, so every row sees exactly the state the
+// sequential schedule gives it and the result is the same bit for bit).
+template <bool kMin>
+__global__ __launch_bounds__(kWave) void cbp_level_kernel(SparseDev g, uint8_t *__restrict__ bits,
+                                                          int32_t *__restrict__ iters, int max_iter, Params p,
+                                                          Handoff h) {
+    const float us = kMin ? 1.0f : kLog2e;
+    p.a *= us;
+    p.lmax *= us;
+    uint32_t k;
+    while (next_item(h, k)) {
+        const CbpState st = cbp_item(g, h, k);
+        const int2 it = item_head(h, k);
+        const int64_t f = it.x;
+        int t = it.y;
+        for (;;) {
+            ++t;
+            for (int l = 0; l < g.nlev; ++l) {
+                const int r1 = ldc(g.lvl_ptr, l + 1);
+                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kWave) {
+                    bool flip = false;
+                    (void)cbp_row<kMin, 1>(g, ldc(g.lvl_rows, r), false, st, 0, p, flip);
+                }
+                __syncthreads();
+            }
+            const bool stop = t >= max_iter || (p.stop_rule == 0 && wave_syndrome_ok(g, st.xb));
+            if (stop) {
+                for (int v = tid_x(); v < g.N; v += kWave) bits[f * g.N + v] = st.xb[v];
+                if (tid_x() == 0) iters[f] = t;
+                break;
+            }
+        }
     }
 }
 
@@ -302,14 +495,121 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
 // (as in the CBP kernel): each row folds g(|Q|) of its edges into a
 // (max, rest) pair and excludes an edge's own term from it exactly.
 // --------------------------------------------------------------------------
+struct BpState {
+    float *Lam, *R, *Acc;
+    uint8_t *xb;
+};
+
+// One row of the layered (kFlood false) or flooding schedule on one frame.
+template <bool kFlood, bool kMin, int kStride>
+__device__ __forceinline__ void bp_row(const SparseDev &g, int i, const BpState &st, uint32_t lf, const Params &p) {
+    float *Lam = st.Lam, *R = st.R, *Acc = st.Acc;
+    const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
+    // min-sum: (m1, m2) = two smallest |Q|; log-tanh: (m1, m2) = (max, rest) of g(|Q|)
+    float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
+    bool par = false;
+    // Edges in chunks of kChunk with all loads of a chunk issued together (the
+    // columns of a row differ, so they never read what the chunk stores).  A
+    // row of at most kChunk edges keeps its V2C messages in registers between
+    // the two passes.
+    float qs[kChunk];
+    for (int c0 = e0; c0 < e1; c0 += kChunk) {
+        const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+        int col[kChunk];  // read unconditionally (padded table)
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
+        float lv[kChunk], rv[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (k < n) {
+                lv[k] = Lam[ix<kStride>(col[k], lf)];
+                rv[k] = R[ix<kStride>(c0 + k, lf)];
+            }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (k < n) {
+                // V2C, eq. equ_s2e3 (flooding: Lambda of the previous sweep) / equ_s2e10
+                const float q = lv[k] - rv[k];
+                qs[k] = q;
+                if constexpr (kMin) {
+                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                    m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
+                    m1 = __builtin_fminf(m1, aq);
+                } else {
+                    fold(m1, m2, phi2_clamped(q, p.a, p.lmax));
+                }
+                par ^= (q < 0.0f);
+            }
+    }
+    const bool kept = e1 - e0 <= kChunk;
+    for (int c0 = e0; c0 < e1; c0 += kChunk) {
+        const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
+        int col[kChunk];  // read unconditionally (padded table)
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
+        float qv[kChunk], av[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (k < n) {
+                const uint32_t iv = ix<kStride>(col[k], lf);
+                qv[k] = kept ? qs[k] : Lam[iv] - R[ix<kStride>(c0 + k, lf)];
+                if (kFlood) av[k] = Acc[iv];
+            }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k)
+            if (k < n) {
+                const uint32_t iv = ix<kStride>(col[k], lf);
+                const float q = qv[k];
+                float rn;
+                if constexpr (kMin) {
+                    const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                    rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
+                } else {  // C2V, eq. equ_s2e4
+                    rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))), par ^ (q < 0.0f));
+                }
+                R[ix<kStride>(c0 + k, lf)] = rn;
+                if (kFlood) Acc[iv] = av[k] + rn;
+                else Lam[iv] = q + rn;  // eq. equ_s2e12
+            }
+    }
+}
+
+// Posterior of the flooding schedule (eq. equ_s2e6) from the channel LLR in
+// log2 units and the sum of the C2V messages.
+__device__ __forceinline__ float flood_posterior(float l, float us, float acc) { return l * us + acc; }
+
+__device__ __forceinline__ BpState bp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
+    char *b = item_base(h, k);
+    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E);
+    return BpState{(float *)b, (float *)(b + n4), (float *)(b + n4 + e4), (uint8_t *)(b + 2 * n4 + e4)};
+}
+
+__device__ __forceinline__ void hand_over_bp(const SparseDev &g, const Handoff &h, const BpState &w,
+                                             uint64_t hand, uint32_t hk, int64_t f, int t) {
+    for (uint64_t m = hand; m != 0; m &= m - 1) {
+        const int d = __builtin_ctzll(m);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)hk, d);
+        const int fd = __builtin_amdgcn_readlane((int)f, d);
+        const int td = __builtin_amdgcn_readlane(t, d);
+        const BpState it = bp_item(g, h, k);
+        int r, na;
+        active_rank(r, na);
+        copy_slot(it.Lam, w.Lam, g.N, d, r, na);
+        copy_slot(it.xb, w.xb, g.N, d, r, na);
+        copy_slot(it.R, w.R, g.E, d, r, na);
+        if (r == 0) h.items[k] = make_int2(fd, td);
+    }
+}
+
 template <bool kFlood, bool kMin>
 __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
     int32_t *__restrict__ iters, int64_t nf, int max_iter, Params p, SparseWs w, Dump d,
-    unsigned long long *counter) {
+    unsigned long long *counter, Handoff h) {
     w = wave_block(w);
     const uint32_t lf = tid_x();  // this lane's slot in its wave's block
     float *Lam = w.a0, *R = w.a1, *Acc = w.a2;
+    const BpState st{Lam, R, Acc, w.xb};
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
     const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
     p.a *= us;
@@ -342,85 +642,17 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
             }
         }
         if (__ballot(!done) == 0) break;
+        bool hand = false;
+        uint32_t hk = 0;
         if (!done) {
             ++t;
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) Acc[at(v, lf)] = 0.0f;
-            for (int i = 0; i < g.M; ++i) {
-                const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
-                // min-sum: (m1, m2) = two smallest |Q|; log-tanh: (m1, m2) = (max, rest) of g(|Q|)
-                float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
-                bool par = false;
-                // Edges in chunks of kChunk with all loads of a chunk issued
-                // together (the columns of a row differ, so they never read what
-                // the chunk stores).  A row of at most kChunk edges keeps its V2C
-                // messages in registers between the two passes.
-                float qs[kChunk];
-                for (int c0 = e0; c0 < e1; c0 += kChunk) {
-                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
-                    int col[kChunk];  // read unconditionally (padded table)
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
-                    float lv[kChunk], rv[kChunk];
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k)
-                        if (k < n) {
-                            lv[k] = Lam[at(col[k], lf)];
-                            rv[k] = R[at((c0 + k), lf)];
-                        }
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k)
-                        if (k < n) {
-                            // V2C, eq. equ_s2e3 (flooding: Lambda of the previous sweep) / equ_s2e10
-                            const float q = lv[k] - rv[k];
-                            qs[k] = q;
-                            if constexpr (kMin) {
-                                const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-                                m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
-                                m1 = __builtin_fminf(m1, aq);
-                            } else {
-                                fold(m1, m2, phi2_clamped(q, p.a, p.lmax));
-                            }
-                            par ^= (q < 0.0f);
-                        }
-                }
-                const bool kept = e1 - e0 <= kChunk;
-                for (int c0 = e0; c0 < e1; c0 += kChunk) {
-                    const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
-                    int col[kChunk];  // read unconditionally (padded table)
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k) col[k] = ldc(g.col_idx, c0 + k);
-                    float qv[kChunk], av[kChunk];
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k)
-                        if (k < n) {
-                            const uint32_t iv = at(col[k], lf);
-                            qv[k] = kept ? qs[k] : Lam[iv] - R[at((c0 + k), lf)];
-                            if (kFlood) av[k] = Acc[iv];
-                        }
-#pragma unroll
-                    for (int k = 0; k < kChunk; ++k)
-                        if (k < n) {
-                            const uint32_t iv = at(col[k], lf);
-                            const float q = qv[k];
-                            float rn;
-                            if constexpr (kMin) {
-                                const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-                                rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
-                            } else {  // C2V, eq. equ_s2e4
-                                rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))),
-                                               par ^ (q < 0.0f));
-                            }
-                            R[at((c0 + k), lf)] = rn;
-                            if (kFlood) Acc[iv] = av[k] + rn;
-                            else Lam[iv] = q + rn;  // eq. equ_s2e12
-                        }
-                }
-            }
+            for (int i = 0; i < g.M; ++i) bp_row<kFlood, kMin, kWave>(g, i, st, lf, p);
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) {
                     const uint32_t iv = at(v, lf);
-                    Lam[iv] = llr[f * g.N + v] * us + Acc[iv];  // eq. equ_s2e6
+                    Lam[iv] = flood_posterior(llr[f * g.N + v], us, Acc[iv]);
                 }
             for (int v = 0; v < g.N; ++v) xb[at(v, lf)] = Lam[at(v, lf)] < 0.0f;
             if (t == d.sweep && f < d.frames) {
@@ -433,6 +665,52 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
             if (stop) {
                 write_out(g, xb, lf, bits, iters, f, t);
                 need = true;
+            }
+        }
+        if (h.lanes > 0 && handing_off(h, counter, nf, !done && !need, hand, hk))
+            hand_over_bp(g, h, st, __ballot(hand), hk, f, t);
+        if (hand) need = true;
+    }
+}
+
+// Level-parallel layered / flooding BP on handed-over frames (see
+// cbp_level_kernel).  Flooding rows only read the previous sweep's posterior
+// and add to per-variable sums in row order, which the levels keep.
+template <bool kFlood, bool kMin>
+__global__ __launch_bounds__(kWave) void bp_level_kernel(SparseDev g, const float *__restrict__ llr,
+                                                         uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                         int max_iter, Params p, Handoff h) {
+    const float us = kMin ? 1.0f : kLog2e;
+    p.a *= us;
+    p.lmax *= us;
+    uint32_t k;
+    while (next_item(h, k)) {
+        const BpState st = bp_item(g, h, k);
+        const int2 it = item_head(h, k);
+        const int64_t f = it.x;
+        int t = it.y;
+        for (;;) {
+            ++t;
+            if (kFlood) {
+                for (int v = tid_x(); v < g.N; v += kWave) st.Acc[v] = 0.0f;
+                __syncthreads();
+            }
+            for (int l = 0; l < g.nlev; ++l) {
+                const int r1 = ldc(g.lvl_ptr, l + 1);
+                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kWave)
+                    bp_row<kFlood, kMin, 1>(g, ldc(g.lvl_rows, r), st, 0, p);
+                __syncthreads();
+            }
+            for (int v = tid_x(); v < g.N; v += kWave) {
+                if (kFlood) st.Lam[v] = flood_posterior(llr[f * g.N + v], us, st.Acc[v]);
+                st.xb[v] = st.Lam[v] < 0.0f;
+            }
+            __syncthreads();
+            const bool stop = t >= max_iter || (p.stop_rule == 0 && wave_syndrome_ok(g, st.xb));
+            if (stop) {
+                for (int v = tid_x(); v < g.N; v += kWave) bits[f * g.N + v] = st.xb[v];
+                if (tid_x() == 0) iters[f] = t;
+                break;
             }
         }
     }
@@ -481,6 +759,12 @@ static int64_t sparse_block_bytes(int algo, const SparseDev &g) {
     return 2 * arr(g.N, 4) + arr(g.E, 4) + arr(g.N, 1);
 }
 
+int64_t sparse_item_bytes(int algo, const SparseDev &g) {
+    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m4 = round256(4 * (int64_t)g.M);
+    if (algo == kCBP || algo == kCBPNMS) return 2 * n4 + e4 + 2 * m4 + round256(g.N);
+    return 2 * n4 + e4 + round256(g.N);
+}
+
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames) {
     return (size_t)(round_up(frames, kWave) / kWave * sparse_block_bytes(algo, g));
 }
@@ -514,30 +798,44 @@ SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *bas
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
                          const SparseWs &ws, const Dump &d, unsigned long long *counter,
-                         hipStream_t s) {
-    // one lane per state slot; the frame counter starts at zero
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kFillBlock), 0, s, (int *)counter, 2, 0);
+                         const Handoff &h, hipStream_t s) {
+    // one lane per state slot; the frame counter, hand-off count and claim start at zero
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kFillBlock), 0, s, (int *)counter, 4, 0);
     const dim3 grid((unsigned)ws.waves), block(kWave);
     if (algo == kCBP)
         hipLaunchKernelGGL(cbp_sparse_kernel<false>, grid, block, 0, s, g, llr, bits, iters, nf,
-                           max_iter, p, ws, d, counter);
+                           max_iter, p, ws, d, counter, h);
     else if (algo == kCBPNMS)
         hipLaunchKernelGGL(cbp_sparse_kernel<true>, grid, block, 0, s, g, llr, bits, iters, nf,
-                           max_iter, p, ws, d, counter);
+                           max_iter, p, ws, d, counter, h);
     else if (algo == kLBPNMS)
         hipLaunchKernelGGL((bp_sparse_kernel<false, true>), grid, block, 0, s, g, llr, bits, iters,
-                           nf, max_iter, p, ws, d, counter);
+                           nf, max_iter, p, ws, d, counter, h);
     else if (algo == kFBPNMS)
         hipLaunchKernelGGL((bp_sparse_kernel<true, true>), grid, block, 0, s, g, llr, bits, iters,
-                           nf, max_iter, p, ws, d, counter);
+                           nf, max_iter, p, ws, d, counter, h);
     else if (algo == kLBP)
         hipLaunchKernelGGL((bp_sparse_kernel<false, false>), grid, block, 0, s, g, llr, bits, iters,
-                           nf, max_iter, p, ws, d, counter);
+                           nf, max_iter, p, ws, d, counter, h);
     else if (algo == kFBP)
         hipLaunchKernelGGL((bp_sparse_kernel<true, false>), grid, block, 0, s, g, llr, bits, iters,
-                           nf, max_iter, p, ws, d, counter);
+                           nf, max_iter, p, ws, d, counter, h);
     else
         return hipErrorInvalidValue;
+    if (h.lanes <= 0) return hipGetLastError();
+    const dim3 lgrid((unsigned)h.waves);
+    if (algo == kCBP)
+        hipLaunchKernelGGL(cbp_level_kernel<false>, lgrid, block, 0, s, g, bits, iters, max_iter, p, h);
+    else if (algo == kCBPNMS)
+        hipLaunchKernelGGL(cbp_level_kernel<true>, lgrid, block, 0, s, g, bits, iters, max_iter, p, h);
+    else if (algo == kLBPNMS)
+        hipLaunchKernelGGL((bp_level_kernel<false, true>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+    else if (algo == kFBPNMS)
+        hipLaunchKernelGGL((bp_level_kernel<true, true>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+    else if (algo == kLBP)
+        hipLaunchKernelGGL((bp_level_kernel<false, false>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+    else
+        hipLaunchKernelGGL((bp_level_kernel<true, false>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 """The C ABI without a GPU: the library loads, exports what include/cbp.h
 declares, and its host-side validation returns the documented errors."""
+import contextlib
 import ctypes
+import os
 import re
 from pathlib import Path
 
@@ -129,6 +131,45 @@ def test_decode_argument_errors_without_gpu(L):
     assert L.cbp_syndrome(None, None, None, 3, None) == cbp.CBP_EINVAL
 
 
+@contextlib.contextmanager
+def env(**kw):
+    old = {k: os.environ.get(k) for k in kw}
+    os.environ.update(kw)
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("name", ["reg36_n96", "qc2304", "qc26112", "peg_reg36_n2048", "peg_irr_n8192"])
+def test_row_levels(L, name):
+    """Row levels: a permutation of the rows; rows of one level share no variable; rows with a
+    common variable keep their index order; each row sits one level above the highest earlier
+    row it shares a variable with (checked from the columns' row lists)."""
+    code = get_code(name)
+    nlev, ptr, rows = cbp.Code.from_workload(code).levels()
+    assert ptr[0] == 0 and ptr[-1] == code.M and (np.diff(ptr) > 0).all()
+    assert np.array_equal(np.sort(rows), np.arange(code.M))
+    level = np.empty(code.M, np.int64)
+    for l in range(nlev):
+        rl = rows[ptr[l]:ptr[l + 1]]
+        assert (np.diff(rl) > 0).all()
+        level[rl] = l
+        cols = np.concatenate([code.col_idx[code.row_ptr[i]:code.row_ptr[i + 1]] for i in rl])
+        assert len(np.unique(cols)) == len(cols), f"level {l} has rows sharing a variable"
+    col_rows = [[] for _ in range(code.N)]
+    for i in range(code.M):
+        for v in code.col_idx[code.row_ptr[i]:code.row_ptr[i + 1]]:
+            col_rows[v].append(i)
+    for i in range(code.M):
+        earlier = {k for v in code.col_idx[code.row_ptr[i]:code.row_ptr[i + 1]] for k in col_rows[v] if k < i}
+        assert level[i] == (1 + max(level[k] for k in earlier) if earlier else 0)
+
+
 def test_workspace_sizes(L):
     c = cbp.Code.from_workload(get_code("reg36_n96"))
     n = cbp.workspace_size(c, "cbp", 2000)
@@ -148,10 +189,20 @@ def test_workspace_sizes(L):
 def test_log_tanh_baselines_run_on_the_sparse_kernel(L):
     c = cbp.Code.from_workload(get_code("reg36_n96"))
     S = 2048
+    # hand-off items: (frame, sweeps) and one contiguous frame state per slot
+    r256 = lambda x: (x + 255) // 256 * 256
+    item = 2 * r256(4 * 96) + r256(4 * 288) + r256(96)
     for dec in ("lbp", "fbp", "lbp_nms"):
         # Lambda, R, flooding accumulator, decisions, each frame-interleaved
         n = cbp.workspace_size(c, dec, 2000)
+        lo = (2 * 96 + 288) * 4 * S + 96 * S + 256 + r256(8 * S) + S * item
+        assert lo <= n <= lo + 9 * 256
+    with env(CBP_SPARSE_HANDOFF="0"):   # no hand-off: header and lane blocks only
+        n = cbp.workspace_size(c, "lbp", 2000)
         assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 9 * 256
+    # options the level-parallel kernel does not serve reserve no items
+    assert cbp.workspace_size(c, "cbp", 2000, stop_rule=1) < cbp.workspace_size(c, "cbp", 2000)
+    assert cbp.workspace_size(c, "cbp", 2000, hd_mode=1) < cbp.workspace_size(c, "cbp", 2000)
     q = cbp.Code.from_workload(get_code("qc2304"))
     # a QC code: auto picks the sparse kernel for lbp/fbp (a large frame-interleaved workspace)
     assert cbp.workspace_size(q, "lbp", 4096) > 4096 * (2304 + 6912) * 4
