@@ -402,11 +402,14 @@ constexpr size_t kSparseCounterBytes = 256;  // frame counter, hand-off counters
 // kernel.  CBP_SPARSE_HANDOFF in the environment overrides it (0 = never,
 // 64 = as soon as the batch is exhausted).  Items take at most
 // kHandoffMaxBytes (CBP_SPARSE_HANDOFF_ITEMS can lower their number; frames
-// beyond it finish on their lanes); the level-parallel launch has at most
-// kHandoffWaves waves.
+// beyond it finish on their lanes).
 constexpr int kHandoffLanes = 16;
 constexpr int64_t kHandoffMaxBytes = (int64_t)8 << 30;
-constexpr int kHandoffWaves = 8192;
+// Workgroups of the level-parallel launch: at most kHandoffGroups, and few
+// enough that the frames in flight fit in kLevelResident bytes (their rows
+// touch scattered words of the frame state, which then stay in cache).
+constexpr int64_t kHandoffGroups = 2048;
+constexpr int64_t kLevelResident = (int64_t)192 << 20;
 
 // A non-negative integer from the environment, else `def`.
 int64_t env_count(const char *name, int64_t def) {
@@ -586,9 +589,9 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
         if (sp.cap > 0 && hl > 0 && max_iter > 1) {
             h.lanes = hl;
             h.cap = sp.cap;
-            h.waves = (int)std::min<int64_t>(sp.cap, kHandoffWaves);
+            h.groups = (int)std::min<int64_t>(
+                {(int64_t)sp.cap, kHandoffGroups, std::max<int64_t>(64, kLevelResident / sp.item_bytes)});
             h.count = (unsigned int *)((char *)ws + 8);
-            h.claim = (unsigned int *)((char *)ws + 12);
             h.items = (int2 *)((char *)ws + sp.items_off);
             h.state = (char *)ws + sp.state_off;
             h.item_bytes = sp.item_bytes;

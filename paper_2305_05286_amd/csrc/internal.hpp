@@ -83,17 +83,16 @@ struct SparseWs {
 __host__ __device__ inline int64_t round256(int64_t x) { return (x + 255) / 256 * 256; }
 
 // Hand-off of slow frames from the one-frame-per-lane kernels to a
-// level-parallel kernel (one frame per wave, the rows of each level on
-// separate lanes).  An item holds one frame's state contiguously: CBP Q, PQ
+// level-parallel kernel (one frame per workgroup, the rows of each level on
+// separate threads).  An item holds one frame's state contiguously: CBP Q, PQ
 // [N], R [E], OmM, OmS [M], decisions [N]; BP Lambda [N], R [E], sums [N],
 // decisions [N]; each array 256-byte aligned.
 struct Handoff {
     int lanes;            // a wave hands over once the batch is exhausted and at most
                           // this many of its lanes are busy (0 = never)
     uint32_t cap;         // items
-    int waves;            // waves of the level-parallel launch
+    int groups;           // workgroups of the level-parallel launch (one frame each at a time)
     unsigned int *count;  // frames handed over (any beyond cap stay on their lanes)
-    unsigned int *claim;  // items taken by the level-parallel launch
     int2 *items;          // [cap] (frame, sweeps done)
     char *state;          // [cap] frame states, item_bytes apart
     int64_t item_bytes;
@@ -103,8 +102,8 @@ int64_t sparse_item_bytes(int algo, const SparseDev &g);
 size_t sparse_ws_bytes(int algo, const SparseDev &g, int64_t frames);
 SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *base);
 // Persistent sparse launch: one wave per block of `ws`, lanes take frames
-// 0 .. nf-1 from `counter` (16 bytes: the frame counter, then h.count and
-// h.claim; reset by the launch).  With h.lanes > 0 a level-parallel launch
+// 0 .. nf-1 from `counter` (16 bytes: the frame counter, then h.count;
+// reset by the launch).  With h.lanes > 0 a level-parallel launch
 // over the handed-over frames follows on the same stream.
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
                          int32_t *iters, int64_t nf, int max_iter, const Params &p,

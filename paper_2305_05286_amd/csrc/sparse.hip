@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kChunk = 8;  // edges of a row whose loads are issued together
+constexpr int kLevelThreads = 256;  // threads per frame in the level-parallel kernels
 constexpr int kSyndromeBlock = 256;
 constexpr int kFillBlock = 256;
 
@@ -299,10 +300,9 @@ __device__ __forceinline__ bool handing_off(const Handoff &h, unsigned long long
     if (bm == 0 || __builtin_popcountll(bm) > h.lanes) return false;
     const unsigned long long taken = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (__builtin_amdgcn_readfirstlane((int)(taken < (unsigned long long)nf))) return false;
-    if (busy) {
-        hk = atomicAdd(h.count, 1u);
-        hand = hk < h.cap;
-    }
+    // every active lane executes the atomic (lanes that are not busy add 0)
+    hk = atomicAdd(h.count, busy ? 1u : 0u);
+    hand = busy && hk < h.cap;
     return __ballot(hand) != 0;
 }
 
@@ -409,12 +409,15 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     }
 }
 
-// Syndrome of one contiguous frame, rows spread over the wave's lanes.
+// Syndrome of one contiguous frame, rows spread over the workgroup's threads.
 // A row's column entries in chunks of kChunk, read unconditionally (padded
-// table) so that the loads of a chunk go out together.
-__device__ bool wave_syndrome_ok(const SparseDev &g, const uint8_t *xb) {
+// table) so that the loads of a chunk go out together.  The result is
+// workgroup-uniform.  Every thread clears and sets the LDS flag (no branch):
+// a branch taken by some threads inside the sweep loop lets the compiler split
+// that loop by lanes, and a split wave would meet the barriers out of step.
+__device__ bool block_syndrome_ok(const SparseDev &g, const uint8_t *xb, int *s_flag) {
     uint32_t bad = 0;
-    for (int i = tid_x(); i < g.M; i += kWave) {
+    for (int i = tid_x(); i < g.M; i += kLevelThreads) {
         uint32_t par = 0;
         const int e1 = ldc(g.row_ptr, i + 1);
         for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
@@ -427,21 +430,21 @@ __device__ bool wave_syndrome_ok(const SparseDev &g, const uint8_t *xb) {
         }
         bad |= par;
     }
-    return __ballot(bad != 0) == 0;
+    *s_flag = 0;
+    __syncthreads();
+    atomicOr(s_flag, (int)(bad != 0));
+    __syncthreads();
+    const int any = __builtin_amdgcn_readfirstlane(*s_flag);
+    __syncthreads();  // every thread has read the flag before it is cleared again
+    return any == 0;
 }
 
-// The next item for this wave, or false once none is left.  Every active lane
-// executes the atomic (the first adds 1, the others 0) rather than one lane
-// inside a branch, and the item index and count are read into wave-uniform
-// registers: with a per-lane claim inside a branch and a loop bound loaded
-// per lane, the compiler may split the loop by lanes, and the lanes left
-// behind would read a stale index.
-__device__ __forceinline__ bool next_item(const Handoff &h, uint32_t &k) {
-    const int leader = __builtin_ctzll(__ballot(1));
-    const uint32_t v = atomicAdd(h.claim, tid_x() == leader ? 1u : 0u);
-    k = (uint32_t)__builtin_amdgcn_readlane((int)v, leader);
-    const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)*h.count);
-    return k < (n < h.cap ? n : h.cap);
+// Items handed over, wave-uniform.  Workgroup g takes items g, g + G, ... (no
+// claim: a counter read back by one thread would need a branch in the item
+// loop, see block_syndrome_ok).
+__device__ __forceinline__ uint32_t item_count(const Handoff &h) {
+    const uint32_t n = *h.count;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(n < h.cap ? n : h.cap));
 }
 
 // Item k's (frame, sweeps done), wave-uniform.
@@ -450,19 +453,22 @@ __device__ __forceinline__ int2 item_head(const Handoff &h, uint32_t k) {
     return make_int2(__builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y));
 }
 
-// Level-parallel CBP on handed-over frames, one frame per wave: each sweep
-// runs the row levels in order, the rows of a level on separate lanes (rows
-// of a level share no variable, so every row sees exactly the state the
+// Level-parallel CBP on handed-over frames, one frame per workgroup: each
+// sweep runs the row levels in order, the rows of a level on separate threads
+// (rows of a level share no variable, so every row sees exactly the state the
 // sequential schedule gives it and the result is the same bit for bit).
 template <bool kMin>
-__global__ __launch_bounds__(kWave) void cbp_level_kernel(SparseDev g, uint8_t *__restrict__ bits,
-                                                          int32_t *__restrict__ iters, int max_iter, Params p,
-                                                          Handoff h) {
+__global__ __launch_bounds__(kLevelThreads) void cbp_level_kernel(SparseDev g, uint8_t *__restrict__ bits,
+                                                                  int32_t *__restrict__ iters, int max_iter,
+                                                                  Params p, Handoff h) {
+    __shared__ int s_flag;
     const float us = kMin ? 1.0f : kLog2e;
     p.a *= us;
     p.lmax *= us;
-    uint32_t k;
-    while (next_item(h, k)) {
+    const uint32_t n = item_count(h);
+    for (uint32_t j = 0;; ++j) {
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)(gid_x() + j * gridDim.x));
+        if (k >= n) break;
         const CbpState st = cbp_item(g, h, k);
         const int2 it = item_head(h, k);
         const int64_t f = it.x;
@@ -471,16 +477,16 @@ __global__ __launch_bounds__(kWave) void cbp_level_kernel(SparseDev g, uint8_t *
             ++t;
             for (int l = 0; l < g.nlev; ++l) {
                 const int r1 = ldc(g.lvl_ptr, l + 1);
-                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kWave) {
+                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kLevelThreads) {
                     bool flip = false;
                     (void)cbp_row<kMin, 1>(g, ldc(g.lvl_rows, r), false, st, 0, p, flip);
                 }
                 __syncthreads();
             }
-            const bool stop = t >= max_iter || (p.stop_rule == 0 && wave_syndrome_ok(g, st.xb));
+            const bool stop = t >= max_iter || (p.stop_rule == 0 && block_syndrome_ok(g, st.xb, &s_flag));
             if (stop) {
-                for (int v = tid_x(); v < g.N; v += kWave) bits[f * g.N + v] = st.xb[v];
-                if (tid_x() == 0) iters[f] = t;
+                for (int v = tid_x(); v < g.N; v += kLevelThreads) bits[f * g.N + v] = st.xb[v];
+                iters[f] = t;  // every thread, the same value
                 break;
             }
         }
@@ -677,14 +683,18 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
 // cbp_level_kernel).  Flooding rows only read the previous sweep's posterior
 // and add to per-variable sums in row order, which the levels keep.
 template <bool kFlood, bool kMin>
-__global__ __launch_bounds__(kWave) void bp_level_kernel(SparseDev g, const float *__restrict__ llr,
-                                                         uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
-                                                         int max_iter, Params p, Handoff h) {
+__global__ __launch_bounds__(kLevelThreads) void bp_level_kernel(SparseDev g, const float *__restrict__ llr,
+                                                                 uint8_t *__restrict__ bits,
+                                                                 int32_t *__restrict__ iters, int max_iter,
+                                                                 Params p, Handoff h) {
+    __shared__ int s_flag;
     const float us = kMin ? 1.0f : kLog2e;
     p.a *= us;
     p.lmax *= us;
-    uint32_t k;
-    while (next_item(h, k)) {
+    const uint32_t n = item_count(h);
+    for (uint32_t j = 0;; ++j) {
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)(gid_x() + j * gridDim.x));
+        if (k >= n) break;
         const BpState st = bp_item(g, h, k);
         const int2 it = item_head(h, k);
         const int64_t f = it.x;
@@ -692,24 +702,24 @@ __global__ __launch_bounds__(kWave) void bp_level_kernel(SparseDev g, const floa
         for (;;) {
             ++t;
             if (kFlood) {
-                for (int v = tid_x(); v < g.N; v += kWave) st.Acc[v] = 0.0f;
+                for (int v = tid_x(); v < g.N; v += kLevelThreads) st.Acc[v] = 0.0f;
                 __syncthreads();
             }
             for (int l = 0; l < g.nlev; ++l) {
                 const int r1 = ldc(g.lvl_ptr, l + 1);
-                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kWave)
+                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kLevelThreads)
                     bp_row<kFlood, kMin, 1>(g, ldc(g.lvl_rows, r), st, 0, p);
                 __syncthreads();
             }
-            for (int v = tid_x(); v < g.N; v += kWave) {
+            for (int v = tid_x(); v < g.N; v += kLevelThreads) {
                 if (kFlood) st.Lam[v] = flood_posterior(llr[f * g.N + v], us, st.Acc[v]);
                 st.xb[v] = st.Lam[v] < 0.0f;
             }
             __syncthreads();
-            const bool stop = t >= max_iter || (p.stop_rule == 0 && wave_syndrome_ok(g, st.xb));
+            const bool stop = t >= max_iter || (p.stop_rule == 0 && block_syndrome_ok(g, st.xb, &s_flag));
             if (stop) {
-                for (int v = tid_x(); v < g.N; v += kWave) bits[f * g.N + v] = st.xb[v];
-                if (tid_x() == 0) iters[f] = t;
+                for (int v = tid_x(); v < g.N; v += kLevelThreads) bits[f * g.N + v] = st.xb[v];
+                iters[f] = t;  // every thread, the same value
                 break;
             }
         }
@@ -799,7 +809,7 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
                          const SparseWs &ws, const Dump &d, unsigned long long *counter,
                          const Handoff &h, hipStream_t s) {
-    // one lane per state slot; the frame counter, hand-off count and claim start at zero
+    // one lane per state slot; the frame counter and the hand-off count start at zero
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kFillBlock), 0, s, (int *)counter, 4, 0);
     const dim3 grid((unsigned)ws.waves), block(kWave);
     if (algo == kCBP)
@@ -823,19 +833,19 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
     else
         return hipErrorInvalidValue;
     if (h.lanes <= 0) return hipGetLastError();
-    const dim3 lgrid((unsigned)h.waves);
+    const dim3 lgrid((unsigned)h.groups), lblock(kLevelThreads);
     if (algo == kCBP)
-        hipLaunchKernelGGL(cbp_level_kernel<false>, lgrid, block, 0, s, g, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL(cbp_level_kernel<false>, lgrid, lblock, 0, s, g, bits, iters, max_iter, p, h);
     else if (algo == kCBPNMS)
-        hipLaunchKernelGGL(cbp_level_kernel<true>, lgrid, block, 0, s, g, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL(cbp_level_kernel<true>, lgrid, lblock, 0, s, g, bits, iters, max_iter, p, h);
     else if (algo == kLBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<false, true>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL((bp_level_kernel<false, true>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     else if (algo == kFBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<true, true>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL((bp_level_kernel<true, true>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     else if (algo == kLBP)
-        hipLaunchKernelGGL((bp_level_kernel<false, false>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL((bp_level_kernel<false, false>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     else
-        hipLaunchKernelGGL((bp_level_kernel<true, false>), lgrid, block, 0, s, g, llr, bits, iters, max_iter, p, h);
+        hipLaunchKernelGGL((bp_level_kernel<true, false>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     return hipGetLastError();
 }
 
