@@ -1,7 +1,7 @@
 """The device approximation of the check-rule transform (csrc/phi.hpp), checked on the host.
 
 The kernels evaluate g(x) = phi(x ln2) / ln2 with phi(x) = -ln tanh(x/2) (Sec. II-A,
-eq. equ_s2e5) from two degree-4 polynomials and one hardware log2 / exp2.  This test reads
+eq. equ_s2e5) from two degree-3 polynomials and one hardware log2 / exp2.  This test reads
 the coefficients out of the header, evaluates the same float32 operation sequence in numpy
 (FMA emulated in float64 and rounded once) and compares with the closed form in float64.
 """
@@ -20,8 +20,8 @@ def _coefficients():
     body = src[src.index("float phi2(float x)"):]
     body = body[:body.index("\n}\n")]
     nums = [float(m) for m in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
-    # p = c4; p = fma(p, uu, c3) ... c0 ; then u = d4; u = fma(u, s, d3) ... d0
-    small, large = nums[:5], nums[5:10]
+    # p = c3; p = fma(p, uu, c2) ... c0 ; then u = d3; u = fma(u, s, d2) ... d0
+    small, large = nums[:4], nums[4:8]
     return [f32(c) for c in small], [f32(c) for c in large]
 
 
@@ -52,7 +52,7 @@ def phi2_exact(x):
 
 def test_coefficients_parsed():
     small_c, large_c = _coefficients()
-    assert len(small_c) == 5 and len(large_c) == 5
+    assert len(small_c) == 4 and len(large_c) == 4
     # leading terms of the two expansions: tanh(ln2 sqrt(u)/2)/sqrt(u) -> ln2/2, and
     # (2/ln2) atanh(sqrt s)/sqrt s -> 2/ln2
     assert abs(small_c[-1] - LN2 / 2) < 1e-6
@@ -63,7 +63,7 @@ def test_relative_error_bound():
     xs = np.concatenate([np.geomspace(5e-9, 60.0, 4000), np.linspace(1.40, 1.48, 400)])
     xs = xs.astype(np.float32)  # compare at the float32 input the kernel sees
     err = max(abs(float(phi2_emulated(x)) - phi2_exact(x)) / phi2_exact(x) for x in xs)
-    assert err < 3e-7, err
+    assert err < 1e-6, err
 
 
 def test_self_inverse():
@@ -77,4 +77,5 @@ def test_self_inverse():
 def test_split_is_continuous():
     lo = phi2_emulated(np.nextafter(f32(1.4426950408889634), f32(0)))
     hi = phi2_emulated(f32(1.4426950408889634))
-    assert abs(float(lo) - float(hi)) / float(hi) < 1e-6
+    # each side is within the 1e-6 bound of the closed form, so they differ by under 2e-6
+    assert abs(float(lo) - float(hi)) / float(hi) < 2e-6
