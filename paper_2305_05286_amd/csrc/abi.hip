@@ -231,7 +231,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             qt.resize(q_sc + (sizeof(StreamCode) + 3) / 4, 0);  // filled once the device address is known
         }
         const size_t P = kSparseTablePad;  // padding of col_idx, pred_edge, pred_row, first
-        const size_t lvl_ints = (size_t)c->nlev + 1 + (size_t)M;
+        // level pointers, then (16-byte aligned) one int4 per row in level order
+        const size_t lvl_pad = (4 - ((size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() +
+                                     (size_t)c->nlev + 1) % 4) % 4;
+        const size_t lvl_ints = (size_t)c->nlev + 1 + lvl_pad + 4 * (size_t)M;
         const size_t ints =
             (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() + lvl_ints;
         const size_t bytes = ints * 4 + (size_t)E + P + 64;
@@ -275,8 +278,14 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         if (!qt.empty()) std::memcpy(p, qt.data(), 4 * qt.size());
         p += qt.size();
         std::memcpy(p, c->lvl_ptr.data(), 4 * ((size_t)c->nlev + 1));
-        p += c->nlev + 1;
-        std::memcpy(p, c->lvl_rows.data(), 4 * (size_t)M);
+        p += c->nlev + 1 + lvl_pad;
+        for (int k = 0; k < M; ++k) {
+            const int i = c->lvl_rows[k];
+            p[4 * k] = i;
+            p[4 * k + 1] = c->row_ptr[i];
+            p[4 * k + 2] = c->row_ptr[i + 1];
+            p[4 * k + 3] = 0;
+        }
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) {
             std::vector<uint8_t> fp(c->first);
@@ -308,8 +317,8 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         d += qt.size();
         t.g.nlev = c->nlev;
         t.g.lvl_ptr = d;
-        d += c->nlev + 1;
-        t.g.lvl_rows = d;
+        d += c->nlev + 1 + lvl_pad;
+        t.g.lvl_rows = reinterpret_cast<const int4 *>(d);
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;

@@ -60,7 +60,7 @@ struct SparseDev {
     const int *last_edge; // [N]  edge of the highest row of each column
     int nlev;             // row levels (rows of one level share no variable)
     const int *lvl_ptr;   // [nlev+1] first entry of each level in lvl_rows
-    const int *lvl_rows;  // [M] rows by (level, index)
+    const int4 *lvl_rows; // [M] (row, first edge, end edge, 0) by (level, index)
 };
 
 // col_idx, pred_edge, pred_row and first are readable (zeros) for this many

@@ -130,6 +130,12 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, uint32_t 
     return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
 }
 
+// Entry r of the level-ordered row table: (row, first edge, end edge, 0).
+__device__ __forceinline__ int4 level_row(const SparseDev &g, int r) {
+    const int *q = reinterpret_cast<const int *>(g.lvl_rows) + 4 * (int64_t)r;
+    return make_int4(ldc(q, 0), ldc(q, 1), ldc(q, 2), 0);
+}
+
 // Element idx of a state array whose frames are kStride apart: kStride = 64
 // for lane lf of a wave's frame-interleaved block, 1 (lf = 0) for one frame's
 // contiguous copy.
@@ -144,24 +150,23 @@ struct CbpState {
 };
 
 // One check-node update of CBP on one frame: Step 2(1) a-e for each edge of
-// row i in ascending column order, then Step 2(2).  Returns the sign parity of
+// row i (edges e0 .. e1-1) in ascending column order, then Step 2(2).  Returns the sign parity of
 // the new belief; with stop_rule 1 ors into flip whether a decision changed.
 // sweep1: first sweep, where a first-visit edge has no latest check yet.
 template <bool kMin, int kStride>
-__device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, bool sweep1, const CbpState &st, uint32_t lf,
-                                        const Params &p, bool &flip) {
+__device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, int e0, int e1, bool sweep1, const CbpState &st,
+                                        uint32_t lf, const Params &p, bool &flip) {
     float *Q = st.Q, *PQ = st.PQ, *R = st.R;
     uint8_t *xb = st.xb;
     float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
     bool par = false;
-    const int e1 = ldc(g.row_ptr, i + 1);
     // The row's edges in chunks of kChunk: every load of a chunk is issued
     // before its first store, so a chunk costs one memory round trip instead
     // of one per edge.  Within a row the columns differ, so no load of a chunk
     // reads what an earlier edge of the same chunk stores, except R(c_i -> v)
     // when v's latest check is c_i itself (a column of weight one): that
     // commit is forwarded in registers.
-    for (int c0 = ldc(g.row_ptr, i); c0 < e1; c0 += kChunk) {
+    for (int c0 = e0; c0 < e1; c0 += kChunk) {
         const int n = e1 - c0 < kChunk ? e1 - c0 : kChunk;
         // the chunk's table entries, unconditionally (padded tables)
         int col[kChunk], pe[kChunk], pr[kChunk];
@@ -362,7 +367,8 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
             int istop = 0;
             for (int i = 0; i < g.M; ++i) {
                 bool flip = false;
-                const bool par = cbp_row<kMin, kWave>(g, i, t == 1, st, lf, p, flip);
+                const bool par = cbp_row<kMin, kWave>(g, i, ldc(g.row_ptr, i), ldc(g.row_ptr, i + 1), t == 1, st, lf,
+                                                      p, flip);
                 if (p.stop_rule == 1) {  // Step 2(3): M updates in a row with Omega > 0, no flip
                     run = (!par && !flip) ? run + 1 : 0;
                     if (run >= g.M) {
@@ -479,7 +485,8 @@ __global__ __launch_bounds__(kLevelThreads) void cbp_level_kernel(SparseDev g, u
                 const int r1 = ldc(g.lvl_ptr, l + 1);
                 for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kLevelThreads) {
                     bool flip = false;
-                    (void)cbp_row<kMin, 1>(g, ldc(g.lvl_rows, r), false, st, 0, p, flip);
+                    const int4 rr = level_row(g, r);
+                    (void)cbp_row<kMin, 1>(g, rr.x, rr.y, rr.z, false, st, 0, p, flip);
                 }
                 __syncthreads();
             }
@@ -506,11 +513,11 @@ struct BpState {
     uint8_t *xb;
 };
 
-// One row of the layered (kFlood false) or flooding schedule on one frame.
+// One row (edges e0 .. e1-1) of the layered (kFlood false) or flooding schedule on one frame.
 template <bool kFlood, bool kMin, int kStride>
-__device__ __forceinline__ void bp_row(const SparseDev &g, int i, const BpState &st, uint32_t lf, const Params &p) {
+__device__ __forceinline__ void bp_row(int e0, int e1, const SparseDev &g, const BpState &st, uint32_t lf,
+                                       const Params &p) {
     float *Lam = st.Lam, *R = st.R, *Acc = st.Acc;
-    const int e0 = ldc(g.row_ptr, i), e1 = ldc(g.row_ptr, i + 1);
     // min-sum: (m1, m2) = two smallest |Q|; log-tanh: (m1, m2) = (max, rest) of g(|Q|)
     float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
     bool par = false;
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
             ++t;
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) Acc[at(v, lf)] = 0.0f;
-            for (int i = 0; i < g.M; ++i) bp_row<kFlood, kMin, kWave>(g, i, st, lf, p);
+            for (int i = 0; i < g.M; ++i) bp_row<kFlood, kMin, kWave>(ldc(g.row_ptr, i), ldc(g.row_ptr, i + 1), g, st, lf, p);
             if (kFlood)
                 for (int v = 0; v < g.N; ++v) {
                     const uint32_t iv = at(v, lf);
@@ -707,8 +714,10 @@ __global__ __launch_bounds__(kLevelThreads) void bp_level_kernel(SparseDev g, co
             }
             for (int l = 0; l < g.nlev; ++l) {
                 const int r1 = ldc(g.lvl_ptr, l + 1);
-                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kLevelThreads)
-                    bp_row<kFlood, kMin, 1>(g, ldc(g.lvl_rows, r), st, 0, p);
+                for (int r = ldc(g.lvl_ptr, l) + tid_x(); r < r1; r += kLevelThreads) {
+                    const int4 rr = level_row(g, r);
+                    bp_row<kFlood, kMin, 1>(rr.y, rr.z, g, st, 0, p);
+                }
                 __syncthreads();
             }
             for (int v = tid_x(); v < g.N; v += kLevelThreads) {
