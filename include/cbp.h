@@ -85,7 +85,7 @@ int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int
 /* Sparse kernel, slow frames: once every frame of the batch has been taken, a
  * wave with at most 16 busy lanes (CBP_SPARSE_HANDOFF in the environment:
  * 0 = never, 1..64) copies their frames into the workspace and a second launch
- * finishes them one frame per wave, running each sweep level by level (see
+ * finishes them one frame per workgroup, running each sweep level by level (see
  * cbp_code_levels) with the rows of a level on separate lanes.  Results are
  * bit-identical to finishing them on their lanes.  Not used with stop_rule 1,
  * hd_mode 1 or state dumps.  CBP_SPARSE_HANDOFF_ITEMS (> 0) caps the frames
