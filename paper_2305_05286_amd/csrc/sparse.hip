@@ -644,6 +644,7 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
                         const float l = llr[f * g.N + v] * us;
                         Lam[at(v, lf)] = l;
                         xb[at(v, lf)] = l < 0.0f;
+                        if (kFlood) Acc[at(v, lf)] = 0.0f;
                     }
                     for (int e = 0; e < g.E; ++e) R[at(e, lf)] = 0.0f;
                     t = 0;
@@ -659,15 +660,20 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
         uint32_t hk = 0;
         if (!done) {
             ++t;
-            if (kFlood)
-                for (int v = 0; v < g.N; ++v) Acc[at(v, lf)] = 0.0f;
             for (int i = 0; i < g.M; ++i) bp_row<kFlood, kMin, kWave>(ldc(g.row_ptr, i), ldc(g.row_ptr, i + 1), g, st, lf, p);
-            if (kFlood)
+            // flooding: posterior and decision of every variable, and its C2V sum
+            // cleared for the next sweep, in one pass
+            if (kFlood) {
                 for (int v = 0; v < g.N; ++v) {
                     const uint32_t iv = at(v, lf);
-                    Lam[iv] = flood_posterior(llr[f * g.N + v], us, Acc[iv]);
+                    const float lm = flood_posterior(llr[f * g.N + v], us, Acc[iv]);
+                    Lam[iv] = lm;
+                    xb[iv] = lm < 0.0f;
+                    Acc[iv] = 0.0f;
                 }
-            for (int v = 0; v < g.N; ++v) xb[at(v, lf)] = Lam[at(v, lf)] < 0.0f;
+            } else {
+                for (int v = 0; v < g.N; ++v) xb[at(v, lf)] = Lam[at(v, lf)] < 0.0f;  // eq. equ_s2e7
+            }
             if (t == d.sweep && f < d.frames) {
                 if (d.lam)
                     for (int v = 0; v < g.N; ++v) d.lam[f * g.N + v] = Lam[at(v, lf)] * un;
