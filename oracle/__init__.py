@@ -16,8 +16,11 @@ Every function follows the paper (Guan & Liang, arXiv 2305.05286):
 * ``algo="fbp"``: flooding BP, Sec. II-A.
 * ``algo="lbp_nms" | "fbp_nms"``: the same schedules with the normalized
   min-sum check rule (alpha * sign * min of the other clamped |Q|).
-* ``algo="cbp_nms"``: CBP with the min-sum B2V/C2B of Sec. IV-D
-  (parity unpinned beyond the tree and symmetry checks in the tests).
+* ``algo="cbp_nms"``: CBP with the min-sum B2V/C2B of Sec. IV-D.
+* the default decision of ``cbp`` / ``cbp_nms`` (``hd_mode=0``, Step 3: from
+  the V2C phase of each variable's last visit) and both stopping rules
+  (syndrome; Step 2(3) with ``stop_rule=1``) are pinned against a layered BP
+  trajectory recorded row by row in ``tests/test_oracle_decision_pins.py``.
 * ``unrolled``: a fixed number of CBP sweeps whose B2V outputs are scaled and
   offset by per-sweep, per-column weights (the differentiable decoder), with
   the flushed soft output.
