@@ -207,6 +207,30 @@ int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch,
                        const cbp_opts_t *opts, size_t *bytes);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the decoder
+ * selected by `decoder` (0 = cbp_decode, 1 = lbp_nms_decode, 2 = fbp_nms_decode,
+ * 3 = lbp_decode, 4 = fbp_decode; opts->check_rule picks CBP's rule as in
+ * cbp_decode) with the same arguments, options and results, allocating
+ * nothing: no hipMalloc / hipFree, stream-ordered or not.
+ *   Workspace: a static device array of 64 MiB per GPU inside the library,
+ *   held until the process ends; opts->workspace is ignored.  The persistent
+ *   kernels take no more frames in flight than fit in it (the decoded results
+ *   do not depend on that number); a code whose smallest unit of work does not
+ *   fit (one streamed workgroup's frame state, or 64 frames on the sparse
+ *   kernel) is rejected with CBP_EUNSUPPORTED, and so is a code whose device
+ *   tables have not been built on the current device: any allocating call
+ *   with that code on that device (e.g. cbp_syndrome) builds them.
+ *   Calls on one GPU share its array and keep the last call's contents (each
+ *   call resets the counters it uses): calls that overlap on one GPU, on any
+ *   streams, race and must not be issued.  opts->validate reads its result
+ *   back through the same array and synchronises `stream`, as in cbp_decode.
+ */
+int cbp_decode_static(const cbp_code_t *code, int32_t decoder, const float *llr_in,
+                     uint8_t *bits_out, int32_t *iters_out, int32_t max_iter, int64_t batch,
+                     const cbp_opts_t *opts, void *stream);
+
+/*
  * Syndrome test (the stopping test of FBP, Sec. II-A): ok_out[f] = 1 if
  * H bits[f]^T = 0 over GF(2), else 0.  bits: device uint8 [batch][N] (0/1);
  * ok_out: device uint8 [batch].

@@ -26,7 +26,7 @@ DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2, "lbp": 3, "fbp": 4}
 # exported names declared in include/cbp.h
 EXPORTS = ("cbp_code_from_csr", "cbp_code_from_qc", "cbp_code_free", "cbp_code_info", "cbp_code_levels",
            "cbp_opts_default", "cbp_decode", "lbp_nms_decode", "fbp_nms_decode",
-           "lbp_decode", "fbp_decode", "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
+           "lbp_decode", "fbp_decode", "cbp_decode_static", "cbp_workspace_size", "cbp_syndrome", "cbp_strerror", "cbp_last_error",
            "cbp_version", "cbp_mix_create", "cbp_mix_free", "cbp_mix_get_schedule",
            "cbp_mix_set_schedule", "cbp_mix_workspace_size", "cbp_mix_decode", "cbp_mix_tune",
            "cbp_mix_graph_create", "cbp_graph_launch", "cbp_graph_free",
@@ -90,6 +90,8 @@ def lib():
                 continue
             getattr(L, name).argtypes = [vp, vp, vp, vp, i32, i64, ctypes.POINTER(Opts), vp]
             getattr(L, name).restype = ctypes.c_int
+        L.cbp_decode_static.argtypes = [vp, i32, vp, vp, vp, i32, i64, ctypes.POINTER(Opts), vp]
+        L.cbp_decode_static.restype = ctypes.c_int
         L.cbp_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(Opts), ctypes.POINTER(sz)]
         L.cbp_syndrome.argtypes = [vp, vp, vp, i64, vp]
         L.cbp_strerror.argtypes = [ctypes.c_int]
@@ -208,7 +210,8 @@ def _opts(stop_rule=0, hd_mode=0, lmax=20.0, alpha=0.75, kernel="auto", dump=Non
 
 def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, lmax=20.0,
          alpha=0.75, kernel="auto", dump_sweep: int = 0, dump_frames: int = 0,
-         workspace=None, out=None, stream=None, check_rule="log_tanh", validate=False):
+         workspace=None, out=None, stream=None, check_rule="log_tanh", validate=False,
+         static=False):
     import torch
     if not (isinstance(llr, torch.Tensor) and llr.is_cuda and llr.dtype == torch.float32):
         raise TypeError("llr must be a float32 CUDA tensor")
@@ -235,11 +238,16 @@ def _run(which: str, code: Code, llr, max_iter: int, *, stop_rule=0, hd_mode=0, 
         which, check_rule = "cbp", "min_sum"
     o = _opts(stop_rule, hd_mode, lmax, alpha, kernel, dump, workspace, check_rule, validate)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
-    fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode",
-                         "fbp_nms": "fbp_nms_decode", "lbp": "lbp_decode", "fbp": "fbp_decode"}[which])
     with torch.cuda.device(dev):
-        check(fn(code.handle, llr.data_ptr(), bits.data_ptr(), iters.data_ptr(), int(max_iter),
-                 B, ctypes.byref(o), ctypes.c_void_p(s.cuda_stream)))
+        if static:
+            check(lib().cbp_decode_static(code.handle, DECODERS[which], llr.data_ptr(), bits.data_ptr(),
+                                          iters.data_ptr(), int(max_iter), B, ctypes.byref(o),
+                                          ctypes.c_void_p(s.cuda_stream)))
+        else:
+            fn = getattr(lib(), {"cbp": "cbp_decode", "lbp_nms": "lbp_nms_decode", "fbp_nms": "fbp_nms_decode",
+                                 "lbp": "lbp_decode", "fbp": "fbp_decode"}[which])
+            check(fn(code.handle, llr.data_ptr(), bits.data_ptr(), iters.data_ptr(), int(max_iter),
+                     B, ctypes.byref(o), ctypes.c_void_p(s.cuda_stream)))
     if dump is not None:
         return bits, iters, dump
     return bits, iters
@@ -276,6 +284,14 @@ def decode(code: Code, llr, max_iter: int, algo: str = "cbp", **kw):
     """algo: "cbp", "cbp_nms" (cbp_decode with the min-sum rule), "lbp_nms", "fbp_nms",
     "lbp", "fbp"."""
     return _run(algo, code, llr, max_iter, **kw)
+
+
+def decode_static(code: Code, llr, max_iter: int, algo: str = "cbp", **kw):
+    """cbp_decode_static: the decoder `algo` (as in decode) with the library's static
+    device scratch as workspace, so the call allocates nothing in the library (the output
+    tensors are allocated here unless out=(bits, iters) is given).  The code's device tables
+    must already exist on llr's device (any earlier decode or cbp_syndrome call builds them)."""
+    return _run(algo, code, llr, max_iter, static=True, **kw)
 
 
 def cbp_syndrome(code: Code, bits, stream=None):

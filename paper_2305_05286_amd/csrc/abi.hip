@@ -50,6 +50,13 @@ struct DevTables {
 
 }  // namespace
 
+// Workspace of cbp_decode_static: one copy per GPU, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (on the
+// host it names a stand-in, not device memory): it uses the device address
+// that hipGetSymbolAddress returns for the current device, kept per device.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 struct cbp_code {
     int M = 0, N = 0;
     int64_t E = 0;
@@ -152,8 +159,10 @@ int check_csr(int32_t M, int32_t N, const int32_t *row_ptr, const int32_t *col_i
 
 double phi64(double x) { return std::log1p(2.0 / std::expm1(x)); }
 
+// The code's device tables on the current device, built on first use unless
+// `build` is false (then a missing table set is an error: nothing allocated).
 int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
-                  const int **qc_sht = nullptr, const DevTables **tab = nullptr) {
+                  const int **qc_sht = nullptr, const DevTables **tab = nullptr, bool build = true) {
     cbp_code *c = const_cast<cbp_code *>(cc);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -162,6 +171,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
     *device_out = dev;
     std::lock_guard<std::mutex> lock(c->mu);
     DevTables &t = c->dev[dev];
+    if (!t.ready && !build)
+        return fail(CBP_EUNSUPPORTED,
+                    "the code's device tables are not built on device %d (any allocating call with this "
+                    "code on this device, e.g. cbp_syndrome, builds them)", dev);
     if (!t.ready) {
         const int64_t E = c->E;
         const int M = c->M, N = c->N;
@@ -485,9 +498,10 @@ int device_cus(int dev) {
     return cus;
 }
 
-SparsePlan sparse_plan(int algo, const SparseDev &g, int64_t batch, bool handoff) {
+SparsePlan sparse_plan(int algo, const SparseDev &g, int64_t batch, bool handoff, int64_t max_lanes = 0) {
     SparsePlan sp;
     sp.lanes = sparse_lanes(algo, g, batch);
+    if (max_lanes > 0) sp.lanes = std::min(sp.lanes, max_lanes);
     sp.item_bytes = sparse_item_bytes(algo, g);
     if (handoff && handoff_lanes() > 0) {
         // CBP_SPARSE_HANDOFF_ITEMS (> 0) lowers the number of items
@@ -503,6 +517,21 @@ SparsePlan sparse_plan(int algo, const SparseDev &g, int64_t batch, bool handoff
     return sp;
 }
 
+// The widest sparse plan (lanes a multiple of 64, at most the default) whose
+// workspace fits in `budget` bytes; lanes = 0 if not even one wave fits.
+SparsePlan sparse_plan_fit(int algo, const SparseDev &g, int64_t batch, bool handoff, size_t budget) {
+    SparsePlan sp = sparse_plan(algo, g, batch, handoff);
+    if (sp.total <= budget) return sp;
+    int64_t lo = 0, hi = sp.lanes / 64;  // in waves; plan(lo) fits, plan(hi) does not
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (sparse_plan(algo, g, batch, handoff, mid * 64).total <= budget) lo = mid;
+        else hi = mid;
+    }
+    if (lo == 0) return SparsePlan{};
+    return sparse_plan(algo, g, batch, handoff, lo * 64);
+}
+
 size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch,
                  bool handoff) {
     if (kernel == CBP_KERNEL_QC_REG) return 256;
@@ -515,14 +544,19 @@ size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kerne
 
 // opts.validate: scan n LLRs for NaN / +-Inf (frames of `row` values, 0 = no frame
 // structure); blocks on s.
-int validate_llr(const float *llr, int64_t n, int64_t row, hipStream_t s) {
-    unsigned long long *pos = nullptr;
-    hipError_t e = hipMallocAsync((void **)&pos, sizeof(*pos), s);
-    if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMallocAsync(8): %s", hipGetErrorString(e));
+// `fixed`: a device word to use for the result (nothing is then allocated).
+int validate_llr(const float *llr, int64_t n, int64_t row, hipStream_t s,
+                 unsigned long long *fixed = nullptr) {
+    unsigned long long *pos = fixed;
+    hipError_t e = hipSuccess;
+    if (!fixed) {
+        e = hipMallocAsync((void **)&pos, sizeof(*pos), s);
+        if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMallocAsync(8): %s", hipGetErrorString(e));
+    }
     unsigned long long h = ~0ull;
     e = launch_nonfinite_scan(llr, n, pos, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, pos, sizeof(h), hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipFreeAsync(pos, s);
+    hipError_t e2 = fixed ? hipSuccess : hipFreeAsync(pos, s);
     if (e == hipSuccess) e = e2;
     e2 = hipStreamSynchronize(s);
     if (e == hipSuccess) e = e2;
@@ -534,8 +568,17 @@ int validate_llr(const float *llr, int64_t n, int64_t row, hipStream_t s) {
     return CBP_OK;
 }
 
+// A workspace the caller of decode() fixes in advance (the static scratch of
+// cbp_decode_static): decode() then allocates nothing, builds no tables, and
+// fits the persistent kernels' frames in flight to its size.
+struct FixedWs {
+    void *base = nullptr;  // 256-byte aligned; the first 256 bytes hold the input-scan word
+    size_t bytes = 0;
+};
+
 int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, int32_t *iters,
-           int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
+           int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream,
+           const FixedWs *fixed = nullptr) {
     if (!code) return fail(CBP_EINVAL, "code is NULL");
     if (batch < 0) return fail(CBP_EINVAL, "batch < 0");
     if (max_iter < 0) return fail(CBP_EINVAL, "max_iter < 0");
@@ -549,17 +592,25 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     const SparseDev *g = nullptr;
     const int *qc_sht = nullptr;
     const DevTables *tab = nullptr;
-    rc = ensure_device(code, &dev, &g, &qc_sht, &tab);
+    rc = ensure_device(code, &dev, &g, &qc_sht, &tab, fixed == nullptr);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (opts && opts->validate) {
-        rc = validate_llr(llr, batch * (int64_t)code->N, code->N, s);
+        rc = validate_llr(llr, batch * (int64_t)code->N, code->N, s,
+                          fixed ? (unsigned long long *)fixed->base : nullptr);
         if (rc) return rc;
     }
-    const size_t need = needed_ws(algo, code, *g, r.kernel, batch, r.handoff);
+    // with a fixed workspace: the part after its first 256 bytes, and no
+    // more frames in flight than fit in it
+    size_t budget = 0;
+    if (fixed) {
+        r.ws = (char *)fixed->base + 256;
+        r.ws_bytes = budget = fixed->bytes - 256;
+    }
+    const size_t need = fixed ? 0 : needed_ws(algo, code, *g, r.kernel, batch, r.handoff);
     void *ws = r.ws;
     bool own = false;
-    if (!ws || r.ws_bytes < need) {
+    if (!fixed && (!ws || r.ws_bytes < need)) {
         hipError_t e = hipMallocAsync(&ws, need, s);
         if (e != hipSuccess) return fail(CBP_ENOMEM, "hipMallocAsync(%zu): %s", need, hipGetErrorString(e));
         own = true;
@@ -582,6 +633,13 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
                         code->Z, code->qdcmax);
         }
         L.groups = (int)std::min<int64_t>(L.groups, (int64_t)per_cu * device_cus(dev));
+        if (fixed) {
+            const int64_t fit = (int64_t)(budget - 256) / L.group_bytes;
+            if (fit < 1)
+                return fail(CBP_EUNSUPPORTED, "one workgroup's frame state (%lld bytes) exceeds the %zu-byte "
+                            "static scratch", (long long)L.group_bytes, budget);
+            L.groups = (int)std::min<int64_t>(L.groups, fit);
+        }
         e = launch_fill_i32((int *)ws, 1, 0, s);
         if (e == hipSuccess)
             e = launch_qc_stream(algo, L, llr, bits, iters, batch, nullptr, nullptr, nullptr,
@@ -591,7 +649,12 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
             if (own) (void)hipFreeAsync(ws, s);
             return fail(CBP_EUNSUPPORTED, "the sparse kernel indexes its state with 32 bits: at most 2^26 edges");
         }
-        const SparsePlan sp = sparse_plan(algo, *g, batch, r.handoff);
+        const SparsePlan sp = fixed ? sparse_plan_fit(algo, *g, batch, r.handoff, budget)
+                                    : sparse_plan(algo, *g, batch, r.handoff);
+        if (sp.lanes == 0)
+            return fail(CBP_EUNSUPPORTED, "the state of 64 frames on the sparse kernel (%lld bytes) exceeds the "
+                        "%zu-byte static scratch",
+                        (long long)sparse_plan(algo, *g, 64, r.handoff).total, budget);
         const SparseWs w = sparse_ws_carve(algo, *g, sp.lanes, (char *)ws + sp.blocks_off);
         Handoff h{};
         const int hl = handoff_lanes();
@@ -613,6 +676,27 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
         if (e == hipSuccess) e = e2;
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return CBP_OK;
+}
+
+// ---- the static scratch of cbp_decode_static -----------------------------
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// once per device.
+int static_scratch(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(CBP_EUNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+        if (!p || ((uintptr_t)p & 255)) return fail(CBP_EHIP, "static scratch at %p is not 256-byte aligned", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return CBP_OK;
 }
 
@@ -1194,6 +1278,23 @@ int lbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out, i
 int fbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out, int32_t *iters_out,
                int32_t max_iter, int64_t batch, const cbp_opts_t *opts, void *stream) {
     return decode(kFBP, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream);
+}
+
+int cbp_decode_static(const cbp_code_t *code, int32_t decoder, const float *llr_in, uint8_t *bits_out,
+                      int32_t *iters_out, int32_t max_iter, int64_t batch, const cbp_opts_t *opts,
+                      void *stream) {
+    if (decoder < 0 || decoder > 4) return fail(CBP_EINVAL, "decoder must be 0 .. 4");
+    static const int kDecoderAlgo[5] = {kCBP, kLBPNMS, kFBPNMS, kLBP, kFBP};
+    int algo = kDecoderAlgo[decoder];
+    if (algo == kCBP && opts && opts->check_rule == CBP_RULE_MIN_SUM) algo = kCBPNMS;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    FixedWs fx;
+    int rc = static_scratch(dev, &fx.base);
+    if (rc) return rc;
+    fx.bytes = kStaticScratchBytes;
+    return decode(algo, code, llr_in, bits_out, iters_out, max_iter, batch, opts, stream, &fx);
 }
 
 int cbp_workspace_size(const cbp_code_t *code, int32_t decoder, int64_t batch, const cbp_opts_t *opts,
