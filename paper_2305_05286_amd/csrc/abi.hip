@@ -1287,6 +1287,12 @@ int cbp_decode_static(const cbp_code_t *code, int32_t decoder, const float *llr_
     static const int kDecoderAlgo[5] = {kCBP, kLBPNMS, kFBPNMS, kLBP, kFBP};
     int algo = kDecoderAlgo[decoder];
     if (algo == kCBP && opts && opts->check_rule == CBP_RULE_MIN_SUM) algo = kCBPNMS;
+    // the checks decode() makes before any device work, so that an empty batch
+    // is a no-op here too
+    if (!code) return fail(CBP_EINVAL, "code is NULL");
+    if (batch < 0) return fail(CBP_EINVAL, "batch < 0");
+    if (max_iter < 0) return fail(CBP_EINVAL, "max_iter < 0");
+    if (batch == 0) return CBP_OK;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
