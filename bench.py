@@ -14,9 +14,16 @@ zero syndrome.  The run
   3. times W warm-up + K decodes of one batch at the sweep point nearest
      CBP's FER = 1e-3 crossing (inputs resident in HBM) and reports that
      decoded info Gbit/s as `value`;
-  4. reports the roofline of the CBP kernel (algorithmic state bytes per
-     launch over its average duration, HIP events on the launch stream) and
-     the FP64 CPU oracle timed on a bounded sample of the same batch.
+  4. reports the roofline of the CBP kernel, which keeps frame state in
+     VGPRs and LDS and is bound by VALU issue: counter-measured VALU
+     wave-instructions per frame-sweep times the launch's frame-sweeps over
+     its average duration (HIP events on the launch stream), beside its HBM
+     and LDS traffic and the method's state bytes as a rate;
+  5. times the FP64 CPU oracle on a bounded sample of the same batch and
+     compares the GPU's decisions and sweep counts with it on that sample;
+  6. sweeps the n=26112 code (0.5 .. 1.5 dB, streamed kernel), decodes the
+     paper's PEG codes at up to 200 sweeps, a mixed-code batch in one
+     persistent launch, and trains the unrolled decoder.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -37,6 +44,11 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "decoded info Gbit/s at matched FER (CBP vs layered min-sum); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# 256 CU x 4 SIMD x 2.4 GHz / 4 cycles per wave64 VALU instruction
+VALU_PEAK_G = 256 * 4 * 2.4 / 4
+# 256 CU x 128 bytes per clock (32 banks x 4 B) x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
+PARITY_HEAD = 32768  # head of the timed batch kept for the oracle comparison
 DECODERS = ("cbp", "cbp_nms", "lbp_nms", "fbp_nms")
 
 
@@ -52,6 +64,19 @@ def algorithmic_bytes(iters: np.ndarray, E: int, M: int, N: int) -> float:
     per frame LLR in (4N), bits out (N) and the sweep count (4)."""
     per_sweep = 20.0 * E + 4.0 * M + E / 8.0
     return float(iters.astype(np.float64).sum() * per_sweep + len(iters) * (5.0 * N + 4.0))
+
+
+def host_cpu() -> dict:
+    """Host processor of this run: online CPUs, the CPUs this process may use, the model name."""
+    model = None
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc_online": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
 def crossing(snrs, fers, target, floor):
@@ -207,47 +232,77 @@ def main() -> int:
         it_np = iters.cpu().numpy()
         results[algo] = {"times": times, "wall": wall, "quality": q, "iters": it_np,
                          "gbps": B * K_info * args.steps / sum(times) / 1e9}
+        if algo == "cbp":  # decisions of the head of the batch, for the oracle comparison below
+            results[algo]["bits_head"] = bits[:PARITY_HEAD].cpu().numpy()
         log(f"[bench] timed {algo}: {args.steps} x {np.mean(times) * 1e3:.2f} ms, "
             f"{results[algo]['gbps']:.1f} Gbit/s, FER {q['fer']:.2e}, iters {q['mean_iters']:.2f}")
     head = results[decoders[0]]
     ms = float(np.mean(head["times"]) * 1e3)
 
     # ---------------- 3. roofline of the CBP kernel --------------------------
-    roof = roof_alu = None
+    # The kernel keeps every frame's state in VGPRs and LDS, so it is bound by
+    # VALU issue, not by HBM.  `roofline`: VALU wave-instructions per
+    # frame-sweep (committed counter pass on this kernel source, SQ_INSTS_VALU
+    # including the transcendentals) times the frame-sweeps of the timed launch
+    # (live), over the launch's mean duration (HIP events on its stream),
+    # against 256 CU x 4 SIMD x 2.4 GHz / 4 cycles per wave64 instruction.
+    # Beside it: HBM traffic (FETCH_SIZE + WRITE_SIZE, copy-calibrated) and LDS
+    # bytes (SQ_INSTS_LDS x 64 lanes x the static mean bytes per lane) over the
+    # same duration, and the method's state bytes as a rate (not a fraction:
+    # that state never reaches HBM in this kernel).
+    roof = extra_roof = None
     if "cbp" in results:
         r = results["cbp"]
         byts = algorithmic_bytes(r["iters"], code.E, code.M, code.N)
         dur = float(np.mean(r["times"]))
-        ach = byts / dur / 1e9
-        traffic = None
-        tf = ROOT / "profiles" / "traffic_qc2304_cbp.json"
-        if tf.exists():
-            t = json.loads(tf.read_text())
-            if t.get("kernel_hash") == kernel_hash() and abs(t.get("ebn0_db", -1) - op) < 1e-9:
-                traffic = t.get("hbm_bytes_per_launch")
-        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "qc_reg_kernel<QcGraph0, CBP>",
-                "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(dur * 1e3, 4),
-                "frame_sweeps_per_s": float(r["iters"].sum()) / dur}
-        # The state of this kernel lives in VGPRs and LDS; its binding limit is
-        # VALU issue.  Main-pipe VALU wave-instructions per launch (committed
-        # counter pass: SQ_INSTS_VALU minus the transcendentals, which gfx950
-        # runs in a separate unit) over the live launch duration, against
-        # 256 CU x 4 SIMD x 2.4 GHz / 4 cycles per wave64 instruction =
-        # 614.4 G wave-instructions/s.
-        vf = ROOT / "profiles" / "valu_qc2304_cbp.json"
-        if vf.exists():
-            v = json.loads(vf.read_text())
-            if (v.get("kernel_hash") == kernel_hash() and abs(v.get("ebn0_db", -1) - op) < 1e-9
-                    and "main_valu_wave_instructions_per_launch" in v):
-                peak = 256 * 4 * 2.4e9 / 4 / 1e9
-                main = v["main_valu_wave_instructions_per_launch"]
-                a_ = main / dur / 1e9
-                roof_alu = {"bound": "alu", "achieved": round(a_, 2), "peak": peak,
-                            "unit": "G VALU wave-instr/s", "frac": round(a_ / peak, 4),
-                            "main_valu_wave_instructions_per_launch": main,
-                            "trans_wave_instructions_per_launch": v["trans_wave_instructions_per_launch"]}
+        fsw = float(r["iters"].astype(np.float64).sum())
+
+        def prof(name):
+            f = ROOT / "profiles" / name
+            if not f.exists():
+                return None
+            v = json.loads(f.read_text())
+            return v if v.get("kernel_hash") == kernel_hash() else None
+
+        def per_fsw(v, key):
+            # counter per frame-sweep: the counted launch's frame-sweeps are
+            # stored with it, or it ran at this operating point
+            if v.get("frame_sweeps_per_launch"):
+                return v[key] / v["frame_sweeps_per_launch"]
+            return v[key] / fsw if abs(v.get("ebn0_db", -1) - op) < 1e-9 else None
+
+        tv, vv, lv = prof("traffic_qc2304_cbp.json"), prof("valu_qc2304_cbp.json"), prof("lds_qc2304_cbp.json")
+        traffic = per_fsw(tv, "hbm_bytes_per_launch") if tv else None
+        traffic = traffic * fsw if traffic is not None else None
+        valu_fs = per_fsw(vv, "valu_wave_instructions_per_launch") if vv else None
+        main_fs = per_fsw(vv, "main_valu_wave_instructions_per_launch") if vv else None
+        extra_roof = {"kernel": "qc_reg_kernel<QcGraph0, CBP>", "avg_launch_ms": round(dur * 1e3, 4),
+                      "frame_sweeps_per_launch": fsw, "frame_sweeps_per_s": fsw / dur,
+                      "edge_updates_per_s": fsw * code.E / dur,
+                      "state_bytes_per_launch": byts, "state_bytes_rate_gbs": round(byts / dur / 1e9, 1)}
+        if traffic is not None:
+            extra_roof["hbm"] = {"achieved": round(traffic / dur / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(traffic / dur / 1e9 / HBM_PEAK_GBS, 4),
+                                 "bytes_per_launch": traffic}
+        if lv is not None:
+            lds_fs = per_fsw(lv, "lds_bytes_per_launch")
+            if lds_fs is not None:
+                la = lds_fs * fsw / dur / 1e9
+                extra_roof["lds"] = {"achieved": round(la, 1), "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(la / LDS_PEAK_GBS, 4), "bytes_per_launch": lds_fs * fsw,
+                                     "busy": round(lv["lds_busy"], 4),
+                                     "bank_conflict_cycles_per_instruction": round(
+                                         lv["lds_bank_conflict_cycles_per_launch"]
+                                         / lv["lds_wave_instructions_per_launch"], 4)}
+        if valu_fs is not None:
+            a_ = valu_fs * fsw / dur / 1e9
+            roof = {"bound": "alu", "achieved": round(a_, 2), "peak": VALU_PEAK_G, "unit": "G VALU wave-instr/s",
+                    "frac": round(a_ / VALU_PEAK_G, 4), "traffic": traffic,
+                    "kernel": "qc_reg_kernel<QcGraph0, CBP>", "avg_launch_ms": round(dur * 1e3, 4),
+                    "valu_wave_instructions_per_frame_sweep": round(valu_fs, 2),
+                    "frame_sweeps_per_launch": fsw}
+            if main_fs is not None:
+                extra_roof["main_pipe_valu_frac"] = round(main_fs * fsw / dur / 1e9 / VALU_PEAK_G, 4)
 
     # ---------------- 4. the n=26112 code (streamed kernel) ----------------
     del llr_t, cw_t
@@ -268,37 +323,48 @@ def main() -> int:
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write)")
     large = None
     if not args.no_large:
+        # Eb/N0 0.5 .. 1.5 dB, 4096 frames per point, at most 25 sweeps; the
+        # first 512 frames of each point (and the last 128 at 1.0 dB, decoded in
+        # refilled slots) are the GPU parity tests' frames
         big = get_code("qc26112")
         bh = cbp.Code.from_workload(big)
-        nb_frames, big_snr, big_mi = 4096, 1.0, 25
-        bl, bc = make_frames(big, big_snr, nb_frames, key=(2026, 100))
-        bl_t = torch.from_numpy(bl).to(dev)
-        bc_t = torch.from_numpy(bc[:, :big.K]).to(dev)
+        nb_frames, big_mi = 4096, 25
         bbits = torch.empty((nb_frames, big.N), dtype=torch.uint8, device=dev)
         bit = torch.empty((nb_frames,), dtype=torch.int32, device=dev)
-        bws = torch.empty(cbp.workspace_size(bh, "cbp", nb_frames), dtype=torch.uint8, device=dev)
+        bws = torch.empty(max(cbp.workspace_size(bh, a, nb_frames) for a in DECODERS),
+                          dtype=torch.uint8, device=dev)
         large = {"code": "qc26112 (46x68 base, Z=384, n=26112, k=8448)", "frames": nb_frames,
-                 "ebn0_db": big_snr, "max_iter": big_mi, "kernel": "qc_stream"}
-        for algo in DECODERS:
-            cbp.decode(bh, bl_t, big_mi, algo, out=(bbits, bit), workspace=bws)
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
-            for s_, e_ in ev:
-                s_.record(stream)
+                 "max_iter": big_mi, "kernel": "qc_stream", "sweep": {a: [] for a in DECODERS}}
+        for big_snr in (0.5, 0.75, 1.0, 1.25, 1.5):
+            t0 = time.time()
+            bl, bc = make_frames(big, big_snr, nb_frames, key=(2027, int(round(big_snr * 100))))
+            bl_t = torch.from_numpy(bl).to(dev)
+            bc_t = torch.from_numpy(bc[:, :big.K]).to(dev)
+            del bl, bc
+            log(f"[bench] n=26112: generated {nb_frames} frames at {big_snr:.2f} dB in {time.time() - t0:.1f}s")
+            for algo in DECODERS:
                 cbp.decode(bh, bl_t, big_mi, algo, out=(bbits, bit), workspace=bws)
-                e_.record(stream)
-            torch.cuda.synchronize()
-            t = float(np.median([s_.elapsed_time(e_) for s_, e_ in ev])) / 1e3
-            fer = (bbits[:, :big.K] != bc_t).any(dim=1).float().mean().item()
-            its = bit.double().mean().item()
-            large[algo] = {"ms": round(t * 1e3, 3), "gbps": round(nb_frames * big.K / t / 1e9, 3),
-                           "fer": fer, "mean_iters": round(its, 3),
-                           "edge_updates_per_s": nb_frames * its * big.E / t}
-            if algo == "cbp":  # algorithmic state bytes (same count as the headline roofline)
-                ab = algorithmic_bytes(bit.cpu().numpy(), big.E, big.M, big.N) / t / 1e9
-                large[algo].update({"algorithmic_gbs": round(ab, 1), "frac_of_peak": round(ab / HBM_PEAK_GBS, 4),
-                                    "frac_of_copy": round(ab / copy_gbs, 4)})
-            log(f"[bench] n=26112 {algo}: {t * 1e3:.2f} ms, FER {fer:.2e}, iters {its:.2f}")
-        del bl_t, bc_t, bbits, bit, bws
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(3)]
+                for s_, e_ in ev:
+                    s_.record(stream)
+                    cbp.decode(bh, bl_t, big_mi, algo, out=(bbits, bit), workspace=bws)
+                    e_.record(stream)
+                torch.cuda.synchronize()
+                t = float(np.median([s_.elapsed_time(e_) for s_, e_ in ev])) / 1e3
+                fer = (bbits[:, :big.K] != bc_t).any(dim=1).float().mean().item()
+                its = bit.double().mean().item()
+                pt = {"ebn0_db": big_snr, "ms": round(t * 1e3, 3), "gbps": round(nb_frames * big.K / t / 1e9, 3),
+                      "fer": fer, "mean_iters": round(its, 3), "edge_updates_per_s": nb_frames * its * big.E / t}
+                if algo == "cbp":  # the method's state bytes: here they do stream through HBM
+                    ab = algorithmic_bytes(bit.cpu().numpy(), big.E, big.M, big.N) / t / 1e9
+                    pt.update({"algorithmic_gbs": round(ab, 1), "frac_of_peak": round(ab / HBM_PEAK_GBS, 4),
+                               "frac_of_copy": round(ab / copy_gbs, 4)})
+                large["sweep"][algo].append(pt)
+                log(f"[bench] n=26112 {big_snr:.2f} dB {algo}: {t * 1e3:.2f} ms, FER {fer:.2e}, iters {its:.2f}")
+            del bl_t, bc_t
+        large["at_1db"] = {a: next(p for p in v if p["ebn0_db"] == 1.0) for a, v in large["sweep"].items()}
+        del bbits, bit, bws
 
     # ---------------- 5. the paper's comparison on PEG codes (sparse kernel) --
     peg = None
@@ -425,12 +491,28 @@ def main() -> int:
         per = (time.perf_counter() - t0) / cal
         n = int(min(B, max(cal, args.cpu_seconds / max(per, 1e-9))))
         t0 = time.perf_counter()
-        oracle.decode(code, llr[:n], MI, "cbp")
+        ores = oracle.decode(code, llr[:n], MI, "cbp")
         dt = time.perf_counter() - t0
         cpu = {"value": round(n * K_info / dt / 1e9, 6), "unit": "Gbit/s",
                "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"first {n} of the {B} timed frames ({op} dB), FP64 CBP oracle, {dt:.1f}s"}
+               "sample": f"first {n} of the {B} timed frames ({op} dB), FP64 CBP oracle, {dt:.1f}s",
+               "host": host_cpu()}
         log(f"[bench] cpu oracle: {n} frames in {dt:.1f}s on {cpu['cores']} threads")
+        if "cbp" in results:
+            # the GPU's decisions and sweep counts on the same frames of the timed batch
+            m = min(n, PARITY_HEAD)
+            gb, gi = results["cbp"]["bits_head"][:m], results["cbp"]["iters"][:m]
+            ob, oi = ores["bits"][:m], ores["iters"][:m]
+            same = (gb == ob).all(axis=1) & (gi == oi)
+            conv = oi < MI
+            cpu["gpu_parity"] = {"frames": int(m), "frames_equal": round(float(same.mean()), 6),
+                                 "converged": {"frames": int(conv.sum()),
+                                               "equal": round(float(same[conv].mean()), 6) if conv.any() else None},
+                                 "failed": {"frames": int((~conv).sum()),
+                                            "equal": round(float(same[~conv].mean()), 6) if (~conv).any() else None},
+                                 "iterations_equal": round(float((gi == oi).mean()), 6)}
+            log(f"[bench] GPU vs oracle on {m} timed frames: {same.mean():.5f} equal "
+                f"({int((~same).sum())} differ; {int((~conv).sum())} frames failed in the oracle)")
         # context: the same oracle on one thread, and the layered min-sum oracle,
         # each on a small sample (about 2 s)
         n1 = max(16, int(2.0 / max(per * cpu["cores"], 1e-9)))
@@ -465,7 +547,7 @@ def main() -> int:
                    "code": "qc2304", "batch": B, "ebn0_db": op, "max_iter": MI,
                    "decoder": decoders[0], "parallelism": "single GPU"},
         "roofline": roof,
-        "roofline_alu": roof_alu,
+        "roofline_context": extra_roof,
         "cpu_baseline": cpu,
         "operating_point": {a: {"gbps": round(v["gbps"], 3), **{k: (round(x, 6) if isinstance(x, float) else x)
                                                                for k, x in v["quality"].items()}}

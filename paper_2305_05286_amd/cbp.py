@@ -309,6 +309,8 @@ def cbp_syndrome(code: Code, bits, stream=None):
 
 
 def workspace_size(code: Code, decoder: str, batch: int, **kw) -> int:
+    if decoder == "cbp_nms":  # cbp_decode with the min-sum rule
+        decoder, kw = "cbp", {**kw, "check_rule": "min_sum"}
     o = _opts(**kw)
     n = ctypes.c_size_t()
     check(lib().cbp_workspace_size(code.handle, DECODERS[decoder], batch, ctypes.byref(o),

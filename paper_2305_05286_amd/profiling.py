@@ -129,6 +129,71 @@ def valu(a) -> dict:
             "valu_busy": active / cus / (grbm / xcds)}
 
 
+def lds(a) -> dict:
+    """LDS traffic of the CBP kernel (one counter pass: SQ_INSTS_LDS,
+    SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_LDS_ADDR_CONFLICT,
+    SQ_ACTIVE_INST_LDS, GRBM_GUI_ACTIVE).  Bytes: instructions times 64 lanes
+    times the static mean bytes per lane (lds_mix).  Busy: the profiler's own
+    LdsUtil, cycles the LDS serves indexed accesses (summed over CUs) over
+    the GPU-active cycles of one XCD times the CUs."""
+    def mean(c):
+        return statistics.mean(_counter(a.dir, is_cbp, c))
+    mix = lds_mix()
+    ins = mean("SQ_INSTS_LDS")
+    idx, grbm = mean("SQ_LDS_IDX_ACTIVE"), mean("GRBM_GUI_ACTIVE")
+    cus, xcds = 256, 8
+    return {"kernel": "qc_reg_kernel<QcGraph0, CBP>", "kernel_hash": kernel_hash(), "ebn0_db": a.ebn0,
+            "lds_wave_instructions_per_launch": ins,
+            "lds_idx_active_cycles_per_launch": idx,
+            "lds_bank_conflict_cycles_per_launch": mean("SQ_LDS_BANK_CONFLICT"),
+            "lds_addr_conflict_cycles_per_launch": mean("SQ_LDS_ADDR_CONFLICT"),
+            "active_inst_lds_per_launch": mean("SQ_ACTIVE_INST_LDS"),
+            "grbm_gui_active_all_xcds": grbm, "lds_busy": idx / cus / (grbm / xcds),
+            "lds_bytes_per_launch": ins * 64 * mix["lds_bytes_per_lane_per_instruction"], **mix}
+
+
+# bytes per lane moved by each LDS instruction form (gfx9 DS encoding);
+# permutes and swizzles go through the LDS crossbar without touching its banks'
+# storage and count as one dword
+DS_BYTES = {"read_u8": 1, "read_i8": 1, "read_u16": 2, "read_i16": 2, "read_u8_d16": 1,
+            "read_u8_d16_hi": 1, "read_u16_d16": 2, "read_u16_d16_hi": 2, "read_b32": 4, "read_b64": 8,
+            "read_b96": 12, "read_b128": 16, "read2_b32": 8, "read2st64_b32": 8, "read2_b64": 16,
+            "read2st64_b64": 16, "write_b8": 1, "write_b16": 2, "write_b8_d16_hi": 1, "write_b16_d16_hi": 2,
+            "write_b32": 4, "write_b64": 8, "write_b96": 12, "write_b128": 16, "write2_b32": 8,
+            "write2st64_b32": 8, "write2_b64": 16, "write2st64_b64": 16, "bpermute_b32": 4,
+            "permute_b32": 4, "swizzle_b32": 4, "add_u32": 4, "max_u32": 4, "min_u32": 4}
+
+
+def lds_mix(kernel_symbol_part: str = "qc_reg_kernelINS0_8QcGraph0ELi0ELb0E") -> dict:
+    """Static LDS instruction mix of the CBP register-resident kernel: the
+    kernel's gfx950 assembly (compiled here with the library's flags) and the
+    bytes per lane of each DS instruction in it.  The mean bytes per LDS
+    wave-instruction turns the SQ_INSTS_LDS counter into LDS bytes."""
+    import re
+    import subprocess
+    import tempfile
+    from paper_2305_05286_amd import build
+    flags = [f for f in build.FLAGS if f not in ("-Xarch_device", "-fPIC")]
+    with tempfile.TemporaryDirectory() as td:
+        out = Path(td) / "k.s"
+        subprocess.run([build.HIPCC, *flags, "--cuda-device-only", "-S",
+                        str(build.CSRC / "qc_reg.hip"), "-o", str(out)], check=True, capture_output=True)
+        text = out.read_text()
+    start = text.index(f"_ZN3cbp12_GLOBAL__N_113{kernel_symbol_part}")
+    start = text.index("\n", text.index(":", start))
+    end = text.index(".Lfunc_end", start)
+    counts: dict = {}
+    for m in re.finditer(r"\bds_([a-z0-9_]+)", text[start:end]):
+        counts[m.group(1)] = counts.get(m.group(1), 0) + 1
+    unknown = sorted(k for k in counts if k not in DS_BYTES)
+    if unknown:
+        raise ValueError(f"unknown DS forms {unknown}")
+    n = sum(counts.values())
+    byts = sum(DS_BYTES[k] * c for k, c in counts.items())
+    return {"ds_static_counts": counts, "ds_static_instructions": n,
+            "lds_bytes_per_lane_per_instruction": byts / n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -140,15 +205,19 @@ def main():
     c.add_argument("--ebn0", type=float, required=True)
     c.add_argument("--kernel", choices=sorted(MATCHERS), default="qc_reg")
     c.add_argument("--out", required=True)
-    v = sub.add_parser("valu")
-    v.add_argument("dir")
-    v.add_argument("--ebn0", type=float, required=True)
-    v.add_argument("--out", required=True)
+    for name in ("valu", "lds"):
+        v = sub.add_parser(name)
+        v.add_argument("dir")
+        v.add_argument("--ebn0", type=float, required=True)
+        v.add_argument("--out", required=True)
+    sub.add_parser("ldsmix")
     a = ap.parse_args()
     if a.cmd == "trace":
         print(trace_table(a.dir))
+    elif a.cmd == "ldsmix":
+        print(json.dumps(lds_mix(), indent=1))
     else:
-        res = traffic(a) if a.cmd == "traffic" else valu(a)
+        res = {"traffic": traffic, "valu": valu, "lds": lds}[a.cmd](a)
         Path(a.out).write_text(json.dumps(res, indent=1) + "\n")
         print(json.dumps(res, indent=1))
 
