@@ -91,7 +91,8 @@ struct cbp_graph {
 namespace {
 
 // Column lists in row order give each edge its latest check in steady state
-// (the cyclically previous row of the same column) and the first-visit flag.
+// (the cyclically previous row of the same column) and the first- and
+// last-visit flags.
 int finish_code(cbp_code *c) {
     const int M = c->M, N = c->N;
     const int64_t E = c->E;
@@ -107,12 +108,14 @@ int finish_code(cbp_code *c) {
             const int v = c->col_idx[e];
             if (first_edge[v] < 0) {
                 first_edge[v] = e;
-                c->first[e] = 1;
+                c->first[e] = (uint8_t)kFirstVisit;
             } else {
                 c->pred_edge[e] = c->last_edge[v];
             }
             c->last_edge[v] = e;
         }
+    for (int v = 0; v < N; ++v)
+        if (c->last_edge[v] >= 0) c->first[c->last_edge[v]] |= (uint8_t)kLastVisit;
     for (int v = 0; v < N; ++v) {
         if (first_edge[v] < 0) return fail(CBP_EINVAL, "column %d has no edge", v);
         c->pred_edge[first_edge[v]] = c->last_edge[v];

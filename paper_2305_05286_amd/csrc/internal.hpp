@@ -34,6 +34,9 @@ __device__ __forceinline__ uint32_t ldc_u8(const uint8_t *p, int64_t i) {
     return (ldc((const uint32_t *)p, i >> 2) >> (8 * (uint32_t)(i & 3))) & 0xffu;
 }
 
+// Bits of SparseDev::first.
+constexpr uint32_t kFirstVisit = 1u, kLastVisit = 2u;
+
 struct Params {
     float a;       // phi(lmax): lower clamp of |Q| entering phi
     float lmax;    // upper clamp
@@ -56,7 +59,8 @@ struct SparseDev {
     const int *edge_row;  // [E]  row of each edge
     const int *pred_edge; // [E]  edge of the cyclically previous row of the same column
     const int *pred_row;  // [E]  row of pred_edge
-    const uint8_t *first; // [E]  1 if this is the lowest row of its column
+    const uint8_t *first; // [E]  visit flags: kFirstVisit if this is the lowest row of its
+                          //      column, kLastVisit if the highest (both for weight one)
     const int *last_edge; // [N]  edge of the highest row of each column
     int nlev;             // row levels (rows of one level share no variable)
     const int *lvl_ptr;   // [nlev+1] first entry of each level in lvl_rows
@@ -84,8 +88,8 @@ __host__ __device__ inline int64_t round256(int64_t x) { return (x + 255) / 256 
 
 // Hand-off of slow frames from the one-frame-per-lane kernels to a
 // level-parallel kernel (one frame per workgroup, the rows of each level on
-// separate threads).  An item holds one frame's state contiguously: CBP Q, PQ
-// [N], R [E], OmM, OmS [M], decisions [N]; BP Lambda [N], R [E], sums [N],
+// separate threads).  An item holds one frame's state contiguously: CBP Q [N],
+// R [E], Om [M] (float2), decisions [N]; BP Lambda [N], R [E], sums [N],
 // decisions [N]; each array 256-byte aligned.
 struct Handoff {
     int lanes;            // a wave hands over once the batch is exhausted and at most

@@ -82,18 +82,20 @@ __device__ __forceinline__ int64_t claim_frames(unsigned long long *counter, uin
 }
 
 // --------------------------------------------------------------------------
-// CBP.  ws: a0 = Q[N] (latest V2C), a1 = PQ[N] (phi2 of the clamped Q folded
-// into the latest check), a2 = R[E], a3 = OmM[M] (max phi2 term, sign bit =
-// parity), a4 = OmS[M] (rest of the phi2 sum), xb = hard decisions [N].  The
-// log-tanh rule keeps LLRs in log2 units (L / ln2), where phi2 serves both
-// directions of the check rule; Params a and lmax arrive already scaled.
+// CBP.  ws: a0 = Q[N] (latest V2C), a2 = R[E], a3 = Om[M] as float2 (max phi2
+// term with the parity in its sign bit, rest of the phi2 sum), xb = hard
+// decisions [N].  The phi2 term of Q_v that v's latest check folded is not
+// stored: Q_v is still that V2C value, and phi2 of it is recomputed bit for
+// bit (8 bytes per edge-update less state traffic).  The log-tanh rule keeps
+// LLRs in log2 units (L / ln2), where phi2 serves both directions of the
+// check rule; Params a and lmax arrive already scaled.
 // --------------------------------------------------------------------------
 // C2V of a check recovered from its belief (om = max term or min1 with the
 // parity in its sign bit, os = rest of the sum or min2), excluding q.
 template <bool kMin>
-__device__ float b2v(float om, float os, float pq, float q, const Params &p) {
+__device__ float b2v(float om, float os, float q, const Params &p) {
     if constexpr (!kMin) {
-        return with_sign(phi2(excl_sum(abs_bits(om), os, pq)), sign_bit(om) ^ (q < 0.0f));
+        return with_sign(phi2(excl_sum(abs_bits(om), os, phi2_clamped(q, p.a, p.lmax))), sign_bit(om) ^ (q < 0.0f));
     } else {
         const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
         const float m1 = abs_bits(om);
@@ -106,7 +108,8 @@ __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, uint32_t lf,
     const int e = ldc(g.last_edge, v);
     const int j = ldc(g.edge_row, e);
     const float q = w.a0[at(v, lf)];
-    return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
+    const float2 om = reinterpret_cast<const float2 *>(w.a3)[at(j, lf)];
+    return q + b2v<kMin>(om.x, om.y, q, p);
 }
 
 // Flushed posterior after a stop in the middle of sweep t, right after row
@@ -119,7 +122,7 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, uint32_t 
     const float q = w.a0[at(v, lf)];
     int e = ldc(g.last_edge, v);
     while (ldc(g.edge_row, e) > istop) {
-        if (ldc_u8(g.first, e)) {  // no visit of v yet in this sweep
+        if (ldc_u8(g.first, e) & kFirstVisit) {  // no visit of v yet in this sweep
             if (t == 1) return q;
             e = ldc(g.last_edge, v);
             break;
@@ -127,7 +130,8 @@ __device__ float cbp_flushed_at(const SparseDev &g, const SparseWs &w, uint32_t 
         e = ldc(g.pred_edge, e);
     }
     const int j = ldc(g.edge_row, e);
-    return q + b2v<kMin>(w.a3[at(j, lf)], w.a4[at(j, lf)], w.a1[at(v, lf)], q, p);
+    const float2 om = reinterpret_cast<const float2 *>(w.a3)[at(j, lf)];
+    return q + b2v<kMin>(om.x, om.y, q, p);
 }
 
 // Entry r of the level-ordered row table: (row, first edge, end edge, 0).
@@ -145,7 +149,8 @@ __device__ __forceinline__ uint32_t ix(int idx, uint32_t lf) {
 }
 
 struct CbpState {
-    float *Q, *PQ, *R, *OmM, *OmS;
+    float *Q, *R;
+    float2 *Om;
     uint8_t *xb;
 };
 
@@ -156,8 +161,11 @@ struct CbpState {
 template <bool kMin, int kStride>
 __device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, int e0, int e1, bool sweep1, const CbpState &st,
                                         uint32_t lf, const Params &p, bool &flip) {
-    float *Q = st.Q, *PQ = st.PQ, *R = st.R;
+    float *Q = st.Q, *R = st.R;
     uint8_t *xb = st.xb;
+    // decisions are stored at a variable's last visit of the sweep (the one
+    // Step 3 reads), or at every visit for the paper's stopping rule
+    const bool every = p.stop_rule == 1;
     float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
     bool par = false;
     // The row's edges in chunks of kChunk: every load of a chunk is issued
@@ -178,19 +186,15 @@ __device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, int e0, int e
             pr[k] = ldc(g.pred_row, c0 + k);
             fi[k] = ldc_u8(g.first, c0 + k);
         }
-        float q[kChunk], pq[kChunk], om[kChunk], os[kChunk], r[kChunk];
+        float q[kChunk], r[kChunk];
+        float2 om[kChunk];
         uint8_t x0[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             if (k < n) {
                 const uint32_t iv = ix<kStride>(col[k], lf);
                 q[k] = Q[iv];
-                if (!kMin) pq[k] = PQ[iv];
-                if (!(sweep1 && fi[k])) {
-                    const uint32_t ij = ix<kStride>(pr[k], lf);
-                    om[k] = st.OmM[ij];
-                    os[k] = st.OmS[ij];
-                }
+                if (!(sweep1 && (fi[k] & kFirstVisit))) om[k] = st.Om[ix<kStride>(pr[k], lf)];
                 r[k] = R[ix<kStride>(c0 + k, lf)];
                 if (p.stop_rule == 1) x0[k] = xb[iv];
             }
@@ -201,23 +205,21 @@ __device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, int e0, int e
                 const int e = c0 + k;
                 const uint32_t iv = ix<kStride>(col[k], lf);
                 float rn = 0.0f, rc = r[k];
-                if (!(sweep1 && fi[k])) {
+                if (!(sweep1 && (fi[k] & kFirstVisit))) {
                     // B2V (eq. equ_s4e18): C2V of the latest check c_j recovered
                     // from its belief, then committed to R(c_j -> v) first.
-                    rn = b2v<kMin>(om[k], os[k], pq[k], q[k], p);
+                    rn = b2v<kMin>(om[k].x, om[k].y, q[k], p);
                     R[ix<kStride>(pe[k], lf)] = rn;
                     if (pe[k] == e) rc = rn;
                 }
                 const float lam = q[k] + rn;              // eq. equ_s4e20
                 const uint8_t nx = lam < 0.0f;            // eq. equ_s2e7
                 if (p.stop_rule == 1) flip |= nx != x0[k];
-                xb[iv] = nx;
+                if (every || (fi[k] & kLastVisit)) xb[iv] = nx;
                 const float qn = lam - rc;                // V2C, eq. equ_s4e19
                 Q[iv] = qn;
                 if constexpr (!kMin) {
-                    const float fq = phi2_clamped(qn, p.a, p.lmax);
-                    PQ[iv] = fq;
-                    fold(Mx, Sr, fq);                     // C2B, eq. equ_s4e21
+                    fold(Mx, Sr, phi2_clamped(qn, p.a, p.lmax));  // C2B, eq. equ_s4e21
                 } else {                                  // eq. equ_s4e21xx
                     const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
                     Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
@@ -227,9 +229,93 @@ __device__ __forceinline__ bool cbp_row(const SparseDev &g, int i, int e0, int e
             }
         }
     }
-    st.OmM[ix<kStride>(i, lf)] = with_sign(Mx, par);  // eq. equ_s4e23
-    st.OmS[ix<kStride>(i, lf)] = Sr;
+    st.Om[ix<kStride>(i, lf)] = make_float2(with_sign(Mx, par), Sr);  // eq. equ_s4e23
     return par;
+}
+
+// Rows of one level handled together by the one-frame-per-lane kernel.
+#ifndef CBP_SPARSE_ROWS
+#define CBP_SPARSE_ROWS 4
+#endif
+constexpr int kRows = CBP_SPARSE_ROWS;
+
+// nr (<= kRows) rows of one level, each of at most kChunk edges, on the lane's
+// frame: the same Step 2(1)-(2) updates as cbp_row, with every load of all
+// the rows issued before any store.  Rows of a level share no variable, so no
+// row reads what another stores (its Q, decisions and R slots are its own
+// columns', and the beliefs it reads are of rows holding its variables, which
+// are in other levels): nr rows cost one memory round trip instead of nr.
+// Syndrome stopping only (decisions at last visits).
+template <bool kMin>
+__device__ __forceinline__ void cbp_level_rows(const SparseDev &g, const int4 (&rr)[kRows], int nr, bool sweep1,
+                                               const CbpState &st, uint32_t lf, const Params &p) {
+    float *Q = st.Q, *R = st.R;
+    uint8_t *xb = st.xb;
+    int col[kRows][kChunk], pe[kRows][kChunk], pr[kRows][kChunk];
+    uint32_t fi[kRows][kChunk];
+    float q[kRows][kChunk], r[kRows][kChunk];
+    float2 om[kRows][kChunk];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+        if (j < nr) {
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {  // unconditionally (padded tables)
+                col[j][k] = ldc(g.col_idx, rr[j].y + k);
+                pe[j][k] = ldc(g.pred_edge, rr[j].y + k);
+                pr[j][k] = ldc(g.pred_row, rr[j].y + k);
+                fi[j][k] = ldc_u8(g.first, rr[j].y + k);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+        if (j < nr) {
+            const int n = rr[j].z - rr[j].y;
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {
+                if (k < n) {
+                    const uint32_t iv = at(col[j][k], lf);
+                    q[j][k] = Q[iv];
+                    if (!(sweep1 && (fi[j][k] & kFirstVisit))) om[j][k] = st.Om[at(pr[j][k], lf)];
+                    r[j][k] = R[at(rr[j].y + k, lf)];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+        if (j < nr) {
+            const int n = rr[j].z - rr[j].y;
+            float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
+            bool par = false;
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k) {
+                if (k < n) {
+                    const int e = rr[j].y + k;
+                    const uint32_t iv = at(col[j][k], lf);
+                    float rn = 0.0f, rc = r[j][k];
+                    if (!(sweep1 && (fi[j][k] & kFirstVisit))) {
+                        rn = b2v<kMin>(om[j][k].x, om[j][k].y, q[j][k], p);  // eq. equ_s4e18
+                        R[at(pe[j][k], lf)] = rn;
+                        if (pe[j][k] == e) rc = rn;
+                    }
+                    const float lam = q[j][k] + rn;   // eq. equ_s4e20
+                    if (fi[j][k] & kLastVisit) xb[iv] = lam < 0.0f;
+                    const float qn = lam - rc;        // eq. equ_s4e19
+                    Q[iv] = qn;
+                    if constexpr (!kMin) {
+                        fold(Mx, Sr, phi2_clamped(qn, p.a, p.lmax));  // eq. equ_s4e21
+                    } else {
+                        const float aq = __builtin_fminf(__builtin_fabsf(qn), p.lmax);
+                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, aq));
+                        Mx = __builtin_fminf(Mx, aq);
+                    }
+                    par ^= (qn < 0.0f);
+                }
+            }
+            st.Om[at(rr[j].x, lf)] = make_float2(with_sign(Mx, par), Sr);  // eq. equ_s4e23
+        }
+    }
 }
 
 // Hand-off of slow frames.  Once the batch is exhausted and a wave has only a
@@ -242,19 +328,17 @@ __device__ __forceinline__ char *item_base(const Handoff &h, uint32_t k) {
 }
 
 __device__ __forceinline__ CbpState cbp_state(const SparseWs &w) {
-    return CbpState{w.a0, w.a1, w.a2, w.a3, w.a4, w.xb};
+    return CbpState{w.a0, w.a2, reinterpret_cast<float2 *>(w.a3), w.xb};
 }
 
 __device__ __forceinline__ CbpState cbp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
     char *b = item_base(h, k);
     CbpState st;
-    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m4 = round256(4 * (int64_t)g.M);
+    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m8 = round256(8 * (int64_t)g.M);
     st.Q = (float *)b;
-    st.PQ = (float *)(b + n4);
-    st.R = (float *)(b + 2 * n4);
-    st.OmM = (float *)(b + 2 * n4 + e4);
-    st.OmS = (float *)(b + 2 * n4 + e4 + m4);
-    st.xb = (uint8_t *)(b + 2 * n4 + e4 + 2 * m4);
+    st.R = (float *)(b + n4);
+    st.Om = (float2 *)(b + n4 + e4);
+    st.xb = (uint8_t *)(b + n4 + e4 + m8);
     return st;
 }
 
@@ -286,11 +370,9 @@ __device__ __forceinline__ void hand_over_cbp(const SparseDev &g, const Handoff 
         int r, na;
         active_rank(r, na);
         copy_slot(it.Q, w.Q, g.N, d, r, na);
-        copy_slot(it.PQ, w.PQ, g.N, d, r, na);
         copy_slot(it.xb, w.xb, g.N, d, r, na);
         copy_slot(it.R, w.R, g.E, d, r, na);
-        copy_slot(it.OmM, w.OmM, g.M, d, r, na);
-        copy_slot(it.OmS, w.OmS, g.M, d, r, na);
+        copy_slot(it.Om, w.Om, g.M, d, r, na);
         if (r == 0) h.items[k] = make_int2(fd, td);
     }
 }
@@ -311,7 +393,7 @@ __device__ __forceinline__ bool handing_off(const Handoff &h, unsigned long long
     return __ballot(hand) != 0;
 }
 
-// kMin: the normalized min-sum check rule (OmM = min1 | parity, OmS = min2).
+// kMin: the normalized min-sum check rule (Om = (min1 | parity, min2)).
 template <bool kMin>
 __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     SparseDev g, const float *__restrict__ llr, uint8_t *__restrict__ bits,
@@ -320,7 +402,8 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
     w = wave_block(w);
     const uint32_t lf = tid_x();  // this lane's slot in its wave's block
     const CbpState st = cbp_state(w);
-    float *Q = w.a0, *R = w.a2, *OmM = w.a3, *OmS = w.a4;
+    float *Q = w.a0, *R = w.a2;
+    const float2 *Om = st.Om;
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
     const float un = kMin ? 1.0f : kLn2;    // dumps in natural units
     p.a *= us;
@@ -362,19 +445,43 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
         uint32_t hk = 0;
         if (!done) {
             ++t;
-            // Step 2: check-nodes in index order
+            // Step 2: check-nodes in index order; with the syndrome stop, level by
+            // level (the same result bit for bit), kRows rows of a level at a time
             bool paper_stop = false;
             int istop = 0;
-            for (int i = 0; i < g.M; ++i) {
-                bool flip = false;
-                const bool par = cbp_row<kMin, kWave>(g, i, ldc(g.row_ptr, i), ldc(g.row_ptr, i + 1), t == 1, st, lf,
-                                                      p, flip);
-                if (p.stop_rule == 1) {  // Step 2(3): M updates in a row with Omega > 0, no flip
+            if (p.stop_rule == 1) {
+                for (int i = 0; i < g.M; ++i) {
+                    bool flip = false;
+                    const bool par = cbp_row<kMin, kWave>(g, i, ldc(g.row_ptr, i), ldc(g.row_ptr, i + 1), t == 1, st,
+                                                          lf, p, flip);
+                    // Step 2(3): M updates in a row with Omega > 0, no flip
                     run = (!par && !flip) ? run + 1 : 0;
                     if (run >= g.M) {
                         paper_stop = true;
                         istop = i;
                         break;
+                    }
+                }
+            } else {
+                for (int l = 0; l < g.nlev; ++l) {
+                    const int r1 = ldc(g.lvl_ptr, l + 1);
+                    for (int r = ldc(g.lvl_ptr, l); r < r1; r += kRows) {
+                        const int nr = r1 - r < kRows ? r1 - r : kRows;
+                        int4 rr[kRows];
+                        bool narrow = true;
+#pragma unroll
+                        for (int j = 0; j < kRows; ++j) {
+                            rr[j] = level_row(g, j < nr ? r + j : r);
+                            narrow &= rr[j].z - rr[j].y <= kChunk;
+                        }
+                        if (narrow) {
+                            cbp_level_rows<kMin>(g, rr, nr, t == 1, st, lf, p);
+                        } else {
+                            for (int j = 0; j < nr; ++j) {
+                                bool flip = false;
+                                (void)cbp_row<kMin, kWave>(g, rr[j].x, rr[j].y, rr[j].z, t == 1, st, lf, p, flip);
+                            }
+                        }
                     }
                 }
             }
@@ -397,10 +504,10 @@ __global__ __launch_bounds__(kWave) void cbp_sparse_kernel(
                     for (int e = 0; e < g.E; ++e) d.r[f * g.E + e] = R[at(e, lf)] * un;
                 if (d.om)
                     for (int i = 0; i < g.M; ++i) {
-                        const float om = OmM[at(i, lf)];
+                        const float2 om = Om[at(i, lf)];
                         d.om[f * g.M + i] =
-                            kMin ? with_sign(p.alpha * abs_bits(om), sign_bit(om))
-                                 : with_sign(phi2(abs_bits(om) + OmS[at(i, lf)]) * un, sign_bit(om));
+                            kMin ? with_sign(p.alpha * abs_bits(om.x), sign_bit(om.x))
+                                 : with_sign(phi2(abs_bits(om.x) + om.y) * un, sign_bit(om.x));
                     }
             }
             const bool stop = (p.stop_rule == 0 && lane_syndrome_ok(g, xb, lf)) || t == max_iter;
@@ -779,14 +886,13 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Bytes of one wave's block: each array padded to 256 bytes.
 static int64_t sparse_block_bytes(int algo, const SparseDev &g) {
     auto arr = [](int64_t n, int64_t bytes) { return round_up(n * kWave * bytes, 256); };
-    if (algo == kCBP || algo == kCBPNMS)
-        return 2 * arr(g.N, 4) + arr(g.E, 4) + 2 * arr(g.M, 4) + arr(g.N, 1);
+    if (algo == kCBP || algo == kCBPNMS) return arr(g.N, 4) + arr(g.E, 4) + arr(g.M, 8) + arr(g.N, 1);
     return 2 * arr(g.N, 4) + arr(g.E, 4) + arr(g.N, 1);
 }
 
 int64_t sparse_item_bytes(int algo, const SparseDev &g) {
-    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m4 = round256(4 * (int64_t)g.M);
-    if (algo == kCBP || algo == kCBPNMS) return 2 * n4 + e4 + 2 * m4 + round256(g.N);
+    const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m8 = round256(8 * (int64_t)g.M);
+    if (algo == kCBP || algo == kCBPNMS) return n4 + e4 + m8 + round256(g.N);
     return 2 * n4 + e4 + round256(g.N);
 }
 
@@ -807,10 +913,8 @@ SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *bas
     };
     if (algo == kCBP || algo == kCBPNMS) {
         w.a0 = (float *)take(g.N, 4);
-        w.a1 = (float *)take(g.N, 4);
         w.a2 = (float *)take(g.E, 4);
-        w.a3 = (float *)take(g.M, 4);
-        w.a4 = (float *)take(g.M, 4);
+        w.a3 = (float *)take(g.M, 8);  // float2
     } else {
         w.a0 = (float *)take(g.N, 4);
         w.a1 = (float *)take(g.E, 4);

@@ -174,7 +174,7 @@ def test_workspace_sizes(L):
     c = cbp.Code.from_workload(get_code("reg36_n96"))
     n = cbp.workspace_size(c, "cbp", 2000)
     S = 2048  # frames padded to whole waves
-    assert n >= (2 * 96 + 288 + 2 * 48) * 4 * S + 96 * S
+    assert n >= (96 + 288 + 2 * 48) * 4 * S + 96 * S  # Q, R, check-beliefs (float2), decisions
     assert cbp.workspace_size(c, "cbp", 0) == 0
     q = cbp.Code.from_workload(get_code("qc2304"))
     assert 0 < cbp.workspace_size(q, "cbp", 131072) <= 4096
