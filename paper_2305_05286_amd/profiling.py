@@ -130,26 +130,34 @@ def valu(a) -> dict:
 
 
 def lds(a) -> dict:
-    """LDS traffic of the CBP kernel (one counter pass: SQ_INSTS_LDS,
-    SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_LDS_ADDR_CONFLICT,
-    SQ_ACTIVE_INST_LDS, GRBM_GUI_ACTIVE).  Bytes: instructions times 64 lanes
-    times the static mean bytes per lane (lds_mix).  Busy: the profiler's own
-    LdsUtil, cycles the LDS serves indexed accesses (summed over CUs) over
-    the GPU-active cycles of one XCD times the CUs."""
-    def mean(c):
-        return statistics.mean(_counter(a.dir, is_cbp, c))
+    """LDS traffic of the CBP kernel from two counter passes.
+
+    a.dir: SQ_INSTS_LDS, SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT,
+    SQ_LDS_ADDR_CONFLICT, SQ_ACTIVE_INST_LDS, GRBM_GUI_ACTIVE.  Busy: the
+    profiler's own LdsUtil, cycles the LDS serves indexed accesses (summed
+    over CUs) over the GPU-active cycles of one XCD times the CUs.
+    a.bw: SQ_INSTS_LDS_LOAD_BANDWIDTH and SQ_INSTS_LDS_STORE_BANDWIDTH, the
+    bytes the LDS instructions moved (active lanes times access size) in
+    units of 64 bytes: the LDS bytes per launch.  The static estimate beside
+    it (SQ_INSTS_LDS x 64 lanes x the kernel's mean DS access size, lds_mix)
+    cross-checks it."""
+    def mean(d, c):
+        return statistics.mean(_counter(d, is_cbp, c))
     mix = lds_mix()
-    ins = mean("SQ_INSTS_LDS")
-    idx, grbm = mean("SQ_LDS_IDX_ACTIVE"), mean("GRBM_GUI_ACTIVE")
+    ins = mean(a.dir, "SQ_INSTS_LDS")
+    idx, grbm = mean(a.dir, "SQ_LDS_IDX_ACTIVE"), mean(a.dir, "GRBM_GUI_ACTIVE")
+    ld, st = mean(a.bw, "SQ_INSTS_LDS_LOAD_BANDWIDTH") * 64, mean(a.bw, "SQ_INSTS_LDS_STORE_BANDWIDTH") * 64
     cus, xcds = 256, 8
     return {"kernel": "qc_reg_kernel<QcGraph0, CBP>", "kernel_hash": kernel_hash(), "ebn0_db": a.ebn0,
             "lds_wave_instructions_per_launch": ins,
             "lds_idx_active_cycles_per_launch": idx,
-            "lds_bank_conflict_cycles_per_launch": mean("SQ_LDS_BANK_CONFLICT"),
-            "lds_addr_conflict_cycles_per_launch": mean("SQ_LDS_ADDR_CONFLICT"),
-            "active_inst_lds_per_launch": mean("SQ_ACTIVE_INST_LDS"),
+            "lds_bank_conflict_cycles_per_launch": mean(a.dir, "SQ_LDS_BANK_CONFLICT"),
+            "lds_addr_conflict_cycles_per_launch": mean(a.dir, "SQ_LDS_ADDR_CONFLICT"),
+            "active_inst_lds_per_launch": mean(a.dir, "SQ_ACTIVE_INST_LDS"),
             "grbm_gui_active_all_xcds": grbm, "lds_busy": idx / cus / (grbm / xcds),
-            "lds_bytes_per_launch": ins * 64 * mix["lds_bytes_per_lane_per_instruction"], **mix}
+            "lds_load_bytes_per_launch": ld, "lds_store_bytes_per_launch": st,
+            "lds_bytes_per_launch": ld + st,
+            "lds_bytes_static_estimate": ins * 64 * mix["lds_bytes_per_lane_per_instruction"], **mix}
 
 
 # bytes per lane moved by each LDS instruction form (gfx9 DS encoding);
@@ -208,6 +216,8 @@ def main():
     for name in ("valu", "lds"):
         v = sub.add_parser(name)
         v.add_argument("dir")
+        if name == "lds":
+            v.add_argument("--bw", required=True, help="pass with the LDS load/store bandwidth counters")
         v.add_argument("--ebn0", type=float, required=True)
         v.add_argument("--out", required=True)
     sub.add_parser("ldsmix")

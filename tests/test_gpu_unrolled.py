@@ -73,8 +73,8 @@ def test_forward_matches_fp64_oracle(name):
                           beta.astype(np.float32).astype(np.float64))
     err = np.abs(o - ref) / np.maximum(np.abs(ref), 1.0)
     say(f"    max rel {err.max():.2e}, within 1e-4: {np.mean(err <= 1e-4):.5f}")
-    assert np.mean(err <= 1e-4) >= 0.999
-    assert err.max() <= 1e-2
+    # every soft output within the FP32 message bar of FP64
+    assert err.max() <= 1e-4
 
 
 @pytest.mark.parametrize("name", ["qc_t16", "qc_t72"])
@@ -130,6 +130,66 @@ def test_gradients_match_fp64_finite_differences(name):
     assert rel(gl_s, fl) < 1e-3
     for g, f in ((gw, fw), (gb, fb), (gl_s, fl)):
         assert np.all(np.abs(g - f) <= 1e-3 * np.abs(f).max() + 1e-3 * np.abs(f))
+
+
+def test_gradients_at_the_training_size():
+    """The configuration the decoder is trained in: the n = 2304 code, 10
+    unrolled sweeps.  FP64 central differences of the oracle's forward at 24
+    sampled (sweep, block-column) weights and offsets, spread over all ten
+    sweeps, and 12 sampled LLRs, on 3 frames at 1.25 dB (cross-entropy 0.04;
+    at 1.75 dB these frames decode with a loss of 5e-10, where the gradients
+    are of order 1e-10 and measure saturation rather than the adjoint)."""
+    code = get_code("qc2304")
+    T, nb = 10, code.N // code.Z
+    rng = np.random.default_rng(57)
+    w = rng.uniform(0.7, 1.3, size=(T, nb)).astype(np.float32).astype(np.float64)
+    beta = rng.uniform(0.01, 0.1, size=(T, nb)).astype(np.float32).astype(np.float64)
+    llr, cw = make_frames(code, 1.25, 3, key=(57,))
+    cwf = cw.astype(np.float64)
+    c = cbp.Code.from_workload(code)
+    lt = torch.from_numpy(llr).cuda().requires_grad_(True)
+    wt = torch.tensor(w, dtype=torch.float32, device="cuda", requires_grad=True)
+    bt = torch.tensor(beta, dtype=torch.float32, device="cuda", requires_grad=True)
+    o = cbp.unrolled_cbp(c, lt, wt, bt, T)
+    ct = torch.from_numpy(cwf).cuda()
+    od = o.double()
+    loss = (ct * torch.nn.functional.softplus(od) + (1 - ct) * torch.nn.functional.softplus(-od)).mean()
+    loss.backward()
+    gw, gb, gl = wt.grad.cpu().numpy(), bt.grad.cpu().numpy(), lt.grad.cpu().numpy()
+
+    def L(w_, b_, llr_=llr):
+        return bce64(oracle.unrolled(code, llr_, w_, b_), cwf)
+    pairs = [(t, int(b)) for t in range(T) for b in rng.choice(nb, size=2, replace=False)][:20]
+    pairs += [(T - 1, int(b)) for b in rng.choice(nb, size=4, replace=False)]
+    h = 1e-5
+    fw, fb, sw, sb = [], [], [], []
+    for t, b in pairs:
+        e = np.zeros_like(w)
+        e[t, b] = h
+        fw.append((L(w + e, beta) - L(w - e, beta)) / (2 * h))
+        fb.append((L(w, beta + e) - L(w, beta - e)) / (2 * h))
+        sw.append(gw[t, b])
+        sb.append(gb[t, b])
+    hl = 2.0 ** -10
+    fl, sl = [], []
+    for f in range(3):
+        for v in rng.choice(code.N, size=4, replace=False):
+            lp, lm = llr.copy(), llr.copy()
+            lp[f, v] += hl
+            lm[f, v] -= hl
+            fl.append((L(w, beta, lp) - L(w, beta, lm)) / (2 * hl))
+            sl.append(gl[f, v])
+    fw, fb, fl, sw, sb, sl = map(np.array, (fw, fb, fl, sw, sb, sl))
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+    say(f"[gpu] unrolled gradients at T=10 on n=2304: rel err w {rel(sw, fw):.2e}, beta {rel(sb, fb):.2e}, "
+        f"llr {rel(sl, fl):.2e}; |dL/dw| max {np.abs(fw).max():.3e}, sweeps with nonzero dL/dw "
+        f"{sorted({t for (t, _), g in zip(pairs, fw) if g != 0})}")
+    assert np.abs(fw).max() > 0 and np.abs(fl).max() > 0
+    assert rel(sw, fw) < 1e-3
+    assert rel(sb, fb) < 1e-3
+    assert rel(sl, fl) < 1e-3
 
 
 def test_backward_is_deterministic():
