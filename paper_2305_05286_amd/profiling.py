@@ -221,11 +221,21 @@ def main():
         v.add_argument("--ebn0", type=float, required=True)
         v.add_argument("--out", required=True)
     sub.add_parser("ldsmix")
+    an = sub.add_parser("annotate", help="record the counted launch's frame-sweeps in a summary, so that "
+                                         "its per-launch counts scale to other launches of the kernel")
+    an.add_argument("file")
+    an.add_argument("--frame-sweeps", type=float, required=True,
+                    help="sweeps summed over the frames of the counted launch")
     a = ap.parse_args()
     if a.cmd == "trace":
         print(trace_table(a.dir))
     elif a.cmd == "ldsmix":
         print(json.dumps(lds_mix(), indent=1))
+    elif a.cmd == "annotate":
+        f = Path(a.file)
+        res = json.loads(f.read_text())
+        res["frame_sweeps_per_launch"] = a.frame_sweeps
+        f.write_text(json.dumps(res, indent=1) + "\n")
     else:
         res = {"traffic": traffic, "valu": valu, "lds": lds}[a.cmd](a)
         Path(a.out).write_text(json.dumps(res, indent=1) + "\n")
