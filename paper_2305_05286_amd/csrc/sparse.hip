@@ -347,8 +347,7 @@ __device__ __forceinline__ CbpState cbp_state(const SparseWs &w) {
     return CbpState{w.a0, w.a2, reinterpret_cast<float2 *>(w.a3), w.xb};
 }
 
-__device__ __forceinline__ CbpState cbp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
-    char *b = item_base(h, k);
+__device__ __forceinline__ CbpState cbp_layout(const SparseDev &g, char *b) {
     CbpState st;
     const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E), m8 = round256(8 * (int64_t)g.M);
     st.Q = (float *)b;
@@ -356,6 +355,23 @@ __device__ __forceinline__ CbpState cbp_item(const SparseDev &g, const Handoff &
     st.Om = (float2 *)(b + n4 + e4);
     st.xb = (uint8_t *)(b + n4 + e4 + m8);
     return st;
+}
+
+__device__ __forceinline__ CbpState cbp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
+    return cbp_layout(g, item_base(h, k));
+}
+
+// Copy of item k's state in LDS (the whole item, 16 bytes per thread and
+// step), for the level-parallel kernels when a frame's state fits: their row
+// accesses are scattered and each level pass waits on them, so LDS latency
+// instead of cache latency shortens every pass.  The barrier in front keeps
+// the previous item's readers ahead of the copy.
+__device__ __forceinline__ char *stage_item(const Handoff &h, uint32_t k, uint4 *lds) {
+    __syncthreads();
+    const uint4 *src = reinterpret_cast<const uint4 *>(item_base(h, k));
+    for (int64_t i = tid_x(); i < h.item_bytes / 16; i += kLevelThreads) lds[i] = src[i];
+    __syncthreads();
+    return reinterpret_cast<char *>(lds);
 }
 
 // The active lanes of the wave (rank r of na) copy lane d's slot
@@ -586,11 +602,13 @@ __device__ __forceinline__ int2 item_head(const Handoff &h, uint32_t k) {
 // sweep runs the row levels in order, the rows of a level on separate threads
 // (rows of a level share no variable, so every row sees exactly the state the
 // sequential schedule gives it and the result is the same bit for bit).
-template <bool kMin>
+// kLds: the frame's state is staged in LDS (dynamic, h.item_bytes).
+template <bool kMin, bool kLds>
 __global__ __launch_bounds__(kLevelThreads) void cbp_level_kernel(SparseDev g, uint8_t *__restrict__ bits,
                                                                   int32_t *__restrict__ iters, int max_iter,
                                                                   Params p, Handoff h) {
     __shared__ int s_flag;
+    extern __shared__ uint4 s_item[];
     const float us = kMin ? 1.0f : kLog2e;
     p.a *= us;
     p.lmax *= us;
@@ -598,7 +616,9 @@ __global__ __launch_bounds__(kLevelThreads) void cbp_level_kernel(SparseDev g, u
     for (uint32_t j = 0;; ++j) {
         const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)(gid_x() + j * gridDim.x));
         if (k >= n) break;
-        const CbpState st = cbp_item(g, h, k);
+        CbpState st;
+        if constexpr (kLds) st = cbp_layout(g, stage_item(h, k, s_item));
+        else st = cbp_item(g, h, k);
         const int2 it = item_head(h, k);
         const int64_t f = it.x;
         int t = it.y;
@@ -792,10 +812,13 @@ __device__ __forceinline__ void bp_level_rows(const int4 (&rr)[K], int nr, const
 // log2 units and the sum of the C2V messages.
 __device__ __forceinline__ float flood_posterior(float l, float us, float acc) { return l * us + acc; }
 
-__device__ __forceinline__ BpState bp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
-    char *b = item_base(h, k);
+__device__ __forceinline__ BpState bp_layout(const SparseDev &g, char *b) {
     const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E);
     return BpState{(float *)b, (float *)(b + n4), (float *)(b + n4 + e4), (uint8_t *)(b + 2 * n4 + e4)};
+}
+
+__device__ __forceinline__ BpState bp_item(const SparseDev &g, const Handoff &h, uint32_t k) {
+    return bp_layout(g, item_base(h, k));
 }
 
 __device__ __forceinline__ void hand_over_bp(const SparseDev &g, const Handoff &h, const BpState &w,
@@ -920,12 +943,13 @@ __global__ __launch_bounds__(kWave) void bp_sparse_kernel(
 // Level-parallel layered / flooding BP on handed-over frames (see
 // cbp_level_kernel).  Flooding rows only read the previous sweep's posterior
 // and add to per-variable sums in row order, which the levels keep.
-template <bool kFlood, bool kMin>
+template <bool kFlood, bool kMin, bool kLds>
 __global__ __launch_bounds__(kLevelThreads) void bp_level_kernel(SparseDev g, const float *__restrict__ llr,
                                                                  uint8_t *__restrict__ bits,
                                                                  int32_t *__restrict__ iters, int max_iter,
                                                                  Params p, Handoff h) {
     __shared__ int s_flag;
+    extern __shared__ uint4 s_item[];
     const float us = kMin ? 1.0f : kLog2e;
     p.a *= us;
     p.lmax *= us;
@@ -933,7 +957,9 @@ __global__ __launch_bounds__(kLevelThreads) void bp_level_kernel(SparseDev g, co
     for (uint32_t j = 0;; ++j) {
         const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)(gid_x() + j * gridDim.x));
         if (k >= n) break;
-        const BpState st = bp_item(g, h, k);
+        BpState st;
+        if constexpr (kLds) st = bp_layout(g, stage_item(h, k, s_item));
+        else st = bp_item(g, h, k);
         const int2 it = item_head(h, k);
         const int64_t f = it.x;
         int t = it.y;
@@ -1042,6 +1068,29 @@ SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *bas
     return w;
 }
 
+// Frames whose state takes at most this much are finished by the
+// level-parallel kernels with the state in LDS (two or more workgroups per
+// CU; larger dynamic LDS would need a raised per-kernel limit).
+constexpr int64_t kLevelLdsBytes = 64 << 10;
+
+template <bool kLds>
+static void launch_level(int algo, dim3 grid, dim3 block, size_t lds, hipStream_t s, const SparseDev &g,
+                         const float *llr, uint8_t *bits, int32_t *iters, int max_iter, const Params &p,
+                         const Handoff &h) {
+    if (algo == kCBP)
+        hipLaunchKernelGGL((cbp_level_kernel<false, kLds>), grid, block, lds, s, g, bits, iters, max_iter, p, h);
+    else if (algo == kCBPNMS)
+        hipLaunchKernelGGL((cbp_level_kernel<true, kLds>), grid, block, lds, s, g, bits, iters, max_iter, p, h);
+    else if (algo == kLBPNMS)
+        hipLaunchKernelGGL((bp_level_kernel<false, true, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+    else if (algo == kFBPNMS)
+        hipLaunchKernelGGL((bp_level_kernel<true, true, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+    else if (algo == kLBP)
+        hipLaunchKernelGGL((bp_level_kernel<false, false, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+    else
+        hipLaunchKernelGGL((bp_level_kernel<true, false, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+}
+
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
                          const SparseWs &ws, const Dump &d, unsigned long long *counter,
@@ -1071,18 +1120,10 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
         return hipErrorInvalidValue;
     if (h.lanes <= 0) return hipGetLastError();
     const dim3 lgrid((unsigned)h.groups), lblock(kLevelThreads);
-    if (algo == kCBP)
-        hipLaunchKernelGGL(cbp_level_kernel<false>, lgrid, lblock, 0, s, g, bits, iters, max_iter, p, h);
-    else if (algo == kCBPNMS)
-        hipLaunchKernelGGL(cbp_level_kernel<true>, lgrid, lblock, 0, s, g, bits, iters, max_iter, p, h);
-    else if (algo == kLBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<false, true>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
-    else if (algo == kFBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<true, true>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
-    else if (algo == kLBP)
-        hipLaunchKernelGGL((bp_level_kernel<false, false>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
+    if (h.item_bytes <= kLevelLdsBytes)
+        launch_level<true>(algo, lgrid, lblock, (size_t)h.item_bytes, s, g, llr, bits, iters, max_iter, p, h);
     else
-        hipLaunchKernelGGL((bp_level_kernel<true, false>), lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
+        launch_level<false>(algo, lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     return hipGetLastError();
 }
 
