@@ -1068,27 +1068,49 @@ SparseWs sparse_ws_carve(int algo, const SparseDev &g, int64_t frames, void *bas
     return w;
 }
 
-// Frames whose state takes at most this much are finished by the
-// level-parallel kernels with the state in LDS (two or more workgroups per
-// CU; larger dynamic LDS would need a raised per-kernel limit).
-constexpr int64_t kLevelLdsBytes = 64 << 10;
+// Frames whose state fits a workgroup's LDS (160 KB on gfx950; above 64 KB
+// the kernel's dynamic-LDS limit is raised first) are finished by the
+// level-parallel kernels with the state in LDS.
+static int64_t level_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 64 << 10;
+    return (int64_t)v - 64;  // room for the kernels' static LDS
+}
 
+template <class K>
+static bool allow_lds(K kernel, size_t bytes) {
+    return bytes <= (64u << 10) ||
+           hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes) == hipSuccess;
+}
+
+// Launches the level-parallel kernel of algo; with kLds the frame state is
+// staged in `lds` bytes of dynamic LDS.  False if that LDS cannot be granted.
 template <bool kLds>
-static void launch_level(int algo, dim3 grid, dim3 block, size_t lds, hipStream_t s, const SparseDev &g,
+static bool launch_level(int algo, dim3 grid, dim3 block, size_t lds, hipStream_t s, const SparseDev &g,
                          const float *llr, uint8_t *bits, int32_t *iters, int max_iter, const Params &p,
                          const Handoff &h) {
+#define CBP_LEVEL_LAUNCH(KERNEL, ...)                                          \
+    do {                                                                       \
+        if (kLds && !allow_lds(KERNEL, lds)) return false;                     \
+        hipLaunchKernelGGL(KERNEL, grid, block, lds, s, __VA_ARGS__);          \
+    } while (0)
     if (algo == kCBP)
-        hipLaunchKernelGGL((cbp_level_kernel<false, kLds>), grid, block, lds, s, g, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((cbp_level_kernel<false, kLds>), g, bits, iters, max_iter, p, h);
     else if (algo == kCBPNMS)
-        hipLaunchKernelGGL((cbp_level_kernel<true, kLds>), grid, block, lds, s, g, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((cbp_level_kernel<true, kLds>), g, bits, iters, max_iter, p, h);
     else if (algo == kLBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<false, true, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((bp_level_kernel<false, true, kLds>), g, llr, bits, iters, max_iter, p, h);
     else if (algo == kFBPNMS)
-        hipLaunchKernelGGL((bp_level_kernel<true, true, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((bp_level_kernel<true, true, kLds>), g, llr, bits, iters, max_iter, p, h);
     else if (algo == kLBP)
-        hipLaunchKernelGGL((bp_level_kernel<false, false, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((bp_level_kernel<false, false, kLds>), g, llr, bits, iters, max_iter, p, h);
     else
-        hipLaunchKernelGGL((bp_level_kernel<true, false, kLds>), grid, block, lds, s, g, llr, bits, iters, max_iter, p, h);
+        CBP_LEVEL_LAUNCH((bp_level_kernel<true, false, kLds>), g, llr, bits, iters, max_iter, p, h);
+#undef CBP_LEVEL_LAUNCH
+    return true;
 }
 
 hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t *bits,
@@ -1120,9 +1142,8 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
         return hipErrorInvalidValue;
     if (h.lanes <= 0) return hipGetLastError();
     const dim3 lgrid((unsigned)h.groups), lblock(kLevelThreads);
-    if (h.item_bytes <= kLevelLdsBytes)
-        launch_level<true>(algo, lgrid, lblock, (size_t)h.item_bytes, s, g, llr, bits, iters, max_iter, p, h);
-    else
+    if (h.item_bytes > level_lds_limit() ||
+        !launch_level<true>(algo, lgrid, lblock, (size_t)h.item_bytes, s, g, llr, bits, iters, max_iter, p, h))
         launch_level<false>(algo, lgrid, lblock, 0, s, g, llr, bits, iters, max_iter, p, h);
     return hipGetLastError();
 }
