@@ -50,6 +50,7 @@ VALU_PEAK_G = 256 * 4 * 2.4 / 4
 LDS_PEAK_GBS = 256 * 128 * 2.4
 PARITY_HEAD = 32768  # head of the timed batch kept for the oracle comparison
 DECODERS = ("cbp", "cbp_nms", "lbp_nms", "fbp_nms")
+NMS_ALPHAS = (0.7, 0.8, 0.85, 0.9)
 
 
 def log(*a):
@@ -186,6 +187,7 @@ def main() -> int:
 
     # ---------------- 1. Eb/N0 sweep ---------------------------------------
     sweep = {d: [] for d in DECODERS}
+    alpha_sweep = {(al, a): [] for al in ("cbp_nms", "lbp_nms") for a in NMS_ALPHAS}
     snrs = [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]
     if not args.no_sweep:
         for snr in snrs:
@@ -198,6 +200,20 @@ def main() -> int:
                 sweep[algo].append(q)
                 log(f"[bench] {snr:.2f} dB {algo:8s} FER {q['fer']:.2e} iters {q['mean_iters']:.2f} "
                     f"{q['gbps']:.1f} Gbit/s")
+            # the min-sum decoders with other normalisation factors (the paper
+            # gives none for CBP's min-sum form; 0.75 is the baselines' value)
+            for algo, a in ((al, a) for al in ("cbp_nms", "lbp_nms") for a in NMS_ALPHAS):
+                cbp.decode(handle, llr_t, MI, algo, alpha=a, out=(bits, iters), workspace=ws)
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+                for s_, e_ in ev:
+                    s_.record(stream)
+                    cbp.decode(handle, llr_t, MI, algo, alpha=a, out=(bits, iters), workspace=ws)
+                    e_.record(stream)
+                torch.cuda.synchronize()
+                t = float(np.median([s_.elapsed_time(e_) for s_, e_ in ev])) / 1e3
+                q = quality(cw_t)
+                q.update(ebn0_db=snr, seconds=t, gbps=B * K_info / t / 1e9)
+                alpha_sweep[(algo, a)].append(q)
             del llr_t, cw_t
     matched = {}
     if not args.no_sweep:
@@ -213,6 +229,17 @@ def main() -> int:
                 row["cbp_over_lbp_nms_gbps"] = round(c["gbps"] / l["gbps"], 4)
                 row["cbp_minus_lbp_nms_db"] = round(c["ebn0_db"] - l["ebn0_db"], 4)
             matched[f"fer_{T:g}"] = row
+        # each min-sum decoder's FER = 1e-3 crossing and throughput there, per alpha
+        nms_alpha = {}
+        for (algo, a), pts in alpha_sweep.items():
+            xs = [p["ebn0_db"] for p in pts]
+            x = crossing(xs, [p["fer"] for p in pts], 1e-3, 0.5 / B)
+            nms_alpha.setdefault(algo, {})[f"{a:g}"] = {
+                "fer_1e-3_ebn0_db": None if x is None else round(x, 4),
+                "gbps_there": None if x is None else round(interp(x, xs, [p["gbps"] for p in pts]), 3),
+                "sweep": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in p.items()} for p in pts]}
+            log(f"[bench] {algo} alpha {a:g}: FER 1e-3 at {x} dB")
+        matched["nms_alpha"] = nms_alpha
 
     # ---------------- 2. timed loop at the operating point ------------------
     # at CBP's FER = 1e-3 crossing (to 0.01 dB), so that `value` is CBP's
