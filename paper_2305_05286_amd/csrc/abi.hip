@@ -388,7 +388,10 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
                                       "have to undo the layer's messages)");
     r->kernel = k;
     r->p.lmax = o->lmax;
-    r->p.a = (float)phi64((double)o->lmax);
+    // lower clamp of a magnitude entering a check: phi(lmax), but never above
+    // lmax (for lmax below phi's fixed point 0.88 both clamps give lmax), so a
+    // kernel may clamp with one median-of-three
+    r->p.a = std::fmin((float)phi64((double)o->lmax), o->lmax);
     r->p.alpha = o->alpha;
     r->p.stop_rule = o->stop_rule;
     r->p.hd_mode = o->hd_mode;

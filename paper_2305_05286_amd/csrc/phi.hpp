@@ -62,9 +62,13 @@ __device__ __forceinline__ float phi2(float x) {
 }
 
 // g of a V2C magnitude (log2 units) clamped to [a2, lmax2], a2 = g(lmax2)
-// (saturation of the messages entering a check).
+// (saturation of the messages entering a check).  The host keeps a2 <= lmax2,
+// where the median of three is that clamp in one instruction.
+__device__ __forceinline__ float clamp_mag(float q, float a2, float lmax2) {
+    return __builtin_amdgcn_fmed3f(__builtin_fabsf(q), a2, lmax2);
+}
 __device__ __forceinline__ float phi2_clamped(float q, float a2, float lmax2) {
-    return phi2(__builtin_fminf(__builtin_fmaxf(__builtin_fabsf(q), a2), lmax2));
+    return phi2(clamp_mag(q, a2, lmax2));
 }
 
 // Float carrying magnitude m >= 0 with its sign bit set iff neg.
@@ -96,6 +100,27 @@ __device__ __forceinline__ float excl_sum(float Mx, float S, float f) {
 __device__ __forceinline__ void fold(float &Mx, float &S, float f) {
     S += __builtin_fminf(Mx, f);
     Mx = __builtin_fmaxf(Mx, f);
+}
+// Fold two terms at once: the two smaller of (Mx, f, g) join the rest.
+__device__ __forceinline__ void fold2(float &Mx, float &S, float f, float g) {
+    const float lo = __builtin_fminf(__builtin_fminf(Mx, f), g);
+    const float mid = __builtin_amdgcn_fmed3f(Mx, f, g);
+    Mx = __builtin_fmaxf(__builtin_fmaxf(Mx, f), g);
+    S = (S + lo) + mid;
+}
+// Two-smallest (min1 <= min2) accumulator of the min-sum rule, one term and
+// two at a time (the second smallest of {m1, m2, f, g} is min(m2, med(m1, f, g))).
+__device__ __forceinline__ void fold_min(float &m1, float &m2, float f) {
+    m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, f));
+    m1 = __builtin_fminf(m1, f);
+}
+__device__ __forceinline__ void fold_min2(float &m1, float &m2, float f, float g) {
+    m2 = __builtin_fminf(m2, __builtin_amdgcn_fmed3f(m1, f, g));
+    m1 = __builtin_fminf(__builtin_fminf(m1, f), g);
+}
+// a ^ b ^ c in one instruction
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 }  // namespace cbp

@@ -145,12 +145,14 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *opaque_s(c
 
 // Occupancy target (waves per SIMD) handed to the register allocator.  The
 // per-lane state is ~2 NB + E registers; measured on MI355X with the n=2304
-// code, CBP is fastest at 3 (168 VGPRs, a few spills outside the layer loop;
-// 2 leaves the SIMDs idle at the barriers, 4 spills in the loop), layered
-// min-sum at 4, flooding min-sum and min-sum CBP at 3.
-template <int kAlgo>
+// code, CBP is fastest at 3 (160 VGPRs; 2 leaves the SIMDs idle at the
+// barriers, 4 spills in the loop), layered min-sum and min-sum CBP at 4
+// (128 VGPRs; min-sum CBP 7% faster than at 3), flooding min-sum at 3.  The
+// instantiations that also serve the dumps and the paper's stopping rule
+// stay at 3 (at 4 the allocator gives up on them).
+template <int kAlgo, bool kDbg>
 constexpr int waves_per_simd() {
-    return kAlgo == kLBPNMS ? 4 : 3;
+    return (kAlgo == kLBPNMS || (kAlgo == kCBPNMS && !kDbg)) ? 4 : 3;
 }
 
 // (x mod Z) for x in (-Z, 2Z)
@@ -171,7 +173,7 @@ __device__ __forceinline__ int wrap_lo(int x) {
 // the production instantiation carries neither (cold code still costs
 // registers in a kernel this close to its register budget).
 template <class G, int kAlgo, bool kDbg>
-__global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) void qc_reg_kernel(QcArgs<G> A) {
+__global__ __launch_bounds__(slots_for<G>() * G::Z, (waves_per_simd<kAlgo, kDbg>())) void qc_reg_kernel(QcArgs<G> A) {
     using TT = TabOf<G>;
     constexpr int MB = G::MB, NB = G::NB, Z = G::Z, E = count_edges<G>();
     constexpr int SL = slots_for<G>(), DCM = TT::T.dcmax;
@@ -186,6 +188,15 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
     // stored twice ([i] and [i + Z]) so that every rotated read (index i + s,
     // 0 <= i, s < Z) needs no wrap-around.
     __shared__ float2 sOm[kBelief ? SL : 1][kBelief ? MB * Z : 1];
+    // Row of the latest check's block-row that lane l meets at edge e,
+    // (l - s) mod Z for that check's shift s: the same for every frame and
+    // sweep, so it is worked out once per launch and each B2V read costs one
+    // byte load instead of a wrap-around in VALU.
+    // (Log-tanh CBP only: min-sum CBP runs at four waves per SIMD, where
+    // these E*Z bytes would cost a workgroup per CU.)
+    constexpr bool kKp = kAlgo == kCBP;
+    static_assert(!kKp || Z <= 256, "row indices are stored as bytes");
+    __shared__ uint8_t sKp[kKp ? E : 1][kKp ? Z : 1];
     __shared__ float2 sRow[kBelief ? 1 : SL][kBelief ? 1 : 2 * Z];
     __shared__ float sX[SL][DCM][2 * Z];
     __shared__ Mask sXB[SL][2 * Z];
@@ -232,8 +243,23 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
             if (v < 0.0f) xb |= Mask(1) << b;
         });
         static_for<0, E>([&](auto ec) { R[decltype(ec)::value] = 0.0f; });
+        if constexpr (kBelief) {
+            // A variable's first visit in a frame has no latest check and its
+            // B2V message is 0 (Step 1's infinite belief only seeds the C2B
+            // fold).  A stored belief whose exclusion is +inf (log-tanh: g(inf)
+            // = 0) or whose two smallest terms are 0 (min-sum) yields exactly
+            // that 0, so the first sweep needs no test of its own; its first
+            // visits also commit that 0 to R, which already holds 0.
+            const float z = kAlgo == kCBP ? __builtin_inff() : 0.0f;
+            static_for<0, MB>([&](auto rc) { sOm[slot][decltype(rc)::value * Z + l] = make_float2(z, z); });
+        }
     };
 
+    if constexpr (kKp)
+        for (int i = tid_x(); i < E * Z; i += SL * Z) {
+            const int e = i / Z, k = i - e * Z;
+            sKp[e][k] = (uint8_t)wrap_lo<Z>(k - A.sht[E + e]);
+        }
     if (l == 0) sF[slot] = atomicAdd(A.counter, 1u);
     __syncthreads();
     f = sF[slot];
@@ -299,7 +325,6 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
         if (anyFresh) continue;  // pre-check the new frames first
 
         // ---------------- one sweep over the layers -------------------------
-        const bool first = (t == 0);
         static_for<0, MB>([&](auto rc) {
             constexpr int r = rc;
             constexpr int e0 = TT::T.rstart[r], e1 = TT::T.rstart[r + 1];
@@ -314,7 +339,10 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 if constexpr (kBelief) {
                     constexpr int ep = TT::T.epred[e], rp = TT::T.er[ep];
                     // B2V (eq. equ_s4e18) from the latest check's belief
-                    const float2 om = sOm[slot][rp * Z + wrap_lo<Z>(lv - sh[E + e])];
+                    int kp;
+                    if constexpr (kKp) kp = sKp[e][lv];
+                    else kp = wrap_lo<Z>(lv - sh[E + e]);
+                    const float2 om = sOm[slot][rp * Z + kp];
                     float rn;
                     if constexpr (kAlgo == kCBP) {
                         const float dd = excl_sum(abs_bits(om.x), om.y, PQ[b]);
@@ -324,12 +352,7 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                         const float m1 = abs_bits(om.x);
                         rn = or_sign(alpha * ((aq == m1) ? om.y : m1), fbits(om.x) ^ fbits(Q[b]));
                     }
-                    if constexpr (TT::T.efirst[e]) {
-                        rn = first ? 0.0f : rn;       // no latest check yet
-                        R[ep] = first ? R[ep] : rn;   // commit R(c_j -> v) first
-                    } else {
-                        R[ep] = rn;
-                    }
+                    R[ep] = rn;                       // commit R(c_j -> v) first
                     const float lam = Q[b] + rn;      // eq. equ_s4e20
                     xb = (xb & ~(Mask(1) << b)) | (Mask(fbits(lam) >> 31) << b);  // [lam < 0]
                     if constexpr (kStop) {
@@ -366,25 +389,38 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, waves_per_simd<kAlgo>()) voi
                 uint32_t par = 0;
                 const int lr = opaque_v(l);
                 const auto shr = opaque_s(A.sht);
+                // the row's entries two at a time (a lone last one for odd degree)
+                constexpr int D = e1 - e0;
+                auto entry = [&](auto jc) { return sX[slot][decltype(jc)::value][lr + shr[e0 + decltype(jc)::value]]; };
                 if constexpr (!kMinRow) {
                     float Mx = 0.0f, Sr = 0.0f;
-                    static_for<0, e1 - e0>([&](auto jc) {
-                        constexpr int j = jc;
-                        const float x = sX[slot][j][lr + shr[e0 + j]];
-                        par ^= fbits(x);
-                        fold(Mx, Sr, abs_bits(x));    // C2B, eq. equ_s4e21
+                    static_for<0, D / 2>([&](auto pc) {
+                        constexpr int j = 2 * pc;
+                        const float x = entry(std::integral_constant<int, j>{});
+                        const float y = entry(std::integral_constant<int, j + 1>{});
+                        par = xor3(par, fbits(x), fbits(y));
+                        fold2(Mx, Sr, abs_bits(x), abs_bits(y));  // C2B, eq. equ_s4e21
                     });
+                    if constexpr (D % 2) {
+                        const float x = entry(std::integral_constant<int, D - 1>{});
+                        par ^= fbits(x);
+                        fold(Mx, Sr, abs_bits(x));
+                    }
                     sOm[slot][r * Z + l] = make_float2(or_sign(Mx, par), Sr);  // eq. equ_s4e23
                 } else {
                     float m1 = __builtin_inff(), m2 = __builtin_inff();
-                    static_for<0, e1 - e0>([&](auto jc) {
-                        constexpr int j = jc;
-                        const float x = sX[slot][j][lr + shr[e0 + j]];
-                        par ^= fbits(x);
-                        const float ax = abs_bits(x);
-                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
-                        m1 = __builtin_fminf(m1, ax);
+                    static_for<0, D / 2>([&](auto pc) {
+                        constexpr int j = 2 * pc;
+                        const float x = entry(std::integral_constant<int, j>{});
+                        const float y = entry(std::integral_constant<int, j + 1>{});
+                        par = xor3(par, fbits(x), fbits(y));
+                        fold_min2(m1, m2, abs_bits(x), abs_bits(y));
                     });
+                    if constexpr (D % 2) {
+                        const float x = entry(std::integral_constant<int, D - 1>{});
+                        par ^= fbits(x);
+                        fold_min(m1, m2, abs_bits(x));
+                    }
                     const float2 rs = make_float2(or_sign(m1, par), m2);
                     if constexpr (kBelief) {
                         sOm[slot][r * Z + l] = rs;  // C2B, eq. equ_s4e21xx
