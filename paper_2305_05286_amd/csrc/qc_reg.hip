@@ -276,15 +276,22 @@ __global__ __launch_bounds__(slots_for<G>() * G::Z, (waves_per_simd<kAlgo, kDbg>
         uint32_t bad = 0;
         static_for<0, MB>([&](auto rc) {
             constexpr int r = rc;
-            uint32_t par = 0;
+            constexpr int e0 = TT::T.rstart[r], D = TT::T.rstart[r + 1] - e0;
             const int lv = opaque_v(l);
             const auto sh = opaque_s(A.sht);
-            static_for<TT::T.rstart[r], TT::T.rstart[r + 1]>([&](auto ec) {
+            // row l meets lane l + s; bit 0 of the XOR of the words shifted
+            // down by their block-columns is the row's parity, two at a time
+            auto word = [&](auto ec) {
                 constexpr int e = ec;
-                constexpr int b = TT::T.eb[e];
-                par ^= (uint32_t)(sXB[slot][lv + sh[e]] >> b) & 1u;  // row l meets lane l + s
+                return (uint32_t)(sXB[slot][lv + sh[e]] >> TT::T.eb[e]);
+            };
+            uint32_t par = 0;
+            static_for<0, D / 2>([&](auto pc) {
+                constexpr int e = e0 + 2 * pc;
+                par = xor3(par, word(std::integral_constant<int, e>{}), word(std::integral_constant<int, e + 1>{}));
             });
-            bad |= par;
+            if constexpr (D % 2) par ^= word(std::integral_constant<int, e0 + D - 1>{});
+            bad |= par & 1u;
         });
         if (bad) sBad[pb][slot] = 1;
         __syncthreads();
