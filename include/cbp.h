@@ -82,6 +82,17 @@ int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
 #define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, persistent (lanes take new  */
                                /* frames as theirs stop), state per wave contiguous      */
+#define CBP_KERNEL_SPARSE_LDS 8 /* any H whose frame state (CBP: 4N + 4E + 8M + N bytes, */
+                               /* rounded) fits a CU's LDS: several frames per workgroup */
+                               /* staged in LDS, each sweep level by level (see          */
+                               /* cbp_code_levels), the edges of a level on separate     */
+                               /* threads; persistent.  cbp_decode only, with stop_rule  */
+                               /* 0 or 2, hd_mode 0 and no dumps (else                   */
+                               /* CBP_EUNSUPPORTED).  Results are bit-identical to       */
+                               /* CBP_KERNEL_SPARSE.  AUTO picks it for a code that has  */
+                               /* no QC layout when the options and the state allow.     */
+                               /* CBP_SPARSE_LDS_FRAMES (>= 1) in the environment caps   */
+                               /* the frames per workgroup (tuning).                     */
 /* Sparse kernel, slow frames: once every frame of the batch has been taken, a
  * wave with at most 16 busy lanes (CBP_SPARSE_HANDOFF in the environment:
  * 0 = never, 1..64) copies their frames into the workspace and a second launch

@@ -17,7 +17,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 BUILD = PKG / "_build"
 LIB = PKG / "libcbp.so"
-SOURCES = ["abi.hip", "sparse.hip", "qc_reg.hip", "qc_stream.hip", "unrolled.hip"]
+SOURCES = ["abi.hip", "sparse.hip", "sparse_lds.hip", "qc_reg.hip", "qc_stream.hip", "unrolled.hip"]
 ARCH = os.environ.get("CBP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

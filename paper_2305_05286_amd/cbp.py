@@ -19,7 +19,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libcbp.so"
 
 CBP_OK, CBP_EINVAL, CBP_EUNSUPPORTED, CBP_EHIP, CBP_ENOMEM = 0, -1, -2, -3, -4
-KERNELS = {"auto": 0, "qc_reg": 1, "qc_stream": 2, "sparse": 4}
+KERNELS = {"auto": 0, "qc_reg": 1, "qc_stream": 2, "sparse": 4, "sparse_lds": 8}
 RULES = {"log_tanh": 0, "min_sum": 1}
 DECODERS = {"cbp": 0, "lbp_nms": 1, "fbp_nms": 2, "lbp": 3, "fbp": 4}
 

@@ -250,7 +250,8 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         // level pointers, then (16-byte aligned) one int4 per row in level order
         const size_t lvl_pad = (4 - ((size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() +
                                      (size_t)c->nlev + 1) % 4) % 4;
-        const size_t lvl_ints = (size_t)c->nlev + 1 + lvl_pad + 4 * (size_t)M;
+        // then one int4 per edge in the same order, then the level edge pointers
+        const size_t lvl_ints = (size_t)c->nlev + 1 + lvl_pad + 4 * (size_t)M + 4 * (size_t)E + (size_t)c->nlev + 1;
         const size_t ints =
             (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() + lvl_ints;
         const size_t bytes = ints * 4 + (size_t)E + P + 64;
@@ -302,6 +303,24 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
             p[4 * k + 2] = c->row_ptr[i + 1];
             p[4 * k + 3] = 0;
         }
+        p += 4 * (size_t)M;
+        {
+            int *eptr = p + 4 * (size_t)E;
+            int64_t k = 0;
+            for (int l = 0; l < c->nlev; ++l) {
+                eptr[l] = (int)k;
+                for (int r = c->lvl_ptr[l]; r < c->lvl_ptr[l + 1]; ++r) {
+                    const int i = c->lvl_rows[r];
+                    for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e, ++k) {
+                        p[4 * k] = c->col_idx[e];
+                        p[4 * k + 1] = c->pred_edge[e];
+                        p[4 * k + 2] = c->pred_row[e];
+                        p[4 * k + 3] = e | (int)((uint32_t)c->first[e] << 30);
+                    }
+                }
+            }
+            eptr[c->nlev] = (int)k;
+        }
         e = hipMemcpy(buf, host.data(), ints * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) {
             std::vector<uint8_t> fp(c->first);
@@ -335,6 +354,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         t.g.lvl_ptr = d;
         d += c->nlev + 1 + lvl_pad;
         t.g.lvl_rows = reinterpret_cast<const int4 *>(d);
+        d += 4 * (size_t)M;
+        t.g.lvl_edges = reinterpret_cast<const int4 *>(d);
+        d += 4 * (size_t)E;
+        t.g.lvl_eptr = d;
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;
@@ -354,6 +377,16 @@ struct Resolved {
     size_t ws_bytes;
 };
 
+// True if the LDS-staged CSR kernel serves algo on this code: at least one
+// frame's state fits the LDS of a gfx950 workgroup.
+bool lds_kernel_fits(int algo, const cbp_code_t *code) {
+    SparseDev g{};
+    g.M = code->M;
+    g.N = code->N;
+    g.E = code->E < ((int64_t)1 << 30) ? (int)code->E : (1 << 30);
+    return lds_frames(lds_item(algo, g), kLdsPlanBytes) >= 1;
+}
+
 int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts_t *o, Resolved *r) {
     cbp_opts_t def;
     cbp_opts_default(&def);
@@ -372,16 +405,28 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     if (o->dump_sweep < 0 || o->dump_frames < 0) return fail(CBP_EINVAL, "negative dump option");
     int k = o->kernel;
     const bool stream_ok = code->qc && code->Z <= 1024 && code->mb < 32768 && code->nb < 65536;
+    // the LDS-staged CSR kernel: the one-frame-per-lane kernel's results, for
+    // the syndrome stop or fixed sweeps, decisions of Step 3, no dumps
+    const bool lds_opts = o->stop_rule != 1 && o->hd_mode == 0 && (o->dump_sweep == 0 || o->dump_frames == 0);
+    const bool lds_fits = lds_kernel_fits(algo, code);
     if ((algo == kLBP || algo == kFBP) && k != CBP_KERNEL_AUTO && k != CBP_KERNEL_SPARSE)
         return fail(CBP_EUNSUPPORTED, "lbp_decode and fbp_decode run on the sparse kernel only");
     if (algo == kLBP || algo == kFBP) k = CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_AUTO)
-        k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : stream_ok ? CBP_KERNEL_QC_STREAM : CBP_KERNEL_SPARSE;
+        k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG
+            : stream_ok          ? CBP_KERNEL_QC_STREAM
+            : (lds_fits && lds_opts) ? CBP_KERNEL_SPARSE_LDS
+                                     : CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_QC_REG && code->qc_reg_id < 0)
         return fail(CBP_EUNSUPPORTED, "no register-resident kernel is compiled for this base pattern");
     if (k == CBP_KERNEL_QC_STREAM && !stream_ok)
         return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024, mb < 32768, nb < 65536");
-    if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE)
+    if (k == CBP_KERNEL_SPARSE_LDS && !lds_fits)
+        return fail(CBP_EUNSUPPORTED, "the LDS-staged kernel serves cbp_decode on codes whose frame state fits "
+                                      "a CU's LDS");
+    if (k == CBP_KERNEL_SPARSE_LDS && !lds_opts)
+        return fail(CBP_EUNSUPPORTED, "the LDS-staged kernel runs with stop_rule 0 or 2, hd_mode 0 and no dumps");
+    if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE && k != CBP_KERNEL_SPARSE_LDS)
         return fail(CBP_EINVAL, "unknown kernel %d", o->kernel);
     if (o->stop_rule == 1 && o->hd_mode == 1 && k != CBP_KERNEL_SPARSE)
         return fail(CBP_EUNSUPPORTED, "stop_rule 1 with hd_mode 1 needs the sparse kernel (a mid-layer stop would "
@@ -540,7 +585,7 @@ SparsePlan sparse_plan_fit(int algo, const SparseDev &g, int64_t batch, bool han
 
 size_t needed_ws(int algo, const cbp_code_t *code, const SparseDev &g, int kernel, int64_t batch,
                  bool handoff) {
-    if (kernel == CBP_KERNEL_QC_REG) return 256;
+    if (kernel == CBP_KERNEL_QC_REG || kernel == CBP_KERNEL_SPARSE_LDS) return 256;
     if (kernel == CBP_KERNEL_QC_STREAM) {
         const StreamLaunch L = single_stream(algo, code, batch);
         return 256 + (size_t)L.groups * L.group_bytes;
@@ -625,6 +670,8 @@ int decode(int algo, const cbp_code_t *code, const float *llr, uint8_t *bits, in
     if (r.kernel == CBP_KERNEL_QC_REG) {
         e = launch_qc_reg(code->qc_reg_id, algo, qc_sht, llr, bits, iters, batch,
                           max_iter, r.p, r.d, (int *)ws, dev, s);
+    } else if (r.kernel == CBP_KERNEL_SPARSE_LDS) {
+        e = launch_sparse_lds(algo, *g, llr, bits, iters, batch, max_iter, r.p, (unsigned int *)ws, dev, s);
     } else if (r.kernel == CBP_KERNEL_QC_STREAM) {
         StreamLaunch L = single_stream(algo, code, batch);
         L.codes = tab->sc_dev;
@@ -1254,7 +1301,8 @@ int cbp_code_info(const cbp_code_t *c, int32_t *M, int32_t *N, int64_t *E, int32
     if (Z) *Z = c->qc ? c->Z : 0;
     if (kernels)
         *kernels = CBP_KERNEL_SPARSE | (c->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG : 0) |
-                   (c->qc && c->Z <= 1024 && c->mb < 32768 && c->nb < 65536 ? CBP_KERNEL_QC_STREAM : 0);
+                   (c->qc && c->Z <= 1024 && c->mb < 32768 && c->nb < 65536 ? CBP_KERNEL_QC_STREAM : 0) |
+                   (lds_kernel_fits(kCBP, c) ? CBP_KERNEL_SPARSE_LDS : 0);
     return CBP_OK;
 }
 

@@ -65,6 +65,9 @@ struct SparseDev {
     int nlev;             // row levels (rows of one level share no variable)
     const int *lvl_ptr;   // [nlev+1] first entry of each level in lvl_rows
     const int4 *lvl_rows; // [M] (row, first edge, end edge, 0) by (level, index)
+    const int *lvl_eptr;  // [nlev+1] first entry of each level in lvl_edges
+    const int4 *lvl_edges;// [E] the edges of lvl_rows' rows in that order: (column,
+                          //      pred_edge, pred_row, edge | first << 30)
 };
 
 // col_idx, pred_edge, pred_row and first are readable (zeros) for this many
@@ -115,6 +118,26 @@ hipError_t launch_sparse(int algo, const SparseDev &g, const float *llr, uint8_t
                          const Handoff &h, hipStream_t s);
 hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok, int64_t batch,
                            hipStream_t s);
+
+// ---- CSR codes with each frame's state in LDS ------------------------------
+// Byte offsets of one frame's arrays in LDS: Q [N] at 0, R [E] at r, beliefs
+// [M] (float2) at om, decisions [N] at xb; bytes = 0 if the algorithm has no
+// such kernel.
+struct LdsItem {
+    int r, om, xb, bytes;
+};
+constexpr int kLdsMaxFrames = 8;       // frames per workgroup
+constexpr int64_t kLdsStaticBytes = 256;  // the kernel's own LDS (slot table)
+// Planning limit of a workgroup's LDS (gfx950: 160 KiB per CU); the launch
+// uses the device's own figure.
+constexpr int64_t kLdsPlanBytes = (int64_t)160 << 10;
+LdsItem lds_item(int algo, const SparseDev &g);
+// Frames per workgroup that fit in lds_limit bytes (0: none).
+int lds_frames(const LdsItem &it, int64_t lds_limit);
+// Persistent launch over frames 0 .. nf-1 (counter: 4 bytes, reset by the call).
+hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters,
+                             int64_t nf, int max_iter, const Params &p, unsigned int *counter, int device,
+                             hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 // *pos (8 bytes, reset by the call) = flat index of the first NaN / +-Inf
 // among x[0 .. n), or all ones if there is none.

@@ -11,6 +11,7 @@
 // wave leaves its loop once the batch is exhausted and every lane is done.
 #include "internal.hpp"
 #include "phi.hpp"
+#include "sparse_rules.hpp"
 
 namespace cbp {
 namespace {
@@ -90,18 +91,6 @@ __device__ __forceinline__ int64_t claim_frames(unsigned long long *counter, uin
 // LLRs in log2 units (L / ln2), where phi2 serves both directions of the
 // check rule; Params a and lmax arrive already scaled.
 // --------------------------------------------------------------------------
-// C2V of a check recovered from its belief (om = max term or min1 with the
-// parity in its sign bit, os = rest of the sum or min2), excluding q.
-template <bool kMin>
-__device__ float b2v(float om, float os, float q, const Params &p) {
-    if constexpr (!kMin) {
-        return with_sign(phi2(excl_sum(abs_bits(om), os, phi2_clamped(q, p.a, p.lmax))), sign_bit(om) ^ (q < 0.0f));
-    } else {
-        const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-        const float m1 = abs_bits(om);
-        return with_sign(p.alpha * ((aq == m1) ? os : m1), sign_bit(om) ^ (q < 0.0f));
-    }
-}
 
 template <bool kMin>
 __device__ float cbp_flushed(const SparseDev &g, const SparseWs &w, uint32_t lf, int v, const Params &p) {

@@ -1,0 +1,344 @@
+// Any parity-check matrix (CSR) with each frame's whole state in LDS.
+//
+// A workgroup holds kF frames (Q [N], R [E], beliefs [M], decisions [N] of
+// each) in LDS and runs their sweeps together, level by level: the rows of
+// one level share no variable, so they commute in the paper's sequential row
+// order (Sec. IV-C) and are updated at once with exactly the sequential
+// result.  Within a level the work is split by edge, not by row, which gives
+// the threads five to six times more independent items than rows alone:
+//   phase A (thread = one edge of one frame): B2V from the latest check's
+//            belief and its commit, V2C, the decision at the variable's last
+//            visit, and the edge's check-rule term, parked in the edge's own
+//            R slot (its old C2V message has just been read, and the next
+//            visit of the variable overwrites it by its commit first);
+//   phase B (thread = one row of one frame): the row's terms folded in
+//            ascending column order into its new belief.
+// Per edge these are the very instructions of the one-frame-per-lane kernel
+// (the same check-rule functions, the same fold order), so the two layouts
+// agree bit for bit.  Within a phase nothing one item writes is read by
+// another: a level's rows share no variable, a commit goes to the R slot of a
+// row in another level, and a belief read is of another level's row (in a
+// weight-one column, of the row itself, whose new belief phase B stores after
+// the barrier).  A CU holds several workgroups (one or a few frames each)
+// rather than one large one: their barriers are independent, so one
+// workgroup's wait is covered by another's work (measured on the PEG codes:
+// three one-frame workgroups per CU decode 1.6x faster than one workgroup of
+// three frames).  The grid is persistent: a slot whose frame stops writes the
+// outputs and loads the next frame of the batch from a global counter; a
+// fresh frame is syndrome-tested before its first sweep.  Every branch that
+// contains a barrier is taken by the whole workgroup (its condition comes
+// from LDS after a barrier).
+#include <cstdlib>
+
+#include "internal.hpp"
+#include "phi.hpp"
+#include "sparse_rules.hpp"
+
+namespace cbp {
+namespace {
+
+constexpr int kLdsFillBlock = 256;
+constexpr int kLdsChunk = 8;  // loads of a row issued together
+constexpr int kLdsCuThreads = 2048;
+
+__global__ __launch_bounds__(kLdsFillBlock) void lds_zero_kernel(unsigned int *p) {
+    if (tid_x() == 0) *p = 0u;
+}
+
+// kMin: the normalized min-sum check rule (beliefs = (min1 | parity, min2)).
+// kT threads per workgroup.
+template <bool kMin, int kF, int kT>
+__global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *__restrict__ llr,
+                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                     int64_t nf, int max_iter, Params p, unsigned int *counter,
+                                                     LdsItem it) {
+    extern __shared__ uint4 s_dyn[];
+    __shared__ int64_t sFrame[kF];
+    __shared__ int sT[kF], sBad[kF], sFresh[kF];
+    const int tid = tid_x();
+    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
+    p.a *= us;
+    p.lmax *= us;
+    char *const base = reinterpret_cast<char *>(s_dyn);
+    auto Qp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes); };
+    auto Rp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.r); };
+    auto Op = [&](int f) { return reinterpret_cast<float2 *>(base + f * it.bytes + it.om); };
+    auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
+
+    // Step 2(1) a-e on edge e (record rec) of frame slot f.  s1: bit f set
+    // while slot f runs its first sweep.
+    uint32_t s1 = 0;
+    auto edge = [&](int f, const int4 &rec) {
+        const int col = rec.x, pe = rec.y, pr = rec.z, e = rec.w & 0x3fffffff;
+        const uint32_t fl = (uint32_t)rec.w >> 30;
+        float *Q = Qp(f), *R = Rp(f);
+        const float q = Q[col];
+        float rc = R[e];
+        const float2 om = Op(f)[pr];
+        float rn = 0.0f;
+        // no latest check yet on a variable's first visit of the first sweep
+        if (!(((s1 >> f) & 1u) && (fl & kFirstVisit))) {
+            rn = b2v<kMin>(om.x, om.y, q, p);  // B2V, eq. equ_s4e18
+            R[pe] = rn;                         // commit R(c_j -> v) first
+            if (pe == e) rc = rn;
+        }
+        const float lam = q + rn;  // eq. equ_s4e20
+        if (fl & kLastVisit) Xp(f)[col] = lam < 0.0f;
+        const float qn = lam - rc;  // V2C, eq. equ_s4e19
+        Q[col] = qn;
+        const float term = kMin ? __builtin_fminf(__builtin_fabsf(qn), p.lmax) : phi2_clamped(qn, p.a, p.lmax);
+        R[e] = with_sign(term, qn < 0.0f);
+    };
+    // Step 2(1)d / 2(2) for row rr = (row, first edge, end edge) of slot f:
+    // the terms folded in ascending column order into the new belief (C2B,
+    // eqs. equ_s4e21 / equ_s4e23), kLdsChunk loads at a time (indices past the
+    // row clamped to its last edge)
+    auto row_fold = [&](int f, const int4 &rr) {
+        const float *R = Rp(f);
+        float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
+        bool par = false;
+        for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
+            float x[kLdsChunk];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) x[c] = R[c0 + c < rr.z ? c0 + c : rr.z - 1];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) {
+                if (c0 + c < rr.z) {
+                    par ^= sign_bit(x[c]);
+                    const float ax = abs_bits(x[c]);
+                    if constexpr (!kMin) {
+                        fold(Mx, Sr, ax);
+                    } else {
+                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, ax));
+                        Mx = __builtin_fminf(Mx, ax);
+                    }
+                }
+            }
+        }
+        Op(f)[rr.x] = make_float2(with_sign(Mx, par), Sr);
+    };
+
+    if (tid < kF) {
+        sFrame[tid] = (int64_t)atomicAdd(counter, 1u);
+        sT[tid] = 0;
+        sFresh[tid] = 1;
+    }
+    __syncthreads();
+    // Step 1 for every fresh slot: latest V2C = channel LLR, R = 0, x = [L < 0]
+    auto load = [&]() {
+        for (int f = 0; f < kF; ++f) {
+            const int64_t fr = sFrame[f];
+            if (!sFresh[f] || fr >= nf) continue;
+            float *Q = Qp(f), *R = Rp(f);
+            uint8_t *xb = Xp(f);
+            for (int v = tid; v < g.N; v += kT) {
+                const float l = llr[fr * g.N + v] * us;
+                Q[v] = l;
+                xb[v] = l < 0.0f;
+            }
+            for (int e = tid; e < g.E; e += kT) R[e] = 0.0f;
+        }
+    };
+    load();
+    __syncthreads();
+    for (;;) {
+        // ---------------- syndrome of every live slot's decisions ------------
+        if (tid < kF) sBad[tid] = 0;
+        __syncthreads();
+        uint32_t live = 0;
+        for (int f = 0; f < kF; ++f) live |= (uint32_t)(sFrame[f] < nf) << f;
+        // a row per thread, its column and decision loads issued together (the
+        // column table is padded past E; entries past the row name other
+        // columns and are masked)
+        for (int i = tid; i < kF * g.M; i += kT) {
+            const int j = i / kF, f = i - j * kF;
+            if (!((live >> f) & 1u)) continue;
+            const uint8_t *xb = Xp(f);
+            const int e0 = g.row_ptr[j], e1 = g.row_ptr[j + 1];
+            uint32_t par = 0;
+            for (int c0 = e0; c0 < e1; c0 += kLdsChunk) {
+                int col[kLdsChunk];
+                uint32_t x[kLdsChunk];
+#pragma unroll
+                for (int c = 0; c < kLdsChunk; ++c) col[c] = g.col_idx[c0 + c];
+#pragma unroll
+                for (int c = 0; c < kLdsChunk; ++c) x[c] = xb[col[c]];
+#pragma unroll
+                for (int c = 0; c < kLdsChunk; ++c) par ^= c0 + c < e1 ? x[c] : 0u;
+            }
+            if (par) sBad[f] = 1;
+        }
+        __syncthreads();
+        // ---------------- stopped frames out, next frames in -----------------
+        uint32_t done = 0;
+        for (int f = 0; f < kF; ++f)
+            if (((live >> f) & 1u) && ((p.stop_rule == 0 && sBad[f] == 0) || sT[f] >= max_iter))
+                done |= 1u << f;
+        for (int f = 0; f < kF; ++f) {
+            if (!((done >> f) & 1u)) continue;
+            const int64_t fr = sFrame[f];
+            const uint8_t *xb = Xp(f);
+            for (int v = tid; v < g.N; v += kT) bits[fr * g.N + v] = xb[v];
+            if (tid == 0) iters[fr] = sT[f];
+        }
+        __syncthreads();  // every thread has read sFrame / sT before they change
+        if (tid < kF) {
+            const bool d = (done >> tid) & 1u;
+            if (d) {
+                sFrame[tid] = (int64_t)atomicAdd(counter, 1u);
+                sT[tid] = 0;
+            }
+            sFresh[tid] = d;
+        }
+        __syncthreads();
+        load();
+        __syncthreads();
+        live = 0;
+        uint32_t fresh = 0;
+        s1 = 0;
+        for (int f = 0; f < kF; ++f) {
+            const bool on = sFrame[f] < nf;
+            live |= (uint32_t)on << f;
+            fresh |= (uint32_t)(on && sFresh[f] != 0) << f;
+            s1 |= (uint32_t)(sT[f] == 0) << f;
+        }
+        if (!live) break;
+        if (fresh) continue;  // test the new frames before they sweep
+
+        // ---------------- one sweep, level by level ---------------------------
+        // Each phase reads its thread's first table record one phase ahead, so
+        // that the table latency overlaps the work before the barrier.
+        int4 recA = make_int4(0, 0, 0, 0), recB = make_int4(0, 0, 0, 0);
+        {
+            const int ea = ldc(g.lvl_eptr, 0);
+            if (tid < kF * (ldc(g.lvl_eptr, 1) - ea)) recA = g.lvl_edges[ea + tid / kF];
+        }
+        for (int l = 0; l < g.nlev; ++l) {
+            // phase A: thread = (edge of the level, frame)
+            const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
+            const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
+            if (tid < kF * rows) recB = g.lvl_rows[ra + tid / kF];
+            for (int i = tid; i < kF * en; i += kT) {
+                const int j = i / kF, f = i - j * kF;
+                if (!((live >> f) & 1u)) continue;
+                edge(f, i == tid ? recA : g.lvl_edges[ea + j]);
+            }
+            __syncthreads();
+            // phase B: thread = (row of the level, frame)
+            if (l + 1 < g.nlev) {
+                const int eb = ldc(g.lvl_eptr, l + 1);
+                if (tid < kF * (ldc(g.lvl_eptr, l + 2) - eb)) recA = g.lvl_edges[eb + tid / kF];
+            }
+            for (int i = tid; i < kF * rows; i += kT) {
+                const int j = i / kF, f = i - j * kF;
+                if (!((live >> f) & 1u)) continue;
+                row_fold(f, i == tid ? recB : g.lvl_rows[ra + j]);
+            }
+            __syncthreads();
+        }
+        if (tid < kF && ((live >> tid) & 1u)) ++sT[tid];
+    }
+}
+
+template <bool kMin, int kF, int kT>
+hipError_t launch_ft(const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters, int64_t nf,
+                     int max_iter, const Params &p, unsigned int *counter, const LdsItem &it, int groups,
+                     hipStream_t s) {
+    const size_t lds = (size_t)kF * (size_t)it.bytes;
+    auto *k = cbp_lds_kernel<kMin, kF, kT>;
+    if (lds > (64u << 10)) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(kT), lds, s, g, llr, bits, iters, nf, max_iter, p, counter,
+                       it);
+    return hipGetLastError();
+}
+
+template <bool kMin, int kT>
+hipError_t launch_t(int F, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters, int64_t nf,
+                    int max_iter, const Params &p, unsigned int *counter, const LdsItem &it, int groups,
+                    hipStream_t s) {
+#define CBP_LDS_F(n) \
+    case n: return launch_ft<kMin, n, kT>(g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
+    switch (F) {
+        CBP_LDS_F(1);
+        CBP_LDS_F(2);
+        CBP_LDS_F(3);
+        CBP_LDS_F(4);
+        CBP_LDS_F(5);
+        CBP_LDS_F(6);
+        CBP_LDS_F(7);
+        CBP_LDS_F(8);
+    default: return hipErrorInvalidValue;
+    }
+#undef CBP_LDS_F
+}
+
+int64_t align16(int64_t x) { return (x + 15) / 16 * 16; }
+
+}  // namespace
+
+LdsItem lds_item(int algo, const SparseDev &g) {
+    LdsItem it{};
+    if (algo != kCBP && algo != kCBPNMS) return it;  // bytes = 0: not available
+    const int64_t q = align16(4 * (int64_t)g.N), r = align16(4 * (int64_t)g.E), om = 8 * (int64_t)g.M,
+                  xb = align16(g.N);
+    const int64_t total = align16(q + r + om + xb);
+    if (total >= ((int64_t)1 << 31)) return it;
+    it.r = (int)q;
+    it.om = (int)(q + r);
+    it.xb = (int)(q + r + om);
+    it.bytes = (int)total;
+    return it;
+}
+
+int lds_frames(const LdsItem &it, int64_t lds_limit) {
+    if (it.bytes <= 0) return 0;
+    const int64_t f = (lds_limit - kLdsStaticBytes) / it.bytes;
+    return (int)(f < kLdsMaxFrames ? f : kLdsMaxFrames);
+}
+
+// Geometry: frames per CU that fit (LDS per CU = the per-workgroup maximum on
+// gfx950).  Four or more: workgroups of 512 threads, four per CU, each with
+// its share of the frames (at most kLdsMaxFrames); two or three: one frame per
+// workgroup of 512 threads; one: one workgroup of 1024 threads.
+// CBP_SPARSE_LDS_FRAMES in the environment caps the frames per workgroup.
+hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters,
+                             int64_t nf, int max_iter, const Params &p, unsigned int *counter, int device,
+                             hipStream_t s) {
+    const LdsItem it = lds_item(algo, g);
+    int lim = 0, cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    if (it.bytes <= 0 || cus < 1) return hipErrorInvalidValue;
+    if (algo != kCBP && algo != kCBPNMS) return hipErrorInvalidValue;
+    const int64_t per_cu_frames = ((int64_t)lim - 4 * kLdsStaticBytes) / it.bytes;
+    if (per_cu_frames < 1 || lds_frames(it, lim) < 1) return hipErrorInvalidValue;
+    const int T = per_cu_frames == 1 ? 1024 : 512;
+    int F = per_cu_frames >= 4 ? (int)(per_cu_frames / 4) : 1;
+    if (F > kLdsMaxFrames) F = kLdsMaxFrames;
+    if (const char *v = std::getenv("CBP_SPARSE_LDS_FRAMES")) {
+        const int cap = std::atoi(v);
+        if (cap >= 1 && cap < F) F = cap;
+    }
+    // small batches: fewer frames per workgroup, more workgroups
+    const int64_t spread = (nf + cus - 1) / cus;
+    if (spread < F) F = (int)(spread < 1 ? 1 : spread);
+    const int64_t by_lds = (int64_t)lim / ((int64_t)F * it.bytes + kLdsStaticBytes);
+    const int64_t by_threads = kLdsCuThreads / T;
+    const int64_t per_cu = by_lds < 1 ? 1 : (by_lds < by_threads ? by_lds : by_threads);
+    const int64_t need = (nf + F - 1) / F;
+    const int groups = (int)(need < per_cu * cus ? need : per_cu * cus);
+    hipLaunchKernelGGL(lds_zero_kernel, dim3(1), dim3(kLdsFillBlock), 0, s, counter);
+    const bool mn = algo == kCBPNMS;
+    if (T == 1024)
+        return mn ? launch_t<true, 1024>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
+                  : launch_t<false, 1024>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s);
+    return mn ? launch_t<true, 512>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
+              : launch_t<false, 512>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s);
+}
+
+}  // namespace cbp

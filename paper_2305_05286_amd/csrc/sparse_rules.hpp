@@ -1,0 +1,24 @@
+// Check rules shared by the CSR kernels (one frame per lane, and frames
+// staged in LDS), so that both compute every message with the same
+// instructions and give the same result bit for bit.
+#pragma once
+#include "internal.hpp"
+#include "phi.hpp"
+
+namespace cbp {
+
+// C2V of a check recovered from its belief (om = max term or min1 with the
+// parity in its sign bit, os = rest of the sum or min2), excluding q
+// (B2V, eq. equ_s4e18; min-sum form of Sec. IV-D with kMin).
+template <bool kMin>
+__device__ float b2v(float om, float os, float q, const Params &p) {
+    if constexpr (!kMin) {
+        return with_sign(phi2(excl_sum(abs_bits(om), os, phi2_clamped(q, p.a, p.lmax))), sign_bit(om) ^ (q < 0.0f));
+    } else {
+        const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+        const float m1 = abs_bits(om);
+        return with_sign(p.alpha * ((aq == m1) ? os : m1), sign_bit(om) ^ (q < 0.0f));
+    }
+}
+
+}  // namespace cbp

@@ -68,6 +68,8 @@ def test_code_handles(L):
     c3 = cbp.Code.from_workload(get_code("qc26112"))
     assert not c3.has_kernel("qc_reg") and c3.has_kernel("qc_stream")
     assert not c1.has_kernel("qc_stream")
+    # frame state in LDS: 4N + 4E + 8M + N bytes (rounded) within 160 KiB
+    assert c.has_kernel("sparse_lds") and c1.has_kernel("sparse_lds") and not c3.has_kernel("sparse_lds")
 
 
 @pytest.mark.parametrize("rp,ci,why", [
@@ -116,6 +118,20 @@ def test_decode_argument_errors_without_gpu(L):
     o.kernel = cbp.KERNELS["qc_reg"]
     assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
     assert b"register-resident" in L.cbp_last_error()
+    # the LDS-staged kernel: cbp_decode only, syndrome stop or fixed sweeps,
+    # Step-3 decisions, no dumps, and a frame that fits a CU's LDS
+    o.kernel = cbp.KERNELS["sparse_lds"]
+    for field, val in (("stop_rule", 1), ("hd_mode", 1), ("dump_sweep", 2)):
+        setattr(o, field, val)
+        o.dump_frames = 1
+        assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+        assert b"LDS-staged" in L.cbp_last_error()
+        setattr(o, field, 0)
+    o.dump_frames = 0
+    assert L.lbp_nms_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
+    big = cbp.Code.from_workload(get_code("qc26112"))  # 0.4 MB of state per frame
+    assert not big.has_kernel("sparse_lds")
+    assert L.cbp_decode(big.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
     o.kernel = 0
     o.lmax = -1.0
     assert L.cbp_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EINVAL
@@ -172,10 +188,13 @@ def test_row_levels(L, name):
 
 def test_workspace_sizes(L):
     c = cbp.Code.from_workload(get_code("reg36_n96"))
-    n = cbp.workspace_size(c, "cbp", 2000)
+    n = cbp.workspace_size(c, "cbp", 2000, kernel="sparse")
     S = 2048  # frames padded to whole waves
     assert n >= (96 + 288 + 2 * 48) * 4 * S + 96 * S  # Q, R, check-beliefs (float2), decisions
     assert cbp.workspace_size(c, "cbp", 0) == 0
+    # frame state in LDS: only the frame counter in device memory (the
+    # default for a code without a QC layout whose frame fits a CU's LDS)
+    assert cbp.workspace_size(c, "cbp", 2000) == cbp.workspace_size(c, "cbp", 2000, kernel="sparse_lds") == 256
     q = cbp.Code.from_workload(get_code("qc2304"))
     assert 0 < cbp.workspace_size(q, "cbp", 131072) <= 4096
     # streamed kernel: one slot of state per frame in flight, at most 2048 slots
@@ -201,8 +220,9 @@ def test_log_tanh_baselines_run_on_the_sparse_kernel(L):
         n = cbp.workspace_size(c, "lbp", 2000)
         assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 9 * 256
     # options the level-parallel kernel does not serve reserve no items
-    assert cbp.workspace_size(c, "cbp", 2000, stop_rule=1) < cbp.workspace_size(c, "cbp", 2000)
-    assert cbp.workspace_size(c, "cbp", 2000, hd_mode=1) < cbp.workspace_size(c, "cbp", 2000)
+    lane = cbp.workspace_size(c, "cbp", 2000, kernel="sparse")
+    assert cbp.workspace_size(c, "cbp", 2000, stop_rule=1) < lane
+    assert cbp.workspace_size(c, "cbp", 2000, hd_mode=1) < lane
     q = cbp.Code.from_workload(get_code("qc2304"))
     # a QC code: auto picks the sparse kernel for lbp/fbp (a large frame-interleaved workspace)
     assert cbp.workspace_size(q, "lbp", 4096) > 4096 * (2304 + 6912) * 4
