@@ -82,15 +82,16 @@ int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
 #define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, persistent (lanes take new  */
                                /* frames as theirs stop), state per wave contiguous      */
-#define CBP_KERNEL_SPARSE_LDS 8 /* any H whose frame state (CBP: 4N + 4E + 8M + N bytes, */
-                               /* rounded) fits a CU's LDS: several frames per workgroup */
+#define CBP_KERNEL_SPARSE_LDS 8 /* any H whose frame state (4N + 4E + 8M + N bytes,       */
+                               /* rounded; flooding BP 4N more) fits a CU's LDS: frames  */
                                /* staged in LDS, each sweep level by level (see          */
                                /* cbp_code_levels), the edges of a level on separate     */
-                               /* threads; persistent.  cbp_decode only, with stop_rule  */
-                               /* 0 or 2, hd_mode 0 and no dumps (else                   */
-                               /* CBP_EUNSUPPORTED).  Results are bit-identical to       */
-                               /* CBP_KERNEL_SPARSE.  AUTO picks it for a code that has  */
-                               /* no QC layout when the options and the state allow.     */
+                               /* threads; persistent.  Every decoder, with stop_rule 0  */
+                               /* or 2, hd_mode 0 and no dumps (else CBP_EUNSUPPORTED).  */
+                               /* Results are bit-identical to CBP_KERNEL_SPARSE.  AUTO  */
+                               /* picks it for a code without a QC layout (and for       */
+                               /* lbp_decode / fbp_decode) when the options and the      */
+                               /* state allow.                                           */
                                /* CBP_SPARSE_LDS_FRAMES (>= 1) in the environment caps   */
                                /* the frames per workgroup (tuning).                     */
 /* Sparse kernel, slow frames: once every frame of the batch has been taken, a
@@ -190,8 +191,8 @@ void cbp_opts_default(cbp_opts_t *opts);
  *   rule, the log-tanh C2V of eq. equ_s2e4 (phi of the sum of phi(|Q|) over
  *   the row's other edges, |Q| clamped to [phi(lmax), lmax] as in
  *   cbp_decode): the LBP and FBP the paper compares CBP with (Sec. V).
- *   They run on the sparse kernel (opts->kernel AUTO or CBP_KERNEL_SPARSE,
- *   else CBP_EUNSUPPORTED) for any code.
+ *   They run on the CSR kernels (opts->kernel AUTO, CBP_KERNEL_SPARSE or
+ *   CBP_KERNEL_SPARSE_LDS, else CBP_EUNSUPPORTED) for any code.
  */
 int cbp_decode(const cbp_code_t *code, const float *llr_in, uint8_t *bits_out,
                int32_t *iters_out, int32_t max_iter, int64_t batch,

@@ -409,9 +409,11 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     // the syndrome stop or fixed sweeps, decisions of Step 3, no dumps
     const bool lds_opts = o->stop_rule != 1 && o->hd_mode == 0 && (o->dump_sweep == 0 || o->dump_frames == 0);
     const bool lds_fits = lds_kernel_fits(algo, code);
-    if ((algo == kLBP || algo == kFBP) && k != CBP_KERNEL_AUTO && k != CBP_KERNEL_SPARSE)
-        return fail(CBP_EUNSUPPORTED, "lbp_decode and fbp_decode run on the sparse kernel only");
-    if (algo == kLBP || algo == kFBP) k = CBP_KERNEL_SPARSE;
+    if ((algo == kLBP || algo == kFBP) && k != CBP_KERNEL_AUTO && k != CBP_KERNEL_SPARSE &&
+        k != CBP_KERNEL_SPARSE_LDS)
+        return fail(CBP_EUNSUPPORTED, "lbp_decode and fbp_decode run on the CSR kernels only");
+    if ((algo == kLBP || algo == kFBP) && k == CBP_KERNEL_AUTO)
+        k = (lds_fits && lds_opts) ? CBP_KERNEL_SPARSE_LDS : CBP_KERNEL_SPARSE;
     if (k == CBP_KERNEL_AUTO)
         k = code->qc_reg_id >= 0 ? CBP_KERNEL_QC_REG
             : stream_ok          ? CBP_KERNEL_QC_STREAM
@@ -422,8 +424,7 @@ int resolve_opts(const cbp_code_t *code, int algo, int64_t batch, const cbp_opts
     if (k == CBP_KERNEL_QC_STREAM && !stream_ok)
         return fail(CBP_EUNSUPPORTED, "the streamed kernel needs a QC code with Z <= 1024, mb < 32768, nb < 65536");
     if (k == CBP_KERNEL_SPARSE_LDS && !lds_fits)
-        return fail(CBP_EUNSUPPORTED, "the LDS-staged kernel serves cbp_decode on codes whose frame state fits "
-                                      "a CU's LDS");
+        return fail(CBP_EUNSUPPORTED, "the LDS-staged kernel serves codes whose frame state fits a CU's LDS");
     if (k == CBP_KERNEL_SPARSE_LDS && !lds_opts)
         return fail(CBP_EUNSUPPORTED, "the LDS-staged kernel runs with stop_rule 0 or 2, hd_mode 0 and no dumps");
     if (k != CBP_KERNEL_QC_REG && k != CBP_KERNEL_QC_STREAM && k != CBP_KERNEL_SPARSE && k != CBP_KERNEL_SPARSE_LDS)

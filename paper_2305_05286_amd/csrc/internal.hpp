@@ -120,11 +120,13 @@ hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok,
                            hipStream_t s);
 
 // ---- CSR codes with each frame's state in LDS ------------------------------
-// Byte offsets of one frame's arrays in LDS: Q [N] at 0, R [E] at r, beliefs
-// [M] (float2) at om, decisions [N] at xb; bytes = 0 if the algorithm has no
-// such kernel.
+// Byte offsets of one frame's arrays in LDS: Q (CBP) or the posterior (BP)
+// [N] at 0, R [E] at r, the rows' beliefs (CBP) or fold states (BP) [M]
+// (float2) at om, decisions [N] at xb; bytes = 0 if the algorithm has no such
+// kernel.
 struct LdsItem {
     int r, om, xb, bytes;
+    int acc;  // flooding BP: the C2V sums [N] (0 otherwise)
 };
 constexpr int kLdsMaxFrames = 8;       // frames per workgroup
 constexpr int64_t kLdsStaticBytes = 256;  // the kernel's own LDS (slot table)

@@ -799,7 +799,6 @@ __device__ __forceinline__ void bp_level_rows(const int4 (&rr)[K], int nr, const
 
 // Posterior of the flooding schedule (eq. equ_s2e6) from the channel LLR in
 // log2 units and the sum of the C2V messages.
-__device__ __forceinline__ float flood_posterior(float l, float us, float acc) { return l * us + acc; }
 
 __device__ __forceinline__ BpState bp_layout(const SparseDev &g, char *b) {
     const int64_t n4 = round256(4 * (int64_t)g.N), e4 = round256(4 * (int64_t)g.E);

@@ -45,101 +45,30 @@ __global__ __launch_bounds__(kLdsFillBlock) void lds_zero_kernel(unsigned int *p
     if (tid_x() == 0) *p = 0u;
 }
 
-// kMin: the normalized min-sum check rule (beliefs = (min1 | parity, min2)).
-// kT threads per workgroup.
-template <bool kMin, int kF, int kT>
-__global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *__restrict__ llr,
-                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
-                                                     int64_t nf, int max_iter, Params p, unsigned int *counter,
-                                                     LdsItem it) {
-    extern __shared__ uint4 s_dyn[];
+// The persistent slot loop shared by the decoders: kF frame slots of
+// it.bytes each in dynamic LDS; `load(f, frame)` runs Step 1 on a fresh slot
+// (all threads, no barrier), `sweep(live, s1)` one sweep of the live slots
+// (bit f of s1: slot f's first sweep; it ends with a barrier).  Decisions are
+// bytes at it.xb in each slot.
+template <int kF, int kT, class Load, class Sweep>
+__device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const LdsItem &it, uint8_t *bits,
+                                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
+                                          unsigned int *counter, Load &&load, Sweep &&sweep) {
     __shared__ int64_t sFrame[kF];
     __shared__ int sT[kF], sBad[kF], sFresh[kF];
     const int tid = tid_x();
-    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
-    p.a *= us;
-    p.lmax *= us;
-    char *const base = reinterpret_cast<char *>(s_dyn);
-    auto Qp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes); };
-    auto Rp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.r); };
-    auto Op = [&](int f) { return reinterpret_cast<float2 *>(base + f * it.bytes + it.om); };
     auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
-
-    // Step 2(1) a-e on edge e (record rec) of frame slot f.  s1: bit f set
-    // while slot f runs its first sweep.
-    uint32_t s1 = 0;
-    auto edge = [&](int f, const int4 &rec) {
-        const int col = rec.x, pe = rec.y, pr = rec.z, e = rec.w & 0x3fffffff;
-        const uint32_t fl = (uint32_t)rec.w >> 30;
-        float *Q = Qp(f), *R = Rp(f);
-        const float q = Q[col];
-        float rc = R[e];
-        const float2 om = Op(f)[pr];
-        float rn = 0.0f;
-        // no latest check yet on a variable's first visit of the first sweep
-        if (!(((s1 >> f) & 1u) && (fl & kFirstVisit))) {
-            rn = b2v<kMin>(om.x, om.y, q, p);  // B2V, eq. equ_s4e18
-            R[pe] = rn;                         // commit R(c_j -> v) first
-            if (pe == e) rc = rn;
-        }
-        const float lam = q + rn;  // eq. equ_s4e20
-        if (fl & kLastVisit) Xp(f)[col] = lam < 0.0f;
-        const float qn = lam - rc;  // V2C, eq. equ_s4e19
-        Q[col] = qn;
-        const float term = kMin ? __builtin_fminf(__builtin_fabsf(qn), p.lmax) : phi2_clamped(qn, p.a, p.lmax);
-        R[e] = with_sign(term, qn < 0.0f);
+    auto load_fresh = [&]() {
+        for (int f = 0; f < kF; ++f)
+            if (sFresh[f] && sFrame[f] < nf) load(f, sFrame[f]);
     };
-    // Step 2(1)d / 2(2) for row rr = (row, first edge, end edge) of slot f:
-    // the terms folded in ascending column order into the new belief (C2B,
-    // eqs. equ_s4e21 / equ_s4e23), kLdsChunk loads at a time (indices past the
-    // row clamped to its last edge)
-    auto row_fold = [&](int f, const int4 &rr) {
-        const float *R = Rp(f);
-        float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
-        bool par = false;
-        for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
-            float x[kLdsChunk];
-#pragma unroll
-            for (int c = 0; c < kLdsChunk; ++c) x[c] = R[c0 + c < rr.z ? c0 + c : rr.z - 1];
-#pragma unroll
-            for (int c = 0; c < kLdsChunk; ++c) {
-                if (c0 + c < rr.z) {
-                    par ^= sign_bit(x[c]);
-                    const float ax = abs_bits(x[c]);
-                    if constexpr (!kMin) {
-                        fold(Mx, Sr, ax);
-                    } else {
-                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, ax));
-                        Mx = __builtin_fminf(Mx, ax);
-                    }
-                }
-            }
-        }
-        Op(f)[rr.x] = make_float2(with_sign(Mx, par), Sr);
-    };
-
     if (tid < kF) {
         sFrame[tid] = (int64_t)atomicAdd(counter, 1u);
         sT[tid] = 0;
         sFresh[tid] = 1;
     }
     __syncthreads();
-    // Step 1 for every fresh slot: latest V2C = channel LLR, R = 0, x = [L < 0]
-    auto load = [&]() {
-        for (int f = 0; f < kF; ++f) {
-            const int64_t fr = sFrame[f];
-            if (!sFresh[f] || fr >= nf) continue;
-            float *Q = Qp(f), *R = Rp(f);
-            uint8_t *xb = Xp(f);
-            for (int v = tid; v < g.N; v += kT) {
-                const float l = llr[fr * g.N + v] * us;
-                Q[v] = l;
-                xb[v] = l < 0.0f;
-            }
-            for (int e = tid; e < g.E; e += kT) R[e] = 0.0f;
-        }
-    };
-    load();
+    load_fresh();
     __syncthreads();
     for (;;) {
         // ---------------- syndrome of every live slot's decisions ------------
@@ -191,11 +120,10 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
             sFresh[tid] = d;
         }
         __syncthreads();
-        load();
+        load_fresh();
         __syncthreads();
         live = 0;
-        uint32_t fresh = 0;
-        s1 = 0;
+        uint32_t fresh = 0, s1 = 0;
         for (int f = 0; f < kF; ++f) {
             const bool on = sFrame[f] < nf;
             live |= (uint32_t)on << f;
@@ -204,8 +132,92 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
         }
         if (!live) break;
         if (fresh) continue;  // test the new frames before they sweep
+        sweep(live, s1);
+        if (tid < kF && ((live >> tid) & 1u)) ++sT[tid];
+    }
+}
 
-        // ---------------- one sweep, level by level ---------------------------
+// CBP.  kMin: the normalized min-sum check rule (beliefs = (min1 | parity,
+// min2)).  kT threads per workgroup.
+template <bool kMin, int kF, int kT>
+__global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *__restrict__ llr,
+                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                     int64_t nf, int max_iter, Params p, unsigned int *counter,
+                                                     LdsItem it) {
+    extern __shared__ uint4 s_dyn[];
+    const int tid = tid_x();
+    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
+    p.a *= us;
+    p.lmax *= us;
+    char *const base = reinterpret_cast<char *>(s_dyn);
+    auto Qp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes); };
+    auto Rp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.r); };
+    auto Op = [&](int f) { return reinterpret_cast<float2 *>(base + f * it.bytes + it.om); };
+    auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
+
+    // Step 2(1) a-e on the edge of record rec of frame slot f (s1 bit f: the
+    // slot's first sweep)
+    auto edge = [&](int f, uint32_t s1, const int4 &rec) {
+        const int col = rec.x, pe = rec.y, pr = rec.z, e = rec.w & 0x3fffffff;
+        const uint32_t fl = (uint32_t)rec.w >> 30;
+        float *Q = Qp(f), *R = Rp(f);
+        const float q = Q[col];
+        float rc = R[e];
+        const float2 om = Op(f)[pr];
+        float rn = 0.0f;
+        // no latest check yet on a variable's first visit of the first sweep
+        if (!(((s1 >> f) & 1u) && (fl & kFirstVisit))) {
+            rn = b2v<kMin>(om.x, om.y, q, p);  // B2V, eq. equ_s4e18
+            R[pe] = rn;                         // commit R(c_j -> v) first
+            if (pe == e) rc = rn;
+        }
+        const float lam = q + rn;  // eq. equ_s4e20
+        if (fl & kLastVisit) Xp(f)[col] = lam < 0.0f;
+        const float qn = lam - rc;  // V2C, eq. equ_s4e19
+        Q[col] = qn;
+        const float term = kMin ? __builtin_fminf(__builtin_fabsf(qn), p.lmax) : phi2_clamped(qn, p.a, p.lmax);
+        R[e] = with_sign(term, qn < 0.0f);
+    };
+    // Step 2(1)d / 2(2) for row rr = (row, first edge, end edge) of slot f:
+    // the terms folded in ascending column order into the new belief (C2B,
+    // eqs. equ_s4e21 / equ_s4e23), kLdsChunk loads at a time (indices past the
+    // row clamped to its last edge)
+    auto row_fold = [&](int f, const int4 &rr) {
+        const float *R = Rp(f);
+        float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
+        bool par = false;
+        for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
+            float x[kLdsChunk];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) x[c] = R[c0 + c < rr.z ? c0 + c : rr.z - 1];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) {
+                if (c0 + c < rr.z) {
+                    par ^= sign_bit(x[c]);
+                    const float ax = abs_bits(x[c]);
+                    if constexpr (!kMin) {
+                        fold(Mx, Sr, ax);
+                    } else {
+                        Sr = __builtin_fminf(Sr, __builtin_fmaxf(Mx, ax));
+                        Mx = __builtin_fminf(Mx, ax);
+                    }
+                }
+            }
+        }
+        Op(f)[rr.x] = make_float2(with_sign(Mx, par), Sr);
+    };
+    // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
+    auto load = [&](int f, int64_t fr) {
+        float *Q = Qp(f), *R = Rp(f);
+        uint8_t *xb = Xp(f);
+        for (int v = tid; v < g.N; v += kT) {
+            const float l = llr[fr * g.N + v] * us;
+            Q[v] = l;
+            xb[v] = l < 0.0f;
+        }
+        for (int e = tid; e < g.E; e += kT) R[e] = 0.0f;
+    };
+    auto sweep = [&](uint32_t live, uint32_t s1) {
         // Each phase reads its thread's first table record one phase ahead, so
         // that the table latency overlaps the work before the barrier.
         int4 recA = make_int4(0, 0, 0, 0), recB = make_int4(0, 0, 0, 0);
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
             for (int i = tid; i < kF * en; i += kT) {
                 const int j = i / kF, f = i - j * kF;
                 if (!((live >> f) & 1u)) continue;
-                edge(f, i == tid ? recA : g.lvl_edges[ea + j]);
+                edge(f, s1, i == tid ? recA : g.lvl_edges[ea + j]);
             }
             __syncthreads();
             // phase B: thread = (row of the level, frame)
@@ -236,44 +248,257 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
             }
             __syncthreads();
         }
-        if (tid < kF && ((live >> tid) & 1u)) ++sT[tid];
-    }
+    };
+    run_slots<kF, kT>(g, base, it, bits, iters, nf, max_iter, p, counter, load, sweep);
 }
 
-template <bool kMin, int kF, int kT>
-hipError_t launch_ft(const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters, int64_t nf,
-                     int max_iter, const Params &p, unsigned int *counter, const LdsItem &it, int groups,
-                     hipStream_t s) {
-    const size_t lds = (size_t)kF * (size_t)it.bytes;
-    auto *k = cbp_lds_kernel<kMin, kF, kT>;
+// Layered (kFlood false) and flooding BP, Sec. II-A / II-B, with the
+// normalized min-sum (kMin) or the log-tanh check rule, in the same layout:
+// the posterior Lambda [N] at 0, R [E], each row's fold state [M] (the two
+// smallest |Q| or the (max, rest) of g(|Q|), the parity in the first's sign
+// bit), the flooding C2V sums [N], decisions.  The same operations as the
+// one-frame-per-lane kernel's row update (a fold pass, then a C2V pass), so
+// the results agree bit for bit.  Layered BP runs three phases per level
+// (see the sweep below).  Flooding BP keeps Lambda for the whole sweep, so
+// per level:
+//   phase B (thread = row of a frame): the row's V2C messages Q = Lambda - R
+//            of the previous sweep folded in ascending column order into its
+//            state;
+//   phase C (thread = edge of a frame): Q again (nothing it reads has
+//            changed), the C2V message from the row's state, then R and the
+//            variable's C2V sum (rows containing a variable meet it in index
+//            order, level by level, as row by row);
+// and the sweep ends with the posterior L + sum and the decisions of every
+// variable.
+template <bool kFlood, bool kMin, int kF, int kT>
+__global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__restrict__ llr,
+                                                    uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                    int64_t nf, int max_iter, Params p, unsigned int *counter,
+                                                    LdsItem it) {
+    extern __shared__ uint4 s_dyn[];
+    const int tid = tid_x();
+    const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
+    p.a *= us;
+    p.lmax *= us;
+    char *const base = reinterpret_cast<char *>(s_dyn);
+    auto Lp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes); };
+    auto Rp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.r); };
+    auto Sp = [&](int f) { return reinterpret_cast<float2 *>(base + f * it.bytes + it.om); };
+    auto Ap = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.acc); };
+    auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
+
+    // fold of row rr of slot f (V2C, eq. equ_s2e3 / equ_s2e10)
+    auto row_fold = [&](int f, const int4 &rr) {
+        const float *Lam = Lp(f), *R = Rp(f);
+        float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
+        bool par = false;
+        for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
+            int col[kLdsChunk];
+            float lv[kLdsChunk], rv[kLdsChunk];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) col[c] = g.col_idx[c0 + c];  // padded table
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) {
+                const int e = c0 + c < rr.z ? c0 + c : rr.z - 1;
+                lv[c] = Lam[c0 + c < rr.z ? col[c] : 0];
+                rv[c] = R[e];
+            }
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) {
+                if (c0 + c < rr.z) {
+                    const float q = lv[c] - rv[c];
+                    if constexpr (kMin) {
+                        const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
+                        m1 = __builtin_fminf(m1, aq);
+                    } else {
+                        fold(m1, m2, phi2_clamped(q, p.a, p.lmax));
+                    }
+                    par ^= (q < 0.0f);
+                }
+            }
+        }
+        Sp(f)[rr.x] = make_float2(with_sign(m1, par), m2);
+    };
+    // C2V of the edge of record rec of slot f (eq. equ_s2e4 or the min-sum
+    // rule), then R and Lambda (eq. equ_s2e12) or the C2V sum
+    auto edge = [&](int f, const int4 &rec) {
+        const int col = rec.x, e = rec.w & 0x3fffffff;
+        const uint32_t fl = (uint32_t)rec.w >> 30;
+        float *Lam = Lp(f), *R = Rp(f);
+        const float2 st = Sp(f)[g.edge_row[e]];
+        const float m1 = abs_bits(st.x), m2 = st.y;
+        const bool par = sign_bit(st.x);
+        const float q = Lam[col] - R[e];
+        float rn;
+        if constexpr (kMin) {
+            const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+            rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
+        } else {
+            rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))), par ^ (q < 0.0f));
+        }
+        R[e] = rn;
+        if constexpr (kFlood) {
+            float *A = Ap(f);
+            A[col] = A[col] + rn;
+        } else {
+            const float lm = q + rn;
+            Lam[col] = lm;
+            if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
+        }
+    };
+    __shared__ int64_t sCur[kF];  // the slot's frame, for the flooding posterior
+    auto load = [&](int f, int64_t fr) {
+        float *Lam = Lp(f), *R = Rp(f);
+        uint8_t *xb = Xp(f);
+        for (int v = tid; v < g.N; v += kT) {
+            const float l = llr[fr * g.N + v] * us;
+            Lam[v] = l;
+            xb[v] = l < 0.0f;
+            if constexpr (kFlood) Ap(f)[v] = 0.0f;
+        }
+        for (int e = tid; e < g.E; e += kT) R[e] = 0.0f;
+        if (tid == 0) sCur[f] = fr;
+    };
+    // layered: three phases per level, all but the fold edge-parallel.
+    //   A (edge): Q = Lambda - R kept in Lambda (no other row of the level
+    //     reads it), its check-rule term in R (the old C2V is no longer needed);
+    //   B (row):  the terms folded in column order into the row's state;
+    //   C (edge): the C2V message from the state and the edge's own term (the
+    //     same bits the one-frame-per-lane kernel recomputes), R, Lambda = Q + C2V.
+    auto term_edge = [&](int f, const int4 &rec) {
+        const int col = rec.x, e = rec.w & 0x3fffffff;
+        float *Lam = Lp(f), *R = Rp(f);
+        const float q = Lam[col] - R[e];  // V2C, eq. equ_s2e10
+        Lam[col] = q;
+        R[e] = with_sign(kMin ? __builtin_fminf(__builtin_fabsf(q), p.lmax) : phi2_clamped(q, p.a, p.lmax), q < 0.0f);
+    };
+    auto term_fold = [&](int f, const int4 &rr) {
+        const float *R = Rp(f);
+        float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
+        bool par = false;
+        for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
+            float x[kLdsChunk];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) x[c] = R[c0 + c < rr.z ? c0 + c : rr.z - 1];
+#pragma unroll
+            for (int c = 0; c < kLdsChunk; ++c) {
+                if (c0 + c < rr.z) {
+                    par ^= sign_bit(x[c]);
+                    const float ax = abs_bits(x[c]);
+                    if constexpr (kMin) {
+                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, ax));
+                        m1 = __builtin_fminf(m1, ax);
+                    } else {
+                        fold(m1, m2, ax);
+                    }
+                }
+            }
+        }
+        Sp(f)[rr.x] = make_float2(with_sign(m1, par), m2);
+    };
+    auto c2v_edge = [&](int f, const int4 &rec) {
+        const int col = rec.x, e = rec.w & 0x3fffffff;
+        const uint32_t fl = (uint32_t)rec.w >> 30;
+        float *Lam = Lp(f), *R = Rp(f);
+        const float2 st = Sp(f)[g.edge_row[e]];
+        const float m1 = abs_bits(st.x), m2 = st.y;
+        const bool par = sign_bit(st.x);
+        const float q = Lam[col], t = abs_bits(R[e]);
+        const float rn = kMin ? with_sign(p.alpha * ((t == m1) ? m2 : m1), par ^ (q < 0.0f))
+                              : with_sign(phi2(excl_sum(m1, m2, t)), par ^ (q < 0.0f));  // eq. equ_s2e4
+        R[e] = rn;
+        const float lm = q + rn;  // eq. equ_s2e12
+        Lam[col] = lm;
+        if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
+    };
+    auto sweep = [&](uint32_t live, uint32_t) {
+        if constexpr (!kFlood) {
+            for (int l = 0; l < g.nlev; ++l) {
+                const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
+                const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
+                for (int i = tid; i < kF * en; i += kT) {
+                    const int j = i / kF, f = i - j * kF;
+                    if ((live >> f) & 1u) term_edge(f, g.lvl_edges[ea + j]);
+                }
+                __syncthreads();
+                for (int i = tid; i < kF * rows; i += kT) {
+                    const int j = i / kF, f = i - j * kF;
+                    if ((live >> f) & 1u) term_fold(f, g.lvl_rows[ra + j]);
+                }
+                __syncthreads();
+                for (int i = tid; i < kF * en; i += kT) {
+                    const int j = i / kF, f = i - j * kF;
+                    if ((live >> f) & 1u) c2v_edge(f, g.lvl_edges[ea + j]);
+                }
+                __syncthreads();
+            }
+            return;
+        }
+        for (int l = 0; l < g.nlev; ++l) {
+            const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
+            for (int i = tid; i < kF * rows; i += kT) {
+                const int j = i / kF, f = i - j * kF;
+                if (!((live >> f) & 1u)) continue;
+                row_fold(f, g.lvl_rows[ra + j]);
+            }
+            __syncthreads();
+            const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
+            for (int i = tid; i < kF * en; i += kT) {
+                const int j = i / kF, f = i - j * kF;
+                if (!((live >> f) & 1u)) continue;
+                edge(f, g.lvl_edges[ea + j]);
+            }
+            __syncthreads();
+        }
+        if constexpr (kFlood) {  // eq. equ_s2e6, then the decisions (eq. equ_s2e7)
+            for (int f = 0; f < kF; ++f) {
+                if (!((live >> f) & 1u)) continue;
+                const int64_t fr = sCur[f];
+                float *Lam = Lp(f), *A = Ap(f);
+                uint8_t *xb = Xp(f);
+                for (int v = tid; v < g.N; v += kT) {
+                    const float lm = flood_posterior(llr[fr * g.N + v], us, A[v]);
+                    Lam[v] = lm;
+                    xb[v] = lm < 0.0f;
+                    A[v] = 0.0f;
+                }
+            }
+        }
+    };
+    run_slots<kF, kT>(g, base, it, bits, iters, nf, max_iter, p, counter, load, sweep);
+}
+
+template <class K>
+hipError_t launch_k(K *k, int groups, int threads, size_t lds, hipStream_t s, const SparseDev &g, const float *llr,
+                    uint8_t *bits, int32_t *iters, int64_t nf, int max_iter, const Params &p, unsigned int *counter,
+                    const LdsItem &it) {
     if (lds > (64u << 10)) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(kT), lds, s, g, llr, bits, iters, nf, max_iter, p, counter,
-                       it);
+    hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(threads), lds, s, g, llr, bits, iters, nf, max_iter, p,
+                       counter, it);
     return hipGetLastError();
 }
 
-template <bool kMin, int kT>
-hipError_t launch_t(int F, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters, int64_t nf,
-                    int max_iter, const Params &p, unsigned int *counter, const LdsItem &it, int groups,
-                    hipStream_t s) {
-#define CBP_LDS_F(n) \
-    case n: return launch_ft<kMin, n, kT>(g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
-    switch (F) {
-        CBP_LDS_F(1);
-        CBP_LDS_F(2);
-        CBP_LDS_F(3);
-        CBP_LDS_F(4);
-        CBP_LDS_F(5);
-        CBP_LDS_F(6);
-        CBP_LDS_F(7);
-        CBP_LDS_F(8);
+// The kernel of algo for kF frames of kT threads.
+template <int kF, int kT>
+hipError_t launch_algo(int algo, int groups, size_t lds, hipStream_t s, const SparseDev &g, const float *llr,
+                       uint8_t *bits, int32_t *iters, int64_t nf, int max_iter, const Params &p,
+                       unsigned int *counter, const LdsItem &it) {
+#define CBP_LDS_GO(KERNEL) return launch_k(KERNEL, groups, kT, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it)
+    switch (algo) {
+    case kCBP: CBP_LDS_GO((cbp_lds_kernel<false, kF, kT>));
+    case kCBPNMS: CBP_LDS_GO((cbp_lds_kernel<true, kF, kT>));
+    case kLBP: CBP_LDS_GO((bp_lds_kernel<false, false, kF, kT>));
+    case kLBPNMS: CBP_LDS_GO((bp_lds_kernel<false, true, kF, kT>));
+    case kFBP: CBP_LDS_GO((bp_lds_kernel<true, false, kF, kT>));
+    case kFBPNMS: CBP_LDS_GO((bp_lds_kernel<true, true, kF, kT>));
     default: return hipErrorInvalidValue;
     }
-#undef CBP_LDS_F
+#undef CBP_LDS_GO
 }
 
 int64_t align16(int64_t x) { return (x + 15) / 16 * 16; }
@@ -282,14 +507,16 @@ int64_t align16(int64_t x) { return (x + 15) / 16 * 16; }
 
 LdsItem lds_item(int algo, const SparseDev &g) {
     LdsItem it{};
-    if (algo != kCBP && algo != kCBPNMS) return it;  // bytes = 0: not available
-    const int64_t q = align16(4 * (int64_t)g.N), r = align16(4 * (int64_t)g.E), om = 8 * (int64_t)g.M,
-                  xb = align16(g.N);
-    const int64_t total = align16(q + r + om + xb);
+    if (algo < kCBP || algo > kFBP) return it;  // bytes = 0: not available
+    const bool flood = algo == kFBP || algo == kFBPNMS;
+    const int64_t q = align16(4 * (int64_t)g.N), r = align16(4 * (int64_t)g.E), om = align16(8 * (int64_t)g.M),
+                  acc = flood ? q : 0, xb = align16(g.N);
+    const int64_t total = q + r + om + acc + xb;
     if (total >= ((int64_t)1 << 31)) return it;
     it.r = (int)q;
     it.om = (int)(q + r);
-    it.xb = (int)(q + r + om);
+    it.acc = flood ? (int)(q + r + om) : 0;
+    it.xb = (int)(q + r + om + acc);
     it.bytes = (int)total;
     return it;
 }
@@ -302,7 +529,7 @@ int lds_frames(const LdsItem &it, int64_t lds_limit) {
 
 // Geometry: frames per CU that fit (LDS per CU = the per-workgroup maximum on
 // gfx950).  Four or more: workgroups of 512 threads, four per CU, each with
-// its share of the frames (at most kLdsMaxFrames); two or three: one frame per
+// its share of the frames (1, 2, 4 or 8); two or three: one frame per
 // workgroup of 512 threads; one: one workgroup of 1024 threads.
 // CBP_SPARSE_LDS_FRAMES in the environment caps the frames per workgroup.
 hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters,
@@ -314,10 +541,8 @@ hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uin
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
     if (it.bytes <= 0 || cus < 1) return hipErrorInvalidValue;
-    if (algo != kCBP && algo != kCBPNMS) return hipErrorInvalidValue;
     const int64_t per_cu_frames = ((int64_t)lim - 4 * kLdsStaticBytes) / it.bytes;
     if (per_cu_frames < 1 || lds_frames(it, lim) < 1) return hipErrorInvalidValue;
-    const int T = per_cu_frames == 1 ? 1024 : 512;
     int F = per_cu_frames >= 4 ? (int)(per_cu_frames / 4) : 1;
     if (F > kLdsMaxFrames) F = kLdsMaxFrames;
     if (const char *v = std::getenv("CBP_SPARSE_LDS_FRAMES")) {
@@ -327,18 +552,22 @@ hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uin
     // small batches: fewer frames per workgroup, more workgroups
     const int64_t spread = (nf + cus - 1) / cus;
     if (spread < F) F = (int)(spread < 1 ? 1 : spread);
+    F = F >= 8 ? 8 : F >= 4 ? 4 : F >= 2 ? 2 : 1;  // the compiled widths
+    const int T = per_cu_frames == 1 ? 1024 : 512;
     const int64_t by_lds = (int64_t)lim / ((int64_t)F * it.bytes + kLdsStaticBytes);
     const int64_t by_threads = kLdsCuThreads / T;
     const int64_t per_cu = by_lds < 1 ? 1 : (by_lds < by_threads ? by_lds : by_threads);
     const int64_t need = (nf + F - 1) / F;
     const int groups = (int)(need < per_cu * cus ? need : per_cu * cus);
+    const size_t lds = (size_t)F * (size_t)it.bytes;
     hipLaunchKernelGGL(lds_zero_kernel, dim3(1), dim3(kLdsFillBlock), 0, s, counter);
-    const bool mn = algo == kCBPNMS;
-    if (T == 1024)
-        return mn ? launch_t<true, 1024>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
-                  : launch_t<false, 1024>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s);
-    return mn ? launch_t<true, 512>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s)
-              : launch_t<false, 512>(F, g, llr, bits, iters, nf, max_iter, p, counter, it, groups, s);
+    if (T == 1024) return launch_algo<1, 1024>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    switch (F) {
+    case 8: return launch_algo<8, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    case 4: return launch_algo<4, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    case 2: return launch_algo<2, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    default: return launch_algo<1, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    }
 }
 
 }  // namespace cbp

@@ -21,4 +21,8 @@ __device__ float b2v(float om, float os, float q, const Params &p) {
     }
 }
 
+// Flooding posterior at the end of a sweep: channel LLR (scaled to the
+// rule's units) plus the sum of the sweep's C2V messages (eq. equ_s2e6).
+__device__ __forceinline__ float flood_posterior(float l, float us, float acc) { return l * us + acc; }
+
 }  // namespace cbp

@@ -128,7 +128,6 @@ def test_decode_argument_errors_without_gpu(L):
         assert b"LDS-staged" in L.cbp_last_error()
         setattr(o, field, 0)
     o.dump_frames = 0
-    assert L.lbp_nms_decode(c.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
     big = cbp.Code.from_workload(get_code("qc26112"))  # 0.4 MB of state per frame
     assert not big.has_kernel("sparse_lds")
     assert L.cbp_decode(big.handle, fake, fake, fake, 5, 8, ctypes.byref(o), None) == cbp.CBP_EUNSUPPORTED
@@ -213,19 +212,26 @@ def test_log_tanh_baselines_run_on_the_sparse_kernel(L):
     item = 2 * r256(4 * 96) + r256(4 * 288) + r256(96)
     for dec in ("lbp", "fbp", "lbp_nms"):
         # Lambda, R, flooding accumulator, decisions, each frame-interleaved
-        n = cbp.workspace_size(c, dec, 2000)
+        n = cbp.workspace_size(c, dec, 2000, kernel="sparse")
         lo = (2 * 96 + 288) * 4 * S + 96 * S + 256 + r256(8 * S) + S * item
         assert lo <= n <= lo + 9 * 256
+        assert cbp.workspace_size(c, dec, 2000) == 256   # auto: the LDS-staged kernel
     with env(CBP_SPARSE_HANDOFF="0"):   # no hand-off: header and lane blocks only
-        n = cbp.workspace_size(c, "lbp", 2000)
+        n = cbp.workspace_size(c, "lbp", 2000, kernel="sparse")
         assert (2 * 96 + 288) * 4 * S + 96 * S <= n <= (2 * 96 + 288) * 4 * S + 96 * S + 9 * 256
     # options the level-parallel kernel does not serve reserve no items
     lane = cbp.workspace_size(c, "cbp", 2000, kernel="sparse")
     assert cbp.workspace_size(c, "cbp", 2000, stop_rule=1) < lane
     assert cbp.workspace_size(c, "cbp", 2000, hd_mode=1) < lane
     q = cbp.Code.from_workload(get_code("qc2304"))
-    # a QC code: auto picks the sparse kernel for lbp/fbp (a large frame-interleaved workspace)
-    assert cbp.workspace_size(q, "lbp", 4096) > 4096 * (2304 + 6912) * 4
+    # a QC code: lbp/fbp run on the CSR kernels; auto picks the LDS-staged one
+    # (frame state in LDS, only the frame counter in device memory) where a
+    # frame fits, else the one-frame-per-lane kernel (a large frame-interleaved
+    # workspace)
+    assert cbp.workspace_size(q, "lbp", 4096) == 256
+    assert cbp.workspace_size(q, "lbp", 4096, kernel="sparse") > 4096 * (2304 + 6912) * 4
+    big = cbp.Code.from_workload(get_code("qc26112"))
+    assert cbp.workspace_size(big, "fbp", 64) > 64 * (2 * 26112 + 76800) * 4
     for k in ("qc_reg", "qc_stream"):
         with pytest.raises(cbp.CbpError) as e:
             cbp.workspace_size(q, "fbp", 64, kernel=k)

@@ -1,11 +1,12 @@
 """The LDS-staged CSR kernel (CBP_KERNEL_SPARSE_LDS).
 
-Several frames per workgroup with their whole state in LDS, each sweep run level by level
-with the edges of a level on separate threads.  Its per-edge arithmetic and row-fold order
-are those of the one-frame-per-lane kernel, so decisions and sweep counts must equal that
-kernel's bit for bit, for both check rules, the syndrome stop and fixed sweeps, ragged and
-tiny batches (fewer frames than workgroups), weight-one columns and the long (200-sweep)
-runs of the PEG codes; and through the lane kernel's own parity, the FP64 oracle's.
+Frames with their whole state in LDS, each sweep run level by level with the edges of a
+level on separate threads.  Its per-edge arithmetic and fold order are those of the
+one-frame-per-lane kernel, so decisions and sweep counts must equal that kernel's bit for
+bit, for CBP and the layered and flooding BP baselines with both check rules, the syndrome
+stop and fixed sweeps, ragged and tiny batches (fewer frames than workgroups), weight-one
+columns and the long (200-sweep) runs of the PEG codes; and through the lane kernel's own
+parity, the FP64 oracle's.
 """
 import sys
 
@@ -39,11 +40,17 @@ CODES = [("reg36_n96", 1.5, 3001, 40), ("qc_t64s", 1.5, 1999, 40), ("peg_irr_n20
 
 
 @pytest.mark.parametrize("name,ebn0,frames,max_iter", CODES)
-@pytest.mark.parametrize("algo", ["cbp", "cbp_nms"])
+@pytest.mark.parametrize("algo", ["cbp", "cbp_nms", "lbp", "fbp", "lbp_nms", "fbp_nms"])
 def test_equals_lane_kernel(name, ebn0, frames, max_iter, algo):
     code = get_code(name)
     c = cbp.Code.from_workload(code)
     assert c.has_kernel("sparse_lds")
+    if algo.startswith("fbp") and code.N == 8192:
+        # flooding BP keeps 4N more bytes per frame: 195 KB does not fit a CU's LDS
+        with pytest.raises(cbp.CbpError) as e:
+            cbp.workspace_size(c, algo, 1, kernel="sparse_lds")
+        assert e.value.status == cbp.CBP_EUNSUPPORTED
+        return
     llr, _ = make_frames(code, ebn0, frames, key=(43,))
     t = torch.from_numpy(llr).cuda()
     say(f"[gpu] sparse_lds {name} {algo} {frames} frames")
