@@ -13,7 +13,9 @@ For each PEG code (regular (3,6) and the paper's irregular lambda/rho, lengths
 * ``cbp_nms``    CBP with the normalized min-sum rule of Sec. IV-D (``--alpha``,
                  default 0.75; the paper's Figs. 10-12), on request,
 
-all through the library's sparse kernel.  A point stops after ``--errors``
+all through the library's CSR kernels (frames staged in LDS where a frame fits
+and the options allow, else one frame per lane; the two agree bit for bit;
+the paper's stopping rule runs one frame per lane).  A point stops after ``--errors``
 frame errors or ``--max-frames`` frames.  Frames: BPSK over AWGN (bit 0 -> +1,
 L = 2 y / sigma^2, sigma^2 = 1 / (2 R Eb/N0)), codewords drawn from a pool of
 seeded random codewords, fresh noise drawn on the GPU for every batch.  The
@@ -49,7 +51,9 @@ def run_point(handle, pool, rate, ebn0, algo, kw, max_iter, batch, max_frames, t
         c = pool[idx]
         y = (1.0 - 2.0 * c.float()) + (s2 ** 0.5) * torch.randn(c.shape, device=pool.device, generator=gen)
         llr = ((2.0 / s2) * y).contiguous()
-        bits, iters = cbp.decode(handle, llr, max_iter, algo, kernel="sparse", **kw)
+        # the CSR kernels: frames staged in LDS where a frame fits and the options
+        # allow (bit-identical to the one-frame-per-lane kernel), else one per lane
+        bits, iters = cbp.decode(handle, llr, max_iter, algo, kernel="auto", **kw)
         err = bits != c
         fe = err.any(dim=1)
         n_fe += int(fe.sum())
