@@ -522,12 +522,34 @@ def main() -> int:
                  "fer": round(float(ferr.mean()), 5),
                  "fer_by_rate": {RATES[r][0]: round(float(ferr[rate_of == r].mean()), 5)
                                  for r in range(len(RATES))}}
-        for algo in ("lbp_nms",):
-            lws = torch.empty(mix.workspace_size(MB_, algo), dtype=torch.uint8, device=dev)
-            mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit))
-            lt = mtime(lambda: mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit)), 3)
-            mixed[f"{algo}_eager_ms"] = round(float(np.median(lt)) * 1e3, 3)
-            mixed[f"{algo}_mean_iters"] = round(float(mit.double().mean().item()), 3)
+        # each decoder tuned for itself, then the streamed kernel alone (LDS-staged part off) at
+        # the tuned lanes and its best workgroups per CU
+        for algo in ("cbp", "lbp_nms", "fbp_nms"):
+            if algo != "cbp":
+                sa, _ = mix.tune(ml, mc, mo, MMI, algo, out=(mbits, mit))
+                lws = torch.empty(mix.workspace_size(MB_, algo), dtype=torch.uint8, device=dev)
+                mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit))
+                lt = mtime(lambda: mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit)), 3)
+                mixed[f"{algo}_schedule_tuned"] = list(sa)
+                mixed[f"{algo}_eager_ms"] = round(float(np.median(lt)) * 1e3, 3)
+                mixed[f"{algo}_mean_iters"] = round(float(mit.double().mean().item()), 3)
+            else:
+                sa = best
+            so = []
+            for g_ in range(1, 6):
+                try:
+                    mix.schedule = (sa[0], g_, 0)
+                except cbp.CbpError:
+                    break
+                lws = torch.empty(mix.workspace_size(MB_, algo), dtype=torch.uint8, device=dev)
+                mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit))
+                lt = mtime(lambda: mix.decode(ml, mc, mo, MMI, algo, workspace=lws, out=(mbits, mit)), 3)
+                so.append((float(np.median(lt)), g_))
+            mixed[f"{algo}_streamed_only_ms"] = round(min(so)[0] * 1e3, 3)
+            mixed[f"{algo}_streamed_only_schedule"] = [sa[0], min(so)[1], 0]
+            log(f"[bench] mixed {algo}: tuned {tuple(sa)} "
+                f"{mixed.get(f'{algo}_eager_ms', mixed['eager_ms']):.2f} ms, "
+                f"streamed kernel only {mixed[f'{algo}_streamed_only_ms']:.2f} ms")
         log(f"[bench] mixed cbp: eager {mixed['eager_ms']:.2f} ms, graph {mixed['graph_ms']:.2f} ms, "
             f"{mixed['gbps']:.2f} Gbit/s, iters {mixed['mean_iters']:.2f}, FER {mixed['fer']:.3f}")
         del ml, mc, mo, mbits, mit, mws, lws, graph

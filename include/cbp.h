@@ -89,9 +89,8 @@ int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int
                                /* threads; persistent.  Every decoder, with stop_rule 0  */
                                /* or 2, hd_mode 0 and no dumps (else CBP_EUNSUPPORTED).  */
                                /* Results are bit-identical to CBP_KERNEL_SPARSE.  AUTO  */
-                               /* picks it for a code without a QC layout (and for       */
-                               /* lbp_decode / fbp_decode) when the options and the      */
-                               /* state allow.                                           */
+                               /* picks it, when the options and the state allow, for    */
+                               /* every code whose base pattern is not compiled in.      */
                                /* CBP_SPARSE_LDS_FRAMES (>= 1) in the environment caps   */
                                /* the frames per workgroup (tuning).                     */
 /* Sparse kernel, slow frames: once every frame of the batch has been taken, a
@@ -276,6 +275,14 @@ void cbp_mix_free(cbp_mix_t *mix);
 typedef struct {
     int32_t lanes;
     int32_t groups_per_cu;
+    /* 0 (default): every code on the streamed kernel.  1 or 2: the codes whose
+     * frame state fits half a CU's LDS are decoded staged in LDS (the layout of
+     * CBP_KERNEL_SPARSE_LDS) by this many workgroups per CU, on a second
+     * stream beside the streamed launch (the plan's own stream, joined back
+     * before the call's work ends; calls with one plan on one device take
+     * turns on it); results are identical either way.  cbp_mix_tune tries 0,
+     * 1 and 2 with every streamed schedule. */
+    int32_t lds_groups_per_cu;
 } cbp_mix_schedule_t;
 int cbp_mix_get_schedule(const cbp_mix_t *mix, cbp_mix_schedule_t *sched);
 int cbp_mix_set_schedule(cbp_mix_t *mix, const cbp_mix_schedule_t *sched);
@@ -312,10 +319,11 @@ int cbp_mix_decode(const cbp_mix_t *mix, int32_t decoder, const float *llr_in, i
 
 /*
  * Autotuner: decodes the given batch (arguments as for cbp_mix_decode, minus
- * the workspace) once per candidate schedule — lanes in {L, 2L, 4L} up to 1024
- * (L = the default lanes) times workgroups per CU from 1 to what fits — timing
- * each launch with HIP events on `stream` (the call synchronises it and
- * allocates its own workspace), and sets the fastest as the plan's schedule.
+ * the workspace) twice per candidate schedule — lanes in {L, 2L, 4L} up to
+ * 1024 (L = the default lanes) times workgroups per CU from 1 to what fits
+ * times lds_groups_per_cu in {0, 1, 2} — timing the second launch with HIP
+ * events on `stream` (the call synchronises it and allocates its own
+ * workspace), and sets the fastest as the plan's schedule.
  * best and best_ms may be NULL.  The outputs hold the last candidate's
  * (identical) decode.
  */

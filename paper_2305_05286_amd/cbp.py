@@ -41,7 +41,7 @@ class CbpError(RuntimeError):
 
 class MixSchedule(ctypes.Structure):
     """Mirror of cbp_mix_schedule_t."""
-    _fields_ = [("lanes", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
+    _fields_ = [("lanes", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("lds_groups_per_cu", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -366,11 +366,12 @@ class Mix:
     def schedule(self):
         sc = MixSchedule()
         check(lib().cbp_mix_get_schedule(self._h, ctypes.byref(sc)))
-        return (sc.lanes, sc.groups_per_cu)
+        return (sc.lanes, sc.groups_per_cu, sc.lds_groups_per_cu)
 
     @schedule.setter
     def schedule(self, value):
-        sc = MixSchedule(int(value[0]), int(value[1]))
+        """(lanes, groups_per_cu[, lds_groups_per_cu = 0]), cbp_mix_schedule_t."""
+        sc = MixSchedule(int(value[0]), int(value[1]), int(value[2]) if len(value) > 2 else 0)
         check(lib().cbp_mix_set_schedule(self._h, ctypes.byref(sc)))
 
     def workspace_size(self, batch, algo="cbp", **kw):
@@ -418,14 +419,14 @@ class Mix:
 
     def tune(self, llr, frame_code, frame_offset, max_iter, algo="cbp", out=None, stream=None, **kw):
         """Times every candidate schedule on this batch and keeps the fastest.
-        Returns ((lanes, groups_per_cu), ms)."""
+        Returns ((lanes, groups_per_cu, lds_groups_per_cu), ms)."""
         import torch
         args, bits, iters, B = self._args(algo, llr, frame_code, frame_offset, max_iter, out, kw)
         s = stream if stream is not None else torch.cuda.current_stream(llr.device)
         best, ms = MixSchedule(), ctypes.c_float()
         with torch.cuda.device(llr.device):
             check(lib().cbp_mix_tune(*args, ctypes.c_void_p(s.cuda_stream), ctypes.byref(best), ctypes.byref(ms)))
-        return (best.lanes, best.groups_per_cu), ms.value
+        return (best.lanes, best.groups_per_cu, best.lds_groups_per_cu), ms.value
 
     def graph(self, llr, frame_code, frame_offset, max_iter, algo="cbp", workspace=None, out=None, **kw):
         """Captures one decode of these buffers into a HIP graph.  Returns (graph, bits, iters)."""

@@ -136,6 +136,23 @@ constexpr int64_t kLdsPlanBytes = (int64_t)160 << 10;
 LdsItem lds_item(int algo, const SparseDev &g);
 // Frames per workgroup that fit in lds_limit bytes (0: none).
 int lds_frames(const LdsItem &it, int64_t lds_limit);
+// Mixed batches: workgroups of kLdsMixThreads threads, kLdsMixGroupsPerCu per
+// CU; code c runs frames[c] (1, 2, 4 or 8; 0: not in this launch) frames per
+// workgroup with layout items[c] from its queue (qstart / perm / counter as
+// filled by launch_mix_prepare), frame f's LLRs and decisions at offset[f].
+constexpr int kLdsMixThreads = 512;
+constexpr int kLdsMixGroupsPerCu = 2;  // the LDS budget of a workgroup: half a CU
+// Raises the kernel's dynamic-LDS limit to lds (done when a plan is set up on
+// a device, outside any graph capture).
+hipError_t prepare_mix_lds(int algo, size_t lds);
+hipError_t launch_mix_lds(int algo, const SparseDev *codes, const LdsItem *items, const int *frames, int ncodes,
+                          int groups, size_t lds, const float *llr, uint8_t *bits, int32_t *iters,
+                          const int64_t *qstart, const int32_t *perm, const int64_t *offset, unsigned int *counter,
+                          int max_iter, const Params &p, hipStream_t s);
+// counter[c] = the length of code c's queue where frames[c] > 0, else 0: the
+// streamed kernel's counters when the LDS-staged kernel takes those codes.
+hipError_t launch_mix_exhaust(const int *frames, const int64_t *qstart, int ncodes, unsigned int *counter,
+                              hipStream_t s);
 // Persistent launch over frames 0 .. nf-1 (counter: 4 bytes, reset by the call).
 hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uint8_t *bits, int32_t *iters,
                              int64_t nf, int max_iter, const Params &p, unsigned int *counter, int device,

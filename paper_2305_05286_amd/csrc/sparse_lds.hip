@@ -29,6 +29,7 @@
 // contains a barrier is taken by the whole workgroup (its condition comes
 // from LDS after a barrier).
 #include <cstdlib>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "phi.hpp"
@@ -45,26 +46,48 @@ __global__ __launch_bounds__(kLdsFillBlock) void lds_zero_kernel(unsigned int *p
     if (tid_x() == 0) *p = 0u;
 }
 
+// Where a launch takes its frames: entries [qs, qs + qn) of a queue filled
+// by a counter (frame = perm[qs + k], or k without perm), the frame's LLRs and
+// decisions at element offset[frame] (frame * N without offset).
+struct LdsQueue {
+    const int32_t *perm;
+    const int64_t *offset;
+    int64_t qs, qn;
+    unsigned int *counter;
+};
+
 // The persistent slot loop shared by the decoders: kF frame slots of
-// it.bytes each in dynamic LDS; `load(f, frame)` runs Step 1 on a fresh slot
-// (all threads, no barrier), `sweep(live, s1)` one sweep of the live slots
-// (bit f of s1: slot f's first sweep; it ends with a barrier).  Decisions are
-// bytes at it.xb in each slot.
+// it.bytes each in dynamic LDS; `load(f, off)` runs Step 1 on a fresh slot
+// whose frame starts at element off (all threads, no barrier), `sweep(live,
+// s1)` one sweep of the live slots (bit f of s1: slot f's first sweep; it
+// ends with a barrier).  Decisions are bytes at it.xb in each slot.  Returns
+// once the queue is exhausted and every slot has stopped.
 template <int kF, int kT, class Load, class Sweep>
 __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const LdsItem &it, uint8_t *bits,
-                                          int32_t *iters, int64_t nf, int max_iter, const Params &p,
-                                          unsigned int *counter, Load &&load, Sweep &&sweep) {
-    __shared__ int64_t sFrame[kF];
+                                          int32_t *iters, const LdsQueue &q, int max_iter, const Params &p,
+                                          Load &&load, Sweep &&sweep) {
+    __shared__ int64_t sFrame[kF], sOff[kF];  // frame (-1: none) and its element offset
     __shared__ int sT[kF], sBad[kF], sFresh[kF];
     const int tid = tid_x();
     auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
+    auto claim = [&](int f) {  // one thread
+        const int64_t k = (int64_t)atomicAdd(q.counter, 1u);
+        int64_t fr = -1, off = 0;
+        if (k < q.qn) {
+            fr = q.perm ? (int64_t)q.perm[q.qs + k] : k;
+            off = q.offset ? q.offset[fr] : fr * (int64_t)g.N;
+        }
+        sFrame[f] = fr;
+        sOff[f] = off;
+        sT[f] = 0;
+    };
     auto load_fresh = [&]() {
         for (int f = 0; f < kF; ++f)
-            if (sFresh[f] && sFrame[f] < nf) load(f, sFrame[f]);
+            if (sFresh[f] && sFrame[f] >= 0) load(f, sOff[f]);
     };
+    __syncthreads();  // a previous loop's last reads of the slot table are done
     if (tid < kF) {
-        sFrame[tid] = (int64_t)atomicAdd(counter, 1u);
-        sT[tid] = 0;
+        claim(tid);
         sFresh[tid] = 1;
     }
     __syncthreads();
@@ -75,7 +98,7 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
         if (tid < kF) sBad[tid] = 0;
         __syncthreads();
         uint32_t live = 0;
-        for (int f = 0; f < kF; ++f) live |= (uint32_t)(sFrame[f] < nf) << f;
+        for (int f = 0; f < kF; ++f) live |= (uint32_t)(sFrame[f] >= 0) << f;
         // a row per thread, its column and decision loads issued together (the
         // column table is padded past E; entries past the row name other
         // columns and are masked)
@@ -105,18 +128,15 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
                 done |= 1u << f;
         for (int f = 0; f < kF; ++f) {
             if (!((done >> f) & 1u)) continue;
-            const int64_t fr = sFrame[f];
+            const int64_t off = sOff[f];
             const uint8_t *xb = Xp(f);
-            for (int v = tid; v < g.N; v += kT) bits[fr * g.N + v] = xb[v];
-            if (tid == 0) iters[fr] = sT[f];
+            for (int v = tid; v < g.N; v += kT) bits[off + v] = xb[v];
+            if (tid == 0) iters[sFrame[f]] = sT[f];
         }
-        __syncthreads();  // every thread has read sFrame / sT before they change
+        __syncthreads();  // every thread has read sFrame / sOff / sT before they change
         if (tid < kF) {
             const bool d = (done >> tid) & 1u;
-            if (d) {
-                sFrame[tid] = (int64_t)atomicAdd(counter, 1u);
-                sT[tid] = 0;
-            }
+            if (d) claim(tid);
             sFresh[tid] = d;
         }
         __syncthreads();
@@ -125,7 +145,7 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
         live = 0;
         uint32_t fresh = 0, s1 = 0;
         for (int f = 0; f < kF; ++f) {
-            const bool on = sFrame[f] < nf;
+            const bool on = sFrame[f] >= 0;
             live |= (uint32_t)on << f;
             fresh |= (uint32_t)(on && sFresh[f] != 0) << f;
             s1 |= (uint32_t)(sT[f] == 0) << f;
@@ -140,10 +160,9 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
 // CBP.  kMin: the normalized min-sum check rule (beliefs = (min1 | parity,
 // min2)).  kT threads per workgroup.
 template <bool kMin, int kF, int kT>
-__global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *__restrict__ llr,
-                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
-                                                     int64_t nf, int max_iter, Params p, unsigned int *counter,
-                                                     LdsItem it) {
+__device__ __forceinline__ void cbp_lds_body(const SparseDev &g, const float *__restrict__ llr,
+                                             uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                             const LdsQueue &q, int max_iter, Params p, const LdsItem &it) {
     extern __shared__ uint4 s_dyn[];
     const int tid = tid_x();
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
@@ -207,11 +226,11 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
         Op(f)[rr.x] = make_float2(with_sign(Mx, par), Sr);
     };
     // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
-    auto load = [&](int f, int64_t fr) {
+    auto load = [&](int f, int64_t off) {
         float *Q = Qp(f), *R = Rp(f);
         uint8_t *xb = Xp(f);
         for (int v = tid; v < g.N; v += kT) {
-            const float l = llr[fr * g.N + v] * us;
+            const float l = llr[off + v] * us;
             Q[v] = l;
             xb[v] = l < 0.0f;
         }
@@ -249,7 +268,15 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
             __syncthreads();
         }
     };
-    run_slots<kF, kT>(g, base, it, bits, iters, nf, max_iter, p, counter, load, sweep);
+    run_slots<kF, kT>(g, base, it, bits, iters, q, max_iter, p, load, sweep);
+}
+
+template <bool kMin, int kF, int kT>
+__global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *__restrict__ llr,
+                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                     int64_t nf, int max_iter, Params p, unsigned int *counter,
+                                                     LdsItem it) {
+    cbp_lds_body<kMin, kF, kT>(g, llr, bits, iters, LdsQueue{nullptr, nullptr, 0, nf, counter}, max_iter, p, it);
 }
 
 // Layered (kFlood false) and flooding BP, Sec. II-A / II-B, with the
@@ -271,10 +298,9 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
 // and the sweep ends with the posterior L + sum and the decisions of every
 // variable.
 template <bool kFlood, bool kMin, int kF, int kT>
-__global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__restrict__ llr,
-                                                    uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
-                                                    int64_t nf, int max_iter, Params p, unsigned int *counter,
-                                                    LdsItem it) {
+__device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__restrict__ llr,
+                                            uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                            const LdsQueue &q, int max_iter, Params p, const LdsItem &it) {
     extern __shared__ uint4 s_dyn[];
     const int tid = tid_x();
     const float us = kMin ? 1.0f : kLog2e;  // log2 units for the log-tanh rule
@@ -347,12 +373,12 @@ __global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__
             if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
         }
     };
-    __shared__ int64_t sCur[kF];  // the slot's frame, for the flooding posterior
+    __shared__ int64_t sCur[kF];  // the slot's frame offset, for the flooding posterior
     auto load = [&](int f, int64_t fr) {
         float *Lam = Lp(f), *R = Rp(f);
         uint8_t *xb = Xp(f);
         for (int v = tid; v < g.N; v += kT) {
-            const float l = llr[fr * g.N + v] * us;
+            const float l = llr[fr + v] * us;
             Lam[v] = l;
             xb[v] = l < 0.0f;
             if constexpr (kFlood) Ap(f)[v] = 0.0f;
@@ -458,7 +484,7 @@ __global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__
                 float *Lam = Lp(f), *A = Ap(f);
                 uint8_t *xb = Xp(f);
                 for (int v = tid; v < g.N; v += kT) {
-                    const float lm = flood_posterior(llr[fr * g.N + v], us, A[v]);
+                    const float lm = flood_posterior(llr[fr + v], us, A[v]);
                     Lam[v] = lm;
                     xb[v] = lm < 0.0f;
                     A[v] = 0.0f;
@@ -466,7 +492,65 @@ __global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__
             }
         }
     };
-    run_slots<kF, kT>(g, base, it, bits, iters, nf, max_iter, p, counter, load, sweep);
+    run_slots<kF, kT>(g, base, it, bits, iters, q, max_iter, p, load, sweep);
+}
+
+template <bool kFlood, bool kMin, int kF, int kT>
+__global__ __launch_bounds__(kT) void bp_lds_kernel(SparseDev g, const float *__restrict__ llr,
+                                                    uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                    int64_t nf, int max_iter, Params p, unsigned int *counter,
+                                                    LdsItem it) {
+    bp_lds_body<kFlood, kMin, kF, kT>(g, llr, bits, iters, LdsQueue{nullptr, nullptr, 0, nf, counter}, max_iter, p,
+                                      it);
+}
+
+// Element i of a device array of structs that no launch writes, read with
+// scalar loads (the index is workgroup-uniform).
+template <class T>
+__device__ __forceinline__ T ldc_struct(const T *p, int64_t i) {
+    static_assert(sizeof(T) % 4 == 0, "read as words");
+    T out;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p + i);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = ldc(src, k);
+    return out;
+}
+
+// Mixed batches: every code c with frames[c] > 0 frames per workgroup (the
+// codes whose frame fits the launch's LDS) is decoded from its queue (frames
+// perm[qstart[c] .. qstart[c + 1]), claimed through counter[c]); a workgroup
+// starts at code (its index mod ncodes) and moves on once that code's queue
+// is exhausted and its slots have stopped.  Codes with frames[c] = 0 are
+// left to the streamed kernel, which runs next and finds the others' queues
+// exhausted.
+template <int kAlgo, int kT>
+__global__ __launch_bounds__(kT) void mix_lds_kernel(const SparseDev *codes, const LdsItem *items,
+                                                     const int *frames, int ncodes, const float *__restrict__ llr,
+                                                     uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                     const int64_t *qstart, const int32_t *perm,
+                                                     const int64_t *offset, unsigned int *counter, int max_iter,
+                                                     Params p) {
+    for (int ci = 0; ci < ncodes; ++ci) {
+        const int c = (gid_x() + ci) % ncodes;
+        const int F = ldc(frames, c);
+        if (F == 0) continue;
+        const SparseDev g = ldc_struct(codes, c);
+        const LdsItem it = ldc_struct(items, c);
+        const LdsQueue q{perm, offset, ldc(qstart, c), ldc(qstart, c + 1) - ldc(qstart, c), counter + c};
+        auto go = [&](auto fc) {
+            constexpr int kF = decltype(fc)::value;
+            if constexpr (kAlgo == kCBP || kAlgo == kCBPNMS)
+                cbp_lds_body<kAlgo == kCBPNMS, kF, kT>(g, llr, bits, iters, q, max_iter, p, it);
+            else
+                bp_lds_body<kAlgo == kFBPNMS || kAlgo == kFBP, kAlgo == kLBPNMS || kAlgo == kFBPNMS, kF, kT>(
+                    g, llr, bits, iters, q, max_iter, p, it);
+        };
+        if (F >= 8) go(std::integral_constant<int, 8>{});
+        else if (F >= 4) go(std::integral_constant<int, 4>{});
+        else if (F >= 2) go(std::integral_constant<int, 2>{});
+        else go(std::integral_constant<int, 1>{});
+    }
 }
 
 template <class K>
@@ -567,6 +651,53 @@ hipError_t launch_sparse_lds(int algo, const SparseDev &g, const float *llr, uin
     case 4: return launch_algo<4, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
     case 2: return launch_algo<2, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
     default: return launch_algo<1, 512>(algo, groups, lds, s, g, llr, bits, iters, nf, max_iter, p, counter, it);
+    }
+}
+
+namespace {
+__global__ __launch_bounds__(kLdsFillBlock) void mix_exhaust_kernel(const int *frames, const int64_t *qstart,
+                                                                    int ncodes, unsigned int *counter) {
+    for (int c = tid_x(); c < ncodes; c += kLdsFillBlock)
+        counter[c] = frames[c] > 0 ? (unsigned int)(qstart[c + 1] - qstart[c]) : 0u;
+}
+}  // namespace
+
+hipError_t launch_mix_exhaust(const int *frames, const int64_t *qstart, int ncodes, unsigned int *counter,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(mix_exhaust_kernel, dim3(1), dim3(kLdsFillBlock), 0, s, frames, qstart, ncodes, counter);
+    return hipGetLastError();
+}
+
+hipError_t prepare_mix_lds(int algo, size_t lds) {
+    auto go = [&](auto *k) {
+        if (lds <= (64u << 10)) return hipSuccess;
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    };
+    switch (algo) {
+    case kCBP: return go(mix_lds_kernel<kCBP, kLdsMixThreads>);
+    case kCBPNMS: return go(mix_lds_kernel<kCBPNMS, kLdsMixThreads>);
+    case kLBPNMS: return go(mix_lds_kernel<kLBPNMS, kLdsMixThreads>);
+    case kFBPNMS: return go(mix_lds_kernel<kFBPNMS, kLdsMixThreads>);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mix_lds(int algo, const SparseDev *codes, const LdsItem *items, const int *frames, int ncodes,
+                          int groups, size_t lds, const float *llr, uint8_t *bits, int32_t *iters,
+                          const int64_t *qstart, const int32_t *perm, const int64_t *offset, unsigned int *counter,
+                          int max_iter, const Params &p, hipStream_t s) {
+    auto go = [&](auto *k) {
+        hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(kLdsMixThreads), lds, s, codes, items, frames, ncodes, llr,
+                           bits, iters, qstart, perm, offset, counter, max_iter, p);
+        return hipGetLastError();
+    };
+    switch (algo) {
+    case kCBP: return go(mix_lds_kernel<kCBP, kLdsMixThreads>);
+    case kCBPNMS: return go(mix_lds_kernel<kCBPNMS, kLdsMixThreads>);
+    case kLBPNMS: return go(mix_lds_kernel<kLBPNMS, kLdsMixThreads>);
+    case kFBPNMS: return go(mix_lds_kernel<kFBPNMS, kLdsMixThreads>);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -251,14 +251,16 @@ def test_mix_plan_validation(L):
     fam = mixed_family()
     handles = [cbp.Code.from_workload(c) for c in fam]
     mix = cbp.Mix(handles)
-    assert mix.schedule == (384, 0)                  # lcm(16, 32, 64, 128, 384) fills whole waves
+    assert mix.schedule == (384, 0, 0)               # lcm(16, 32, 64, 128, 384) fills whole waves
     mix.schedule = (768, 2)
-    assert mix.schedule == (768, 2)
-    for bad in [(384 + 16, 0), (0, 0), (1152, 0), (384, -1)]:
+    assert mix.schedule == (768, 2, 0)
+    mix.schedule = (768, 2, 1)                       # LDS-staged part: one workgroup per CU
+    assert mix.schedule == (768, 2, 1)
+    for bad in [(384 + 16, 0), (0, 0), (1152, 0), (384, -1), (384, 2, 3), (384, 2, -1)]:
         with pytest.raises(cbp.CbpError):
             mix.schedule = bad
     small = cbp.Mix([cbp.Code.from_workload(c) for c in fam if c.Z == 16])
-    assert small.schedule == (64, 0)                 # 16 -> doubled to a whole wave
+    assert small.schedule == (64, 0, 0)              # 16 -> doubled to a whole wave
     # Z values whose workgroup would need more than 1024 lanes, and a non-QC code
     q96 = cbp.Code.from_qc(np.array([[0, 1, -1], [2, 0, 1]]), 96)
     q100 = cbp.Code.from_qc(np.array([[0, 1, -1], [2, 0, 1]]), 100)

@@ -99,6 +99,42 @@ def test_mixed_equals_single_code_decoder():
         assert (gb == sb.cpu().numpy()).all(), codes[c].name
 
 
+@pytest.mark.parametrize("algo", ["cbp", "lbp_nms", "fbp_nms"])
+def test_mixed_lds_part_equals_streamed(algo):
+    """With lds_groups_per_cu > 0 the codes whose frame fits half a CU's LDS are decoded staged
+    in LDS on a second stream beside the streamed launch; with 0 every code streams.  Both give
+    the same decisions and sweep counts bit for bit, and so does a graph replay of the split
+    launch."""
+    codes = list(mixed_family())
+    b = make_mixed_batch(codes, 3000, key=(31, 3))
+    mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])
+    lanes, groups = mix.schedule[:2]
+    say(f"[gpu] mixed {algo}: LDS part against all streamed")
+    mix.schedule = (lanes, 3, 0)
+    sbits, siters = mix.decode(*to_dev(b), 25, algo)
+    torch.cuda.synchronize()
+    for lg in (1, 2):
+        mix.schedule = (lanes, 3, lg)
+        bits, iters = mix.decode(*to_dev(b), 25, algo)
+        torch.cuda.synchronize()
+        assert np.array_equal(iters.cpu().numpy(), siters.cpu().numpy()), lg
+        assert np.array_equal(bits.cpu().numpy(), sbits.cpu().numpy()), lg
+    # captured: the fork to the second stream and the join are part of the graph
+    mix.schedule = (lanes, 3, 1)
+    llr, fc, fo = to_dev(b)
+    gbits = torch.full_like(bits, 7)
+    giters = torch.full_like(iters, -7)
+    g, _, _ = mix.graph(llr, fc, fo, 25, algo, out=(gbits, giters))
+    for rep in range(3):
+        gbits.fill_(7)
+        giters.fill_(-7)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(giters.cpu().numpy(), siters.cpu().numpy()), rep
+        assert np.array_equal(gbits.cpu().numpy(), sbits.cpu().numpy()), rep
+
+
 def test_mixed_malformed_frames_are_skipped():
     codes = small_family()[:4]
     b = make_mixed_batch(codes, 200, key=(31, 3))
@@ -129,13 +165,13 @@ def test_mixed_malformed_frames_are_skipped():
 def test_mixed_schedules_tuner_and_graph_replays():
     codes = list(mixed_family())
     mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])
-    lanes0, g0 = mix.schedule
-    assert lanes0 % 384 == 0 and g0 == 0
+    lanes0, g0, l0 = mix.schedule
+    assert lanes0 % 384 == 0 and g0 == 0 and l0 == 0
     b = make_mixed_batch(codes, 3000, key=(31, 4))
     llr, fc, fo = to_dev(b)
     say("[gpu] mixed schedules")
     ref_bits, ref_iters = mix.decode(llr, fc, fo, 25, "cbp")
-    for sched in [(lanes0, 1), (2 * lanes0, 0), (lanes0, 2)]:
+    for sched in [(lanes0, 1), (2 * lanes0, 0), (lanes0, 2), (lanes0, 2, 1), (lanes0, 3, 2)]:
         mix.schedule = sched
         bb, ii = mix.decode(llr, fc, fo, 25, "cbp")
         assert torch.equal(bb, ref_bits) and torch.equal(ii, ref_iters), sched
