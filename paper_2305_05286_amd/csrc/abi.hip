@@ -260,8 +260,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         // level pointers, then (16-byte aligned) one int4 per row in level order
         const size_t lvl_pad = (4 - ((size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() +
                                      (size_t)c->nlev + 1) % 4) % 4;
-        // then one int4 per edge in the same order, then the level edge pointers
-        const size_t lvl_ints = (size_t)c->nlev + 1 + lvl_pad + 4 * (size_t)M + 4 * (size_t)E + (size_t)c->nlev + 1;
+        // then one int4 per edge in the same order, the level edge pointers and
+        // the row of each of those edges
+        const size_t lvl_ints =
+            (size_t)c->nlev + 1 + lvl_pad + 4 * (size_t)M + 4 * (size_t)E + (size_t)c->nlev + 1 + (size_t)E;
         const size_t ints =
             (size_t)(M + 1) + 4 * (size_t)E + 3 * P + (size_t)N + sht.size() + qt.size() + lvl_ints;
         const size_t bytes = ints * 4 + (size_t)E + P + 64;
@@ -315,7 +317,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         }
         p += 4 * (size_t)M;
         {
-            int *eptr = p + 4 * (size_t)E;
+            int *eptr = p + 4 * (size_t)E, *erow = eptr + c->nlev + 1;
             int64_t k = 0;
             for (int l = 0; l < c->nlev; ++l) {
                 eptr[l] = (int)k;
@@ -326,6 +328,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
                         p[4 * k + 1] = c->pred_edge[e];
                         p[4 * k + 2] = c->pred_row[e];
                         p[4 * k + 3] = e | (int)((uint32_t)c->first[e] << 30);
+                        erow[k] = i;
                     }
                 }
             }
@@ -368,6 +371,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         t.g.lvl_edges = reinterpret_cast<const int4 *>(d);
         d += 4 * (size_t)E;
         t.g.lvl_eptr = d;
+        t.g.lvl_erow = d + c->nlev + 1;
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;

@@ -68,6 +68,7 @@ struct SparseDev {
     const int *lvl_eptr;  // [nlev+1] first entry of each level in lvl_edges
     const int4 *lvl_edges;// [E] the edges of lvl_rows' rows in that order: (column,
                           //      pred_edge, pred_row, edge | first << 30)
+    const int *lvl_erow;  // [E] the row of each lvl_edges entry
 };
 
 // col_idx, pred_edge, pred_row and first are readable (zeros) for this many

@@ -348,11 +348,11 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
     };
     // C2V of the edge of record rec of slot f (eq. equ_s2e4 or the min-sum
     // rule), then R and Lambda (eq. equ_s2e12) or the C2V sum
-    auto edge = [&](int f, const int4 &rec) {
+    auto edge = [&](int f, const int4 &rec, int row) {
         const int col = rec.x, e = rec.w & 0x3fffffff;
         const uint32_t fl = (uint32_t)rec.w >> 30;
         float *Lam = Lp(f), *R = Rp(f);
-        const float2 st = Sp(f)[g.edge_row[e]];
+        const float2 st = Sp(f)[row];
         const float m1 = abs_bits(st.x), m2 = st.y;
         const bool par = sign_bit(st.x);
         const float q = Lam[col] - R[e];
@@ -423,11 +423,11 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
         }
         Sp(f)[rr.x] = make_float2(with_sign(m1, par), m2);
     };
-    auto c2v_edge = [&](int f, const int4 &rec) {
+    auto c2v_edge = [&](int f, const int4 &rec, int row) {
         const int col = rec.x, e = rec.w & 0x3fffffff;
         const uint32_t fl = (uint32_t)rec.w >> 30;
         float *Lam = Lp(f), *R = Rp(f);
-        const float2 st = Sp(f)[g.edge_row[e]];
+        const float2 st = Sp(f)[row];
         const float m1 = abs_bits(st.x), m2 = st.y;
         const bool par = sign_bit(st.x);
         const float q = Lam[col], t = abs_bits(R[e]);
@@ -439,43 +439,60 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
         if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
     };
     auto sweep = [&](uint32_t live, uint32_t) {
-        if constexpr (!kFlood) {
-            for (int l = 0; l < g.nlev; ++l) {
-                const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
-                const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
+        // A thread's first edge record of a level (and the edge's row) is read
+        // at the start of the level before, its first row record at the start
+        // of the level; layered BP keeps the edge record from phase A to C.
+        int4 recE = make_int4(0, 0, 0, 0);
+        int rowE = 0;
+        {
+            const int ea = ldc(g.lvl_eptr, 0);
+            if (tid < kF * (ldc(g.lvl_eptr, 1) - ea)) {
+                recE = g.lvl_edges[ea + tid / kF];
+                rowE = g.lvl_erow[ea + tid / kF];
+            }
+        }
+        for (int l = 0; l < g.nlev; ++l) {
+            const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
+            const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
+            int4 recR = make_int4(0, 0, 0, 0), nextE = make_int4(0, 0, 0, 0);
+            int nextRow = 0;
+            if (tid < kF * rows) recR = g.lvl_rows[ra + tid / kF];
+            if (l + 1 < g.nlev && tid < kF * (ldc(g.lvl_eptr, l + 2) - (ea + en))) {
+                nextE = g.lvl_edges[ea + en + tid / kF];
+                nextRow = g.lvl_erow[ea + en + tid / kF];
+            }
+            if constexpr (!kFlood) {
                 for (int i = tid; i < kF * en; i += kT) {
                     const int j = i / kF, f = i - j * kF;
-                    if ((live >> f) & 1u) term_edge(f, g.lvl_edges[ea + j]);
+                    if ((live >> f) & 1u) term_edge(f, i == tid ? recE : g.lvl_edges[ea + j]);
                 }
                 __syncthreads();
                 for (int i = tid; i < kF * rows; i += kT) {
                     const int j = i / kF, f = i - j * kF;
-                    if ((live >> f) & 1u) term_fold(f, g.lvl_rows[ra + j]);
+                    if ((live >> f) & 1u) term_fold(f, i == tid ? recR : g.lvl_rows[ra + j]);
                 }
                 __syncthreads();
                 for (int i = tid; i < kF * en; i += kT) {
                     const int j = i / kF, f = i - j * kF;
-                    if ((live >> f) & 1u) c2v_edge(f, g.lvl_edges[ea + j]);
+                    if ((live >> f) & 1u)
+                        c2v_edge(f, i == tid ? recE : g.lvl_edges[ea + j], i == tid ? rowE : g.lvl_erow[ea + j]);
+                }
+                __syncthreads();
+            } else {
+                for (int i = tid; i < kF * rows; i += kT) {
+                    const int j = i / kF, f = i - j * kF;
+                    if ((live >> f) & 1u) row_fold(f, i == tid ? recR : g.lvl_rows[ra + j]);
+                }
+                __syncthreads();
+                for (int i = tid; i < kF * en; i += kT) {
+                    const int j = i / kF, f = i - j * kF;
+                    if ((live >> f) & 1u)
+                        edge(f, i == tid ? recE : g.lvl_edges[ea + j], i == tid ? rowE : g.lvl_erow[ea + j]);
                 }
                 __syncthreads();
             }
-            return;
-        }
-        for (int l = 0; l < g.nlev; ++l) {
-            const int ra = ldc(g.lvl_ptr, l), rows = ldc(g.lvl_ptr, l + 1) - ra;
-            for (int i = tid; i < kF * rows; i += kT) {
-                const int j = i / kF, f = i - j * kF;
-                if (!((live >> f) & 1u)) continue;
-                row_fold(f, g.lvl_rows[ra + j]);
-            }
-            __syncthreads();
-            const int ea = ldc(g.lvl_eptr, l), en = ldc(g.lvl_eptr, l + 1) - ea;
-            for (int i = tid; i < kF * en; i += kT) {
-                const int j = i / kF, f = i - j * kF;
-                if (!((live >> f) & 1u)) continue;
-                edge(f, g.lvl_edges[ea + j]);
-            }
-            __syncthreads();
+            recE = nextE;
+            rowE = nextRow;
         }
         if constexpr (kFlood) {  // eq. equ_s2e6, then the decisions (eq. equ_s2e7)
             for (int f = 0; f < kF; ++f) {
@@ -522,8 +539,8 @@ __device__ __forceinline__ T ldc_struct(const T *p, int64_t i) {
 // perm[qstart[c] .. qstart[c + 1]), claimed through counter[c]); a workgroup
 // starts at code (its index mod ncodes) and moves on once that code's queue
 // is exhausted and its slots have stopped.  Codes with frames[c] = 0 are
-// left to the streamed kernel, which runs next and finds the others' queues
-// exhausted.
+// left to the streamed kernel, which runs beside this one and finds the
+// others' queues exhausted.
 template <int kAlgo, int kT>
 __global__ __launch_bounds__(kT) void mix_lds_kernel(const SparseDev *codes, const LdsItem *items,
                                                      const int *frames, int ncodes, const float *__restrict__ llr,
