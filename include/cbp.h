@@ -307,10 +307,12 @@ int cbp_mix_workspace_size(const cbp_mix_t *mix, int32_t decoder, int64_t batch,
  *                [0, llr_elems) (its decisions are not written).
  *   workspace    device buffer of at least cbp_mix_workspace_size bytes, 256-byte
  *                aligned (CBP_EINVAL otherwise).
- * The call only launches kernels on `stream`: no allocation, no host
+ * The call only launches kernels on `stream` (with lds_groups_per_cu > 0 also
+ * on the plan's own side stream, forked from `stream` by an event and joined
+ * back to it before the call's work ends): no allocation, no host
  * synchronisation, no memset node, so it may be captured in a HIP graph once
  * the plan has been used on the device (the first call uploads the code
- * tables) — see cbp_mix_graph_create.
+ * tables and creates the side stream) — see cbp_mix_graph_create.
  */
 int cbp_mix_decode(const cbp_mix_t *mix, int32_t decoder, const float *llr_in, int64_t llr_elems,
                    const int32_t *frame_code, const int64_t *frame_offset, uint8_t *bits_out,

@@ -99,7 +99,7 @@ def test_mixed_equals_single_code_decoder():
         assert (gb == sb.cpu().numpy()).all(), codes[c].name
 
 
-@pytest.mark.parametrize("algo", ["cbp", "lbp_nms", "fbp_nms"])
+@pytest.mark.parametrize("algo", ["cbp", "cbp_nms", "lbp_nms", "fbp_nms"])
 def test_mixed_lds_part_equals_streamed(algo):
     """With lds_groups_per_cu > 0 the codes whose frame fits half a CU's LDS are decoded staged
     in LDS on a second stream beside the streamed launch; with 0 every code streams.  Both give
@@ -133,6 +133,53 @@ def test_mixed_lds_part_equals_streamed(algo):
         torch.cuda.synchronize()
         assert np.array_equal(giters.cpu().numpy(), siters.cpu().numpy()), rep
         assert np.array_equal(gbits.cpu().numpy(), sbits.cpu().numpy()), rep
+
+
+@pytest.mark.parametrize("subset", ["all_fit", "none_fit"])
+def test_mixed_lds_part_subsets_and_small_batches(subset):
+    """Plans whose codes all fit the LDS-staged part (the streamed launch then finds every queue
+    exhausted) or none do (no side launch), batches of 1, 2 and 5 frames (fewer than the
+    workgroups), malformed frames and an empty batch: the same results with and without the
+    LDS-staged part."""
+    codes = [c for c in mixed_family() if (c.Z <= 128) == (subset == "all_fit")]
+    mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])
+    lanes = mix.schedule[0]
+    for n in (1, 2, 5, 700):
+        b = make_mixed_batch(codes, n, key=(31, 6, n))
+        for algo in ("cbp", "lbp_nms", "fbp_nms"):
+            say(f"[gpu] mixed LDS part, {subset}: {algo}, {n} frames")
+            mix.schedule = (lanes, 2, 0)
+            sbits, siters = mix.decode(*to_dev(b), 25, algo)
+            torch.cuda.synchronize()
+            for lg in (1, 2):
+                mix.schedule = (lanes, 2, lg)
+                bits, iters = mix.decode(*to_dev(b), 25, algo)
+                torch.cuda.synchronize()
+                assert np.array_equal(iters.cpu().numpy(), siters.cpu().numpy()), (n, algo, lg)
+                assert np.array_equal(bits.cpu().numpy(), sbits.cpu().numpy()), (n, algo, lg)
+    # malformed frames are rejected before either launch sees a queue
+    b = make_mixed_batch(codes, 300, key=(31, 7))
+    llr, fc, fo = to_dev(b)
+    fc[4] = -1
+    fo[77] = llr.numel() - 3
+    out = {}
+    for lg in (0, 2):
+        say(f"[gpu] mixed LDS part, {subset}: malformed frames, lds_groups_per_cu {lg}")
+        mix.schedule = (lanes, 2, lg)
+        bits = torch.full((llr.numel(),), 7, dtype=torch.uint8, device="cuda")
+        iters = torch.zeros(300, dtype=torch.int32, device="cuda")
+        mix.decode(llr, fc, fo, 25, "cbp", out=(bits, iters))
+        torch.cuda.synchronize()
+        out[lg] = (bits.cpu().numpy(), iters.cpu().numpy())
+        assert out[lg][1][4] == -1 and out[lg][1][77] == -1
+        assert (np.delete(out[lg][1], [4, 77]) >= 0).all()
+    assert np.array_equal(out[0][0], out[2][0]) and np.array_equal(out[0][1], out[2][1])
+    # empty batch
+    e32 = torch.empty(0, dtype=torch.int32, device="cuda")
+    e64 = torch.empty(0, dtype=torch.int64, device="cuda")
+    _, iters = mix.decode(torch.zeros(16, dtype=torch.float32, device="cuda"), e32, e64, 10, "cbp",
+                          workspace=torch.empty(0, dtype=torch.uint8, device="cuda"))
+    assert iters.numel() == 0
 
 
 def test_mixed_malformed_frames_are_skipped():
