@@ -82,8 +82,9 @@ int cbp_code_levels(const cbp_code_t *code, int32_t *nlev, int32_t *lvl_ptr, int
 #define CBP_KERNEL_QC_STREAM 2 /* QC: messages streamed from device memory, any base     */
 #define CBP_KERNEL_SPARSE 4    /* any H: one frame per lane, persistent (lanes take new  */
                                /* frames as theirs stop), state per wave contiguous      */
-#define CBP_KERNEL_SPARSE_LDS 8 /* any H whose frame state (4N + 4E + 8M + N bytes,       */
-                               /* rounded; flooding BP 4N more) fits a CU's LDS: frames  */
+#define CBP_KERNEL_SPARSE_LDS 8 /* any H whose frame state (CBP 4N + 4E + 8M + N bytes,   */
+                               /* rounded; the BP decoders 4N + 4E + 8 x the rows of the */
+                               /* largest level, flooding 4N more) fits a CU's LDS: frames */
                                /* staged in LDS, each sweep level by level (see          */
                                /* cbp_code_levels), the edges of a level on separate     */
                                /* threads; persistent.  Every decoder, with stop_rule 0  */

@@ -65,7 +65,7 @@ struct cbp_code {
     // Row levels: rows that share no variable commute in the sequential
     // schedule, so a sweep may run level by level, each level's rows at once.
     // Rows sorted by (level, index): lvl_rows[lvl_ptr[l] .. lvl_ptr[l + 1]).
-    int nlev = 0;
+    int nlev = 0, lvl_maxrows = 0;
     std::vector<int> lvl_ptr, lvl_rows;
     bool qc = false;
     int mb = 0, nb = 0, Z = 0;
@@ -146,6 +146,7 @@ int finish_code(cbp_code *c) {
     c->nlev = nlev;
     c->lvl_ptr.assign(nlev + 1, 0);
     for (int i = 0; i < M; ++i) ++c->lvl_ptr[lev[i] + 1];
+    for (int l = 0; l < nlev; ++l) c->lvl_maxrows = std::max(c->lvl_maxrows, c->lvl_ptr[l + 1]);
     for (int l = 0; l < nlev; ++l) c->lvl_ptr[l + 1] += c->lvl_ptr[l];
     c->lvl_rows.resize(M);
     std::vector<int> fill(c->lvl_ptr.begin(), c->lvl_ptr.end() - 1);
@@ -317,6 +318,10 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         }
         p += 4 * (size_t)M;
         {
+            // position of every row in level order (the LDS-staged CBP kernel
+            // keeps the beliefs in that order)
+            std::vector<int> rpos(M);
+            for (int r = 0; r < M; ++r) rpos[c->lvl_rows[r]] = r;
             int *eptr = p + 4 * (size_t)E, *erow = eptr + c->nlev + 1;
             int64_t k = 0;
             for (int l = 0; l < c->nlev; ++l) {
@@ -326,9 +331,9 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
                     for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e, ++k) {
                         p[4 * k] = c->col_idx[e];
                         p[4 * k + 1] = c->pred_edge[e];
-                        p[4 * k + 2] = c->pred_row[e];
+                        p[4 * k + 2] = rpos[c->pred_row[e]];
                         p[4 * k + 3] = e | (int)((uint32_t)c->first[e] << 30);
-                        erow[k] = i;
+                        erow[k] = r - c->lvl_ptr[l];
                     }
                 }
             }
@@ -372,6 +377,7 @@ int ensure_device(const cbp_code *cc, int *device_out, const SparseDev **g,
         d += 4 * (size_t)E;
         t.g.lvl_eptr = d;
         t.g.lvl_erow = d + c->nlev + 1;
+        t.g.lvl_maxrows = c->lvl_maxrows;
         t.g.first = (const uint8_t *)((char *)buf + ints * 4);
         t.buf = buf;
         t.ready = true;
@@ -398,6 +404,7 @@ bool lds_kernel_fits(int algo, const cbp_code_t *code) {
     g.M = code->M;
     g.N = code->N;
     g.E = code->E < ((int64_t)1 << 30) ? (int)code->E : (1 << 30);
+    g.lvl_maxrows = code->lvl_maxrows;
     return lds_frames(lds_item(algo, g), kLdsPlanBytes) >= 1;
 }
 
@@ -814,6 +821,7 @@ int mix_ensure_device(cbp_mix *m, int *dev_out, const StreamCode **codes) {
                 g.M = m->codes[i]->M;
                 g.N = m->codes[i]->N;
                 g.E = (int)m->codes[i]->E;
+                g.lvl_maxrows = m->codes[i]->lvl_maxrows;
                 items[i] = lds_item(a, g);
                 int f = items[i].bytes > 0 ? (int)std::min<int64_t>(8, budget / items[i].bytes) : 0;
                 f = f >= 8 ? 8 : f >= 4 ? 4 : f >= 2 ? 2 : f;

@@ -67,8 +67,11 @@ struct SparseDev {
     const int4 *lvl_rows; // [M] (row, first edge, end edge, 0) by (level, index)
     const int *lvl_eptr;  // [nlev+1] first entry of each level in lvl_edges
     const int4 *lvl_edges;// [E] the edges of lvl_rows' rows in that order: (column,
-                          //      pred_edge, pred_row, edge | first << 30)
-    const int *lvl_erow;  // [E] the row of each lvl_edges entry
+                          //      pred_edge, level position of pred_row (its entry
+                          //      in lvl_rows), edge | first << 30)
+    const int *lvl_erow;  // [E] the position of each lvl_edges entry's row
+                          //      within its level
+    int lvl_maxrows;      // rows of the largest level
 };
 
 // col_idx, pred_edge, pred_row and first are readable (zeros) for this many
@@ -122,9 +125,10 @@ hipError_t launch_syndrome(const SparseDev &g, const uint8_t *bits, uint8_t *ok,
 
 // ---- CSR codes with each frame's state in LDS ------------------------------
 // Byte offsets of one frame's arrays in LDS: Q (CBP) or the posterior (BP)
-// [N] at 0, R [E] at r, the rows' beliefs (CBP) or fold states (BP) [M]
-// (float2) at om, decisions [N] at xb; bytes = 0 if the algorithm has no such
-// kernel.
+// [N] at 0, R [E] at r, the rows' beliefs (CBP, [M]) or the fold states of one
+// level's rows (BP, [lvl_maxrows]) (float2) at om, decisions [N] at xb (CBP;
+// BP decides from the posterior's sign); bytes = 0 if the algorithm has no
+// such kernel.
 struct LdsItem {
     int r, om, xb, bytes;
     int acc;  // flooding BP: the C2V sums [N] (0 otherwise)

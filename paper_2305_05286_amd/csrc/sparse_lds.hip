@@ -1,6 +1,6 @@
 // Any parity-check matrix (CSR) with each frame's whole state in LDS.
 //
-// A workgroup holds kF frames (Q [N], R [E], beliefs [M], decisions [N] of
+// A workgroup holds kF frames (Q [N], R [E], beliefs [M] by level position, decisions [N] of
 // each) in LDS and runs their sweeps together, level by level: the rows of
 // one level share no variable, so they commute in the paper's sequential row
 // order (Sec. IV-C) and are updated at once with exactly the sequential
@@ -56,20 +56,18 @@ struct LdsQueue {
     unsigned int *counter;
 };
 
-// The persistent slot loop shared by the decoders: kF frame slots of
-// it.bytes each in dynamic LDS; `load(f, off)` runs Step 1 on a fresh slot
-// whose frame starts at element off (all threads, no barrier), `sweep(live,
-// s1)` one sweep of the live slots (bit f of s1: slot f's first sweep; it
-// ends with a barrier).  Decisions are bytes at it.xb in each slot.  Returns
-// once the queue is exhausted and every slot has stopped.
-template <int kF, int kT, class Load, class Sweep>
-__device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const LdsItem &it, uint8_t *bits,
-                                          int32_t *iters, const LdsQueue &q, int max_iter, const Params &p,
-                                          Load &&load, Sweep &&sweep) {
+// The persistent slot loop shared by the decoders: kF frame slots in dynamic
+// LDS; `load(f, off)` runs Step 1 on a fresh slot whose frame starts at
+// element off (all threads, no barrier), `sweep(live, s1)` one sweep of the
+// live slots (bit f of s1: slot f's first sweep; it ends with a barrier),
+// `dec(f, v)` is slot f's decision on variable v (0 or 1).  Returns once the
+// queue is exhausted and every slot has stopped.
+template <int kF, int kT, class Load, class Sweep, class Dec>
+__device__ __forceinline__ void run_slots(const SparseDev &g, uint8_t *bits, int32_t *iters, const LdsQueue &q,
+                                          int max_iter, const Params &p, Load &&load, Sweep &&sweep, Dec &&dec) {
     __shared__ int64_t sFrame[kF], sOff[kF];  // frame (-1: none) and its element offset
     __shared__ int sT[kF], sBad[kF], sFresh[kF];
     const int tid = tid_x();
-    auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
     auto claim = [&](int f) {  // one thread
         const int64_t k = (int64_t)atomicAdd(q.counter, 1u);
         int64_t fr = -1, off = 0;
@@ -105,7 +103,6 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
         for (int i = tid; i < kF * g.M; i += kT) {
             const int j = i / kF, f = i - j * kF;
             if (!((live >> f) & 1u)) continue;
-            const uint8_t *xb = Xp(f);
             const int e0 = g.row_ptr[j], e1 = g.row_ptr[j + 1];
             uint32_t par = 0;
             for (int c0 = e0; c0 < e1; c0 += kLdsChunk) {
@@ -114,7 +111,7 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
 #pragma unroll
                 for (int c = 0; c < kLdsChunk; ++c) col[c] = g.col_idx[c0 + c];
 #pragma unroll
-                for (int c = 0; c < kLdsChunk; ++c) x[c] = xb[col[c]];
+                for (int c = 0; c < kLdsChunk; ++c) x[c] = dec(f, col[c]);
 #pragma unroll
                 for (int c = 0; c < kLdsChunk; ++c) par ^= c0 + c < e1 ? x[c] : 0u;
             }
@@ -129,8 +126,7 @@ __device__ __forceinline__ void run_slots(const SparseDev &g, char *base, const 
         for (int f = 0; f < kF; ++f) {
             if (!((done >> f) & 1u)) continue;
             const int64_t off = sOff[f];
-            const uint8_t *xb = Xp(f);
-            for (int v = tid; v < g.N; v += kT) bits[off + v] = xb[v];
+            for (int v = tid; v < g.N; v += kT) bits[off + v] = (uint8_t)dec(f, v);
             if (tid == 0) iters[sFrame[f]] = sT[f];
         }
         __syncthreads();  // every thread has read sFrame / sOff / sT before they change
@@ -197,11 +193,11 @@ __device__ __forceinline__ void cbp_lds_body(const SparseDev &g, const float *__
         const float term = kMin ? __builtin_fminf(__builtin_fabsf(qn), p.lmax) : phi2_clamped(qn, p.a, p.lmax);
         R[e] = with_sign(term, qn < 0.0f);
     };
-    // Step 2(1)d / 2(2) for row rr = (row, first edge, end edge) of slot f:
-    // the terms folded in ascending column order into the new belief (C2B,
-    // eqs. equ_s4e21 / equ_s4e23), kLdsChunk loads at a time (indices past the
-    // row clamped to its last edge)
-    auto row_fold = [&](int f, const int4 &rr) {
+    // Step 2(1)d / 2(2) for row rr = (row, first edge, end edge) of slot f, at
+    // level position pos: the terms folded in ascending column order into the
+    // new belief (C2B, eqs. equ_s4e21 / equ_s4e23), kLdsChunk loads at a time
+    // (indices past the row clamped to its last edge)
+    auto row_fold = [&](int f, const int4 &rr, int pos) {
         const float *R = Rp(f);
         float Mx = kMin ? __builtin_inff() : 0.0f, Sr = kMin ? __builtin_inff() : 0.0f;
         bool par = false;
@@ -223,7 +219,7 @@ __device__ __forceinline__ void cbp_lds_body(const SparseDev &g, const float *__
                 }
             }
         }
-        Op(f)[rr.x] = make_float2(with_sign(Mx, par), Sr);
+        Op(f)[pos] = make_float2(with_sign(Mx, par), Sr);
     };
     // Step 1: latest V2C = channel LLR, R = 0, x = [L < 0]
     auto load = [&](int f, int64_t off) {
@@ -263,12 +259,13 @@ __device__ __forceinline__ void cbp_lds_body(const SparseDev &g, const float *__
             for (int i = tid; i < kF * rows; i += kT) {
                 const int j = i / kF, f = i - j * kF;
                 if (!((live >> f) & 1u)) continue;
-                row_fold(f, i == tid ? recB : g.lvl_rows[ra + j]);
+                row_fold(f, i == tid ? recB : g.lvl_rows[ra + j], ra + j);
             }
             __syncthreads();
         }
     };
-    run_slots<kF, kT>(g, base, it, bits, iters, q, max_iter, p, load, sweep);
+    run_slots<kF, kT>(g, bits, iters, q, max_iter, p, load, sweep,
+                      [&](int f, int v) { return (uint32_t)Xp(f)[v]; });
 }
 
 template <bool kMin, int kF, int kT>
@@ -281,9 +278,14 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
 
 // Layered (kFlood false) and flooding BP, Sec. II-A / II-B, with the
 // normalized min-sum (kMin) or the log-tanh check rule, in the same layout:
-// the posterior Lambda [N] at 0, R [E], each row's fold state [M] (the two
-// smallest |Q| or the (max, rest) of g(|Q|), the parity in the first's sign
-// bit), the flooding C2V sums [N], decisions.  The same operations as the
+// the posterior Lambda [N] at 0, R [E], the fold states of one level's rows
+// (the two smallest |Q| or the (max, rest) of g(|Q|), the parity in the
+// first's sign bit; a row's state is used only within its level, so the
+// array holds the largest level, indexed by a row's position in its level),
+// the flooding C2V sums [N].  The decisions are Lambda's signs (whenever the
+// syndrome is taken, Lambda holds the value the decision is defined on: the
+// channel LLR, the value after a variable's last visit, or the flooding
+// posterior), so no decision array is kept.  The same operations as the
 // one-frame-per-lane kernel's row update (a fold pass, then a C2V pass), so
 // the results agree bit for bit.  Layered BP runs three phases per level
 // (see the sweep below).  Flooding BP keeps Lambda for the whole sweep, so
@@ -311,10 +313,10 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
     auto Rp = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.r); };
     auto Sp = [&](int f) { return reinterpret_cast<float2 *>(base + f * it.bytes + it.om); };
     auto Ap = [&](int f) { return reinterpret_cast<float *>(base + f * it.bytes + it.acc); };
-    auto Xp = [&](int f) { return reinterpret_cast<uint8_t *>(base + f * it.bytes + it.xb); };
 
-    // fold of row rr of slot f (V2C, eq. equ_s2e3 / equ_s2e10)
-    auto row_fold = [&](int f, const int4 &rr) {
+    // fold of row rr (position j in its level) of slot f (V2C, eq. equ_s2e3 /
+    // equ_s2e10)
+    auto row_fold = [&](int f, const int4 &rr, int j) {
         const float *Lam = Lp(f), *R = Rp(f);
         float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
         bool par = false;
@@ -344,18 +346,18 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
                 }
             }
         }
-        Sp(f)[rr.x] = make_float2(with_sign(m1, par), m2);
+        Sp(f)[j] = make_float2(with_sign(m1, par), m2);
     };
-    // C2V of the edge of record rec of slot f (eq. equ_s2e4 or the min-sum
-    // rule), then R and Lambda (eq. equ_s2e12) or the C2V sum
+    // flooding: C2V of the edge of record rec of slot f, its row at position
+    // row of the level (eq. equ_s2e4 or the min-sum rule), then R and the C2V
+    // sum
     auto edge = [&](int f, const int4 &rec, int row) {
         const int col = rec.x, e = rec.w & 0x3fffffff;
-        const uint32_t fl = (uint32_t)rec.w >> 30;
-        float *Lam = Lp(f), *R = Rp(f);
+        float *R = Rp(f), *A = Ap(f);
         const float2 st = Sp(f)[row];
         const float m1 = abs_bits(st.x), m2 = st.y;
         const bool par = sign_bit(st.x);
-        const float q = Lam[col] - R[e];
+        const float q = Lp(f)[col] - R[e];
         float rn;
         if constexpr (kMin) {
             const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
@@ -364,23 +366,13 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
             rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))), par ^ (q < 0.0f));
         }
         R[e] = rn;
-        if constexpr (kFlood) {
-            float *A = Ap(f);
-            A[col] = A[col] + rn;
-        } else {
-            const float lm = q + rn;
-            Lam[col] = lm;
-            if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
-        }
+        A[col] = A[col] + rn;
     };
     __shared__ int64_t sCur[kF];  // the slot's frame offset, for the flooding posterior
     auto load = [&](int f, int64_t fr) {
         float *Lam = Lp(f), *R = Rp(f);
-        uint8_t *xb = Xp(f);
         for (int v = tid; v < g.N; v += kT) {
-            const float l = llr[fr + v] * us;
-            Lam[v] = l;
-            xb[v] = l < 0.0f;
+            Lam[v] = llr[fr + v] * us;
             if constexpr (kFlood) Ap(f)[v] = 0.0f;
         }
         for (int e = tid; e < g.E; e += kT) R[e] = 0.0f;
@@ -399,7 +391,7 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
         Lam[col] = q;
         R[e] = with_sign(kMin ? __builtin_fminf(__builtin_fabsf(q), p.lmax) : phi2_clamped(q, p.a, p.lmax), q < 0.0f);
     };
-    auto term_fold = [&](int f, const int4 &rr) {
+    auto term_fold = [&](int f, const int4 &rr, int j) {
         const float *R = Rp(f);
         float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
         bool par = false;
@@ -421,11 +413,10 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
                 }
             }
         }
-        Sp(f)[rr.x] = make_float2(with_sign(m1, par), m2);
+        Sp(f)[j] = make_float2(with_sign(m1, par), m2);
     };
     auto c2v_edge = [&](int f, const int4 &rec, int row) {
         const int col = rec.x, e = rec.w & 0x3fffffff;
-        const uint32_t fl = (uint32_t)rec.w >> 30;
         float *Lam = Lp(f), *R = Rp(f);
         const float2 st = Sp(f)[row];
         const float m1 = abs_bits(st.x), m2 = st.y;
@@ -434,9 +425,7 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
         const float rn = kMin ? with_sign(p.alpha * ((t == m1) ? m2 : m1), par ^ (q < 0.0f))
                               : with_sign(phi2(excl_sum(m1, m2, t)), par ^ (q < 0.0f));  // eq. equ_s2e4
         R[e] = rn;
-        const float lm = q + rn;  // eq. equ_s2e12
-        Lam[col] = lm;
-        if (fl & kLastVisit) Xp(f)[col] = lm < 0.0f;  // eq. equ_s2e7
+        Lam[col] = q + rn;  // eq. equ_s2e12; its sign after the last visit is the decision (eq. equ_s2e7)
     };
     auto sweep = [&](uint32_t live, uint32_t) {
         // A thread's first edge record of a level (and the edge's row) is read
@@ -469,7 +458,7 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
                 __syncthreads();
                 for (int i = tid; i < kF * rows; i += kT) {
                     const int j = i / kF, f = i - j * kF;
-                    if ((live >> f) & 1u) term_fold(f, i == tid ? recR : g.lvl_rows[ra + j]);
+                    if ((live >> f) & 1u) term_fold(f, i == tid ? recR : g.lvl_rows[ra + j], j);
                 }
                 __syncthreads();
                 for (int i = tid; i < kF * en; i += kT) {
@@ -481,7 +470,7 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
             } else {
                 for (int i = tid; i < kF * rows; i += kT) {
                     const int j = i / kF, f = i - j * kF;
-                    if ((live >> f) & 1u) row_fold(f, i == tid ? recR : g.lvl_rows[ra + j]);
+                    if ((live >> f) & 1u) row_fold(f, i == tid ? recR : g.lvl_rows[ra + j], j);
                 }
                 __syncthreads();
                 for (int i = tid; i < kF * en; i += kT) {
@@ -494,22 +483,20 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
             recE = nextE;
             rowE = nextRow;
         }
-        if constexpr (kFlood) {  // eq. equ_s2e6, then the decisions (eq. equ_s2e7)
+        if constexpr (kFlood) {  // eq. equ_s2e6 (its sign is the decision, eq. equ_s2e7)
             for (int f = 0; f < kF; ++f) {
                 if (!((live >> f) & 1u)) continue;
                 const int64_t fr = sCur[f];
                 float *Lam = Lp(f), *A = Ap(f);
-                uint8_t *xb = Xp(f);
                 for (int v = tid; v < g.N; v += kT) {
-                    const float lm = flood_posterior(llr[fr + v], us, A[v]);
-                    Lam[v] = lm;
-                    xb[v] = lm < 0.0f;
+                    Lam[v] = flood_posterior(llr[fr + v], us, A[v]);
                     A[v] = 0.0f;
                 }
             }
         }
     };
-    run_slots<kF, kT>(g, base, it, bits, iters, q, max_iter, p, load, sweep);
+    run_slots<kF, kT>(g, bits, iters, q, max_iter, p, load, sweep,
+                      [&](int f, int v) { return (uint32_t)(Lp(f)[v] < 0.0f); });
 }
 
 template <bool kFlood, bool kMin, int kF, int kT>
@@ -609,9 +596,11 @@ int64_t align16(int64_t x) { return (x + 15) / 16 * 16; }
 LdsItem lds_item(int algo, const SparseDev &g) {
     LdsItem it{};
     if (algo < kCBP || algo > kFBP) return it;  // bytes = 0: not available
-    const bool flood = algo == kFBP || algo == kFBPNMS;
-    const int64_t q = align16(4 * (int64_t)g.N), r = align16(4 * (int64_t)g.E), om = align16(8 * (int64_t)g.M),
-                  acc = flood ? q : 0, xb = align16(g.N);
+    const bool flood = algo == kFBP || algo == kFBPNMS, bp = algo != kCBP && algo != kCBPNMS;
+    if (bp && g.M > 0 && g.lvl_maxrows < 1) return it;
+    const int64_t q = align16(4 * (int64_t)g.N), r = align16(4 * (int64_t)g.E),
+                  om = align16(8 * (int64_t)(bp ? g.lvl_maxrows : g.M)), acc = flood ? q : 0,
+                  xb = bp ? 0 : align16(g.N);
     const int64_t total = q + r + om + acc + xb;
     if (total >= ((int64_t)1 << 31)) return it;
     it.r = (int)q;

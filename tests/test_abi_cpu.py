@@ -68,8 +68,17 @@ def test_code_handles(L):
     c3 = cbp.Code.from_workload(get_code("qc26112"))
     assert not c3.has_kernel("qc_reg") and c3.has_kernel("qc_stream")
     assert not c1.has_kernel("qc_stream")
-    # frame state in LDS: 4N + 4E + 8M + N bytes (rounded) within 160 KiB
+    # frame state in LDS within 160 KiB: CBP 4N + 4E + 8M + N bytes (rounded); the BP
+    # decoders 4N + 4E + 8 x (rows of the largest level), flooding 4N more
     assert c.has_kernel("sparse_lds") and c1.has_kernel("sparse_lds") and not c3.has_kernel("sparse_lds")
+    for algo in ("cbp", "lbp", "fbp", "lbp_nms", "fbp_nms"):
+        with pytest.raises(cbp.CbpError) as e:
+            cbp.workspace_size(c3, algo, 1, kernel="sparse_lds")
+        assert e.value.status == cbp.CBP_EUNSUPPORTED
+    # n = 8192 PEG: flooding BP (4N + 4E + 8 x 258 + 4N = 156,496 bytes) fits as well
+    peg = cbp.Code.from_workload(get_code("peg_irr_n8192"))
+    for algo in ("cbp", "lbp", "fbp"):
+        assert cbp.workspace_size(peg, algo, 1, kernel="sparse_lds") == 256
 
 
 @pytest.mark.parametrize("rp,ci,why", [

@@ -45,12 +45,9 @@ def test_equals_lane_kernel(name, ebn0, frames, max_iter, algo):
     code = get_code(name)
     c = cbp.Code.from_workload(code)
     assert c.has_kernel("sparse_lds")
-    if algo.startswith("fbp") and code.N == 8192:
-        # flooding BP keeps 4N more bytes per frame: 195 KB does not fit a CU's LDS
-        with pytest.raises(cbp.CbpError) as e:
-            cbp.workspace_size(c, algo, 1, kernel="sparse_lds")
-        assert e.value.status == cbp.CBP_EUNSUPPORTED
-        return
+    # every case fits, flooding BP at n = 8192 included (157 KB: the BP kernels keep one
+    # level's fold states and decide from the posterior's sign)
+    assert cbp.workspace_size(c, algo, 1, kernel="sparse_lds") > 0
     llr, _ = make_frames(code, ebn0, frames, key=(43,))
     t = torch.from_numpy(llr).cuda()
     say(f"[gpu] sparse_lds {name} {algo} {frames} frames")
