@@ -1,7 +1,8 @@
 // Any parity-check matrix (CSR) with each frame's whole state in LDS.
 //
-// A workgroup holds kF frames (Q [N], R [E], beliefs [M] by level position, decisions [N] of
-// each) in LDS and runs their sweeps together, level by level: the rows of
+// A workgroup holds kF frames in LDS (CBP: Q [N], R [E], the rows' beliefs
+// [M] by level position, decisions [N]; the BP layout is given with its
+// kernel below) and runs their sweeps together, level by level: the rows of
 // one level share no variable, so they commute in the paper's sequential row
 // order (Sec. IV-C) and are updated at once with exactly the sequential
 // result.  Within a level the work is split by edge, not by row, which gives
