@@ -180,11 +180,15 @@ __device__ __forceinline__ void cbp_lds_body(const SparseDev &g, const float *__
         const float q = Q[col];
         float rc = R[e];
         const float2 om = Op(f)[pr];
+        // the term of q that the latest check folded, still parked in that
+        // edge's slot (only this visit's commit replaces it, and q has not
+        // changed since): B2V needs no second evaluation of the check rule
+        const float tp = R[pe];
         float rn = 0.0f;
         // no latest check yet on a variable's first visit of the first sweep
         if (!(((s1 >> f) & 1u) && (fl & kFirstVisit))) {
-            rn = b2v<kMin>(om.x, om.y, q, p);  // B2V, eq. equ_s4e18
-            R[pe] = rn;                         // commit R(c_j -> v) first
+            rn = b2v_term<kMin>(om.x, om.y, tp, p);  // B2V, eq. equ_s4e18
+            R[pe] = rn;                               // commit R(c_j -> v) first
             if (pe == e) rc = rn;
         }
         const float lam = q + rn;  // eq. equ_s4e20
@@ -293,11 +297,13 @@ __global__ __launch_bounds__(kT) void cbp_lds_kernel(SparseDev g, const float *_
 // per level:
 //   phase B (thread = row of a frame): the row's V2C messages Q = Lambda - R
 //            of the previous sweep folded in ascending column order into its
-//            state;
-//   phase C (thread = edge of a frame): Q again (nothing it reads has
-//            changed), the C2V message from the row's state, then R and the
-//            variable's C2V sum (rows containing a variable meet it in index
-//            order, level by level, as row by row);
+//            state, each one's check-rule term (with its sign) left in its
+//            edge's R slot in place of the old C2V message;
+//   phase C (thread = edge of a frame): the C2V message from the row's state
+//            and that term (Lambda is fixed for the sweep, so this is the
+//            term the lane kernel recomputes), then R and the variable's C2V
+//            sum (rows containing a variable meet it in index order, level by
+//            level, as row by row);
 // and the sweep ends with the posterior L + sum and the decisions of every
 // variable.
 template <bool kFlood, bool kMin, int kF, int kT>
@@ -318,7 +324,8 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
     // fold of row rr (position j in its level) of slot f (V2C, eq. equ_s2e3 /
     // equ_s2e10)
     auto row_fold = [&](int f, const int4 &rr, int j) {
-        const float *Lam = Lp(f), *R = Rp(f);
+        const float *Lam = Lp(f);
+        float *R = Rp(f);
         float m1 = kMin ? __builtin_inff() : 0.0f, m2 = kMin ? __builtin_inff() : 0.0f;
         bool par = false;
         for (int c0 = rr.y; c0 < rr.z; c0 += kLdsChunk) {
@@ -336,36 +343,37 @@ __device__ __forceinline__ void bp_lds_body(const SparseDev &g, const float *__r
             for (int c = 0; c < kLdsChunk; ++c) {
                 if (c0 + c < rr.z) {
                     const float q = lv[c] - rv[c];
+                    float t;
                     if constexpr (kMin) {
-                        const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, aq));
-                        m1 = __builtin_fminf(m1, aq);
+                        t = __builtin_fminf(__builtin_fabsf(q), p.lmax);
+                        m2 = __builtin_fminf(m2, __builtin_fmaxf(m1, t));
+                        m1 = __builtin_fminf(m1, t);
                     } else {
-                        fold(m1, m2, phi2_clamped(q, p.a, p.lmax));
+                        t = phi2_clamped(q, p.a, p.lmax);
+                        fold(m1, m2, t);
                     }
                     par ^= (q < 0.0f);
+                    // the term, with q's sign, replaces the old C2V message (read
+                    // just now; Lambda stays fixed for the sweep, so phase C needs
+                    // only this term of q)
+                    R[c0 + c] = with_sign(t, q < 0.0f);
                 }
             }
         }
         Sp(f)[j] = make_float2(with_sign(m1, par), m2);
     };
     // flooding: C2V of the edge of record rec of slot f, its row at position
-    // row of the level (eq. equ_s2e4 or the min-sum rule), then R and the C2V
-    // sum
+    // row of the level (eq. equ_s2e4 or the min-sum rule) from the term of its
+    // V2C message that the row fold left in R, then R and the C2V sum
     auto edge = [&](int f, const int4 &rec, int row) {
         const int col = rec.x, e = rec.w & 0x3fffffff;
         float *R = Rp(f), *A = Ap(f);
         const float2 st = Sp(f)[row];
         const float m1 = abs_bits(st.x), m2 = st.y;
         const bool par = sign_bit(st.x);
-        const float q = Lp(f)[col] - R[e];
-        float rn;
-        if constexpr (kMin) {
-            const float aq = __builtin_fminf(__builtin_fabsf(q), p.lmax);
-            rn = with_sign(p.alpha * ((aq == m1) ? m2 : m1), par ^ (q < 0.0f));
-        } else {
-            rn = with_sign(phi2(excl_sum(m1, m2, phi2_clamped(q, p.a, p.lmax))), par ^ (q < 0.0f));
-        }
+        const float t = R[e];
+        const float rn = kMin ? with_sign(p.alpha * ((abs_bits(t) == m1) ? m2 : m1), par ^ sign_bit(t))
+                              : with_sign(phi2(excl_sum(m1, m2, abs_bits(t))), par ^ sign_bit(t));
         R[e] = rn;
         A[col] = A[col] + rn;
     };

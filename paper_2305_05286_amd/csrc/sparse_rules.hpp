@@ -21,6 +21,19 @@ __device__ float b2v(float om, float os, float q, const Params &p) {
     }
 }
 
+// The same B2V from the excluded term itself: t is the check-rule term of q
+// as the check folded it, with q's sign (|t| = phi2_clamped(q) or
+// min(|q|, lmax), sign bit = q < 0), so the result is b2v's bit for bit.
+template <bool kMin>
+__device__ float b2v_term(float om, float os, float t, const Params &p) {
+    if constexpr (!kMin) {
+        return with_sign(phi2(excl_sum(abs_bits(om), os, abs_bits(t))), sign_bit(om) ^ sign_bit(t));
+    } else {
+        const float m1 = abs_bits(om);
+        return with_sign(p.alpha * ((abs_bits(t) == m1) ? os : m1), sign_bit(om) ^ sign_bit(t));
+    }
+}
+
 // Flooding posterior at the end of a sweep: channel LLR (scaled to the
 // rule's units) plus the sum of the sweep's C2V messages (eq. equ_s2e6).
 __device__ __forceinline__ float flood_posterior(float l, float us, float acc) { return l * us + acc; }
