@@ -430,7 +430,8 @@ def main() -> int:
         PB, PMI, PSNR = 131072, 200, 2.0
         peg = {"frames": PB, "ebn0_db": PSNR, "max_iter": PMI, "kernel": "auto (sparse_lds where a frame fits)",
                "note": "codewords from a pool of 1024 seeded random codewords, fresh GPU noise; "
-                       "ms_lane: the same decode on the one-frame-per-lane kernel"}
+                       "ms_lane: the same decode on the one-frame-per-lane kernel; ms_per_sweep: "
+                       "(time of 15 fixed sweeps - time of 5) / 10 on the same frames"}
         for name in ("peg_reg36_n2048", "peg_irr_n8192"):
             pc = get_code(name)
             ph = cbp.Code.from_workload(pc)
@@ -465,8 +466,26 @@ def main() -> int:
                                    "fer": fe / PB, "frame_errors": fe,
                                    "mean_iters": round(its.mean().item(), 3), "max_iters": int(its.max().item()),
                                    "gbps": round(PB * pc.K / t / 1e9, 3)}
+                # cost of one sweep on the same frames: every frame runs 5, then 15 sweeps
+                # (fixed sweeps), the difference over 10
+                fixed = {}
+                pws = torch.empty(cbp.workspace_size(ph, algo, PB, stop_rule=2), dtype=torch.uint8, device=dev)
+                for n_sw in (5, 15):
+                    cbp.decode(ph, llr_p, n_sw, algo, out=(pbits, pit), workspace=pws, stop_rule=2)
+                    ts_ = []
+                    for _ in range(3):
+                        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        s_.record(stream)
+                        cbp.decode(ph, llr_p, n_sw, algo, out=(pbits, pit), workspace=pws, stop_rule=2)
+                        e_.record(stream)
+                        torch.cuda.synchronize()
+                        ts_.append(s_.elapsed_time(e_))
+                    fixed[n_sw] = float(np.median(ts_))
+                del pws
+                peg[name][algo]["ms_per_sweep"] = round((fixed[15] - fixed[5]) / 10, 3)
                 log(f"[bench] {name} {algo}: {t * 1e3:.0f} ms ({peg[name][algo]['kernel']}; lane kernel "
-                    f"{times['sparse'] * 1e3:.0f} ms), FER {fe / PB:.2e}, sweeps {its.mean().item():.2f}")
+                    f"{times['sparse'] * 1e3:.0f} ms), FER {fe / PB:.2e}, sweeps {its.mean().item():.2f}, "
+                    f"{peg[name][algo]['ms_per_sweep']:.2f} ms per sweep")
             del pool, cw_p, llr_p, pbits, pit
             torch.cuda.empty_cache()
 
