@@ -182,6 +182,35 @@ def test_mixed_lds_part_subsets_and_small_batches(subset):
     assert iters.numel() == 0
 
 
+def test_mixed_two_streams_share_the_plan():
+    """Two decodes with one plan on two streams at once, the LDS-staged part on: both use the
+    plan's side stream and fork / join events, taking turns on them, and each gives the result
+    of a decode on its own."""
+    codes = list(mixed_family())
+    mix = cbp.Mix([cbp.Code.from_workload(c) for c in codes])
+    mix.schedule = (mix.schedule[0], 2, 2)
+    ba, bb = make_mixed_batch(codes, 2000, key=(31, 8)), make_mixed_batch(codes, 1500, key=(31, 9))
+    da, db = to_dev(ba), to_dev(bb)
+    say("[gpu] mixed: one plan on two streams")
+    ref_a = mix.decode(*da, 25, "cbp")
+    ref_b = mix.decode(*db, 25, "cbp")
+    out_a = (torch.empty_like(ref_a[0]), torch.empty_like(ref_a[1]))
+    out_b = (torch.empty_like(ref_b[0]), torch.empty_like(ref_b[1]))
+    wa = torch.empty(mix.workspace_size(2000, "cbp"), dtype=torch.uint8, device="cuda")
+    wb = torch.empty(mix.workspace_size(1500, "cbp"), dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        for o in (out_a, out_b):
+            o[0].fill_(7)
+            o[1].fill_(-7)
+        torch.cuda.synchronize()
+        mix.decode(*da, 25, "cbp", workspace=wa, out=out_a, stream=s1)
+        mix.decode(*db, 25, "cbp", workspace=wb, out=out_b, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(out_a[0], ref_a[0]) and torch.equal(out_a[1], ref_a[1]), rep
+        assert torch.equal(out_b[0], ref_b[0]) and torch.equal(out_b[1], ref_b[1]), rep
+
+
 def test_mixed_malformed_frames_are_skipped():
     codes = small_family()[:4]
     b = make_mixed_batch(codes, 200, key=(31, 3))
